@@ -1,0 +1,533 @@
+"""Pins of the FP64 oracle against facts fixed by the paper's equations and by mathematics.
+
+None of these compare the oracle with itself: each checks a closed form, an
+invariant, a brute-force evaluation or a special case that reduces to a
+textbook result.
+"""
+import math
+
+import numpy as np
+import pytest
+from scipy.optimize import brentq
+
+from oracle import pm
+from synth import lattice_positions, plane_wave_particles
+
+RNG = np.random.default_rng(12345)
+
+
+def _rand_particles(n_p, seed=0, umax=0.3):
+    r = np.random.default_rng(seed)
+    return r.random((n_p, 3)), (r.random((n_p, 3)) - 0.5) * 2 * umax
+
+
+# --------------------------------------------------------------------------
+# P1-P3: deposit
+# --------------------------------------------------------------------------
+
+def test_p1_deposit_partition_of_unity():
+    pos, u = _rand_particles(300, seed=1)
+    a = 0.07
+    dep = pm.deposit(pos, u, a, 8)
+    q = pm.deposit_quantities(u, a)
+    for c in range(10):
+        tot = dep[c].sum()
+        ref = q[c].sum()
+        assert abs(tot - ref) <= 1e-13 * max(1.0, np.abs(q[c]).sum()), c
+    # e = sqrt(a^2 + u^2) written out independently
+    e = np.sqrt(a * a + (u ** 2).sum(1))
+    assert np.allclose(dep[0].sum(), e.sum(), rtol=1e-14, atol=0)
+    assert np.allclose(dep[4].sum(), (u[:, 0] ** 2 / e).sum(), rtol=1e-13, atol=0)
+
+
+def test_p2_uniform_lattice_and_vertex_particle():
+    n = 8
+    pos = lattice_positions(n)
+    a = 0.25
+    dep = pm.deposit(pos, np.zeros_like(pos), a, n)
+    assert np.all(dep[0] == a)  # exactly uniform
+    assert np.all(dep[1:] == 0)
+    # one particle exactly on vertex (3, 5, 6)
+    p = np.array([[3 / n, 5 / n, 6 / n]])
+    d = pm.deposit(p, np.zeros_like(p), 1.0, n)[0]
+    assert d[6, 5, 3] == 1.0 and d.sum() == 1.0
+
+
+def test_p3_bruteforce_loop():
+    n = 6
+    pos, u = _rand_particles(40, seed=3)
+    a = 0.3
+    dep = pm.deposit(pos, u, a, n)
+    ref = np.zeros((10, n, n, n))
+    for p in range(pos.shape[0]):
+        e = math.sqrt(a * a + sum(u[p, d] ** 2 for d in range(3)))
+        vals = [e, u[p, 0], u[p, 1], u[p, 2]] + [u[p, i] * u[p, j] / e for i, j in pm.SYM]
+        s = [pos[p, d] * n for d in range(3)]
+        b = [int(math.floor(s[d])) for d in range(3)]
+        f = [s[d] - b[d] for d in range(3)]
+        for cz in range(2):
+            for cy in range(2):
+                for cx in range(2):
+                    w = (f[0] if cx else 1 - f[0]) * (f[1] if cy else 1 - f[1]) * (f[2] if cz else 1 - f[2])
+                    for c in range(10):
+                        ref[c, (b[2] + cz) % n, (b[1] + cy) % n, (b[0] + cx) % n] += w * vals[c]
+    assert np.max(np.abs(dep - ref)) <= 1e-15 * np.max(np.abs(ref)) * 10
+
+
+# --------------------------------------------------------------------------
+# P4: FFT against a brute-force DFT
+# --------------------------------------------------------------------------
+
+def test_p4_fft_bruteforce_parseval_roundtrip():
+    n = 8
+    f = RNG.standard_normal((n, n, n))
+    fk = pm.fft3(f)
+    idx = np.arange(n)
+    # brute force: sum over all n^3 points for every (kz, ky, kx) of the half spectrum
+    zz, yy, xx = np.meshgrid(idx, idx, idx, indexing="ij")
+    pts = np.stack([zz.ravel(), yy.ravel(), xx.ravel()], 1)
+    kz, ky, kx = np.meshgrid(idx, idx, np.arange(n // 2 + 1), indexing="ij")
+    ks = np.stack([kz.ravel(), ky.ravel(), kx.ravel()], 1)
+    phase = np.exp(-2j * np.pi * (ks @ pts.T) / n)
+    ref = (phase @ f.ravel()).reshape(n, n, n // 2 + 1)
+    assert np.max(np.abs(fk - ref)) < 1e-12 * np.max(np.abs(ref))
+    # round trip and Parseval (full spectrum energy from the half spectrum)
+    assert np.max(np.abs(pm.ifft3(fk, n) - f)) < 1e-14
+    w = np.full(n // 2 + 1, 2.0)
+    w[0] = w[-1] = 1.0
+    e_k = (np.abs(fk) ** 2 * w).sum() / n ** 3
+    assert abs(e_k - (f ** 2).sum()) < 1e-12 * (f ** 2).sum()
+
+
+# --------------------------------------------------------------------------
+# helpers to drive the solve with mesh sources
+# --------------------------------------------------------------------------
+
+def _sim_with_deposit(n, physics, dep, tau=30.0, box=320.0, n_p=None):
+    n_p = n ** 3 if n_p is None else n_p
+    pos = np.zeros((n_p, 3))
+    s = pm.OracleSim(n=n, box_mpch=box, physics=physics, pos=pos, u=np.zeros_like(pos), tau=tau)
+    s.dep = dep
+    return s
+
+
+def _plane(n, m):
+    g = np.arange(n) / n
+    z, y, x = np.meshgrid(g, g, g, indexing="ij")
+    return np.cos(2 * np.pi * (m[0] * x + m[1] * y + m[2] * z))
+
+
+def _kt(n, m):
+    return np.array([2 * n * math.sin(math.pi * mi / n) for mi in m])
+
+
+# --------------------------------------------------------------------------
+# P5: phi for a plane-wave density
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("inv_dtau", [0.0, 1.0 / 0.7])
+def test_p5_phi_plane_wave_closed_form(inv_dtau):
+    n, m = 16, (1, 2, 3)
+    s = _sim_with_deposit(n, pm.SCALAR, None)
+    a, hc = s.bg.a(s.tau), s.bg.hconf(s.tau)
+    eb = s.bg.ebar(a)
+    A = 1e-3
+    kap = s.bg.kappa(n, n ** 3) / a ** 2
+    E = eb * (1 + A * _plane(n, m))
+    dep = np.zeros((10, n, n, n))
+    dep[0] = E / kap
+    s.dep = dep
+    z = np.zeros((n, n, n))
+    phi, chi, _, _ = s._solve_once(z, z, 0.0, inv_dtau)
+    kt2 = float((_kt(n, m) ** 2).sum())
+    ref = eb * A * _plane(n, m) / (-kt2 - 3 * hc * inv_dtau - 6 * hc * hc - eb)
+    # round-off scale is set by the source (E ~ ebar), not by its small modulation A
+    assert np.max(np.abs(phi - ref)) < 1e-12 * np.max(np.abs(ref)) / A
+    assert np.max(np.abs(chi)) == 0.0
+
+
+def test_p5_newtonian_laplacian_real_space():
+    n = 16
+    s = _sim_with_deposit(n, pm.NEWTONIAN, None)
+    a = s.bg.a(s.tau)
+    rho = 1.0 + 0.3 * RNG.standard_normal((n, n, n))
+    rho *= n ** 3 / rho.sum()  # mean one particle per cell
+    s.dep = (rho * a)[None]
+    s.solve(0.0)
+    E = s.bg.kappa(n, n ** 3) / a * rho  # kappa a^-2 n00 with n00 = a rho
+    src = E - s.bg.ebar(a)
+    lap = pm.laplacian7(s.phi, n)
+    assert np.max(np.abs(lap - src)) < 1e-11 * np.max(np.abs(src))
+
+
+# --------------------------------------------------------------------------
+# P6: chi
+# --------------------------------------------------------------------------
+
+def _solve_with_K(n, m, C, physics=pm.SCALAR):
+    s = _sim_with_deposit(n, physics, None)
+    a = s.bg.a(s.tau)
+    kap = s.bg.kappa(n, n ** 3) / a ** 2
+    dep = np.zeros((10, n, n, n))
+    dep[0] = s.bg.ebar(a) / kap
+    cosw = _plane(n, m)
+    for idx, (i, j) in enumerate(pm.SYM):
+        dep[4 + idx] = C[i, j] * cosw / kap
+    s.dep = dep
+    z = np.zeros((n, n, n))
+    return s, s._solve_once(z, z, 0.0, 0.0)
+
+
+def test_p6_chi_axis_wave_real_space_laplacian():
+    n, m = 16, (3, 0, 0)
+    C = np.array([[1.0, 0.2, -0.3], [0.2, -0.5, 0.1], [-0.3, 0.1, 0.7]]) * 1e-6
+    _, (phi, chi, _, _) = _solve_with_K(n, m, C)
+    sig = 4.0 * C * 1.0  # lagged phi = 0: Sigma = 4 K
+    # k along x: chi satisfies (4/3) d_x^2 chi = Sigma_xx - tr(Sigma)/3 with the 3-point second difference
+    lap = pm.laplacian7(chi, n)
+    ref = 0.75 * (sig[0, 0] - np.trace(sig) / 3.0) * _plane(n, m)
+    assert np.max(np.abs(lap - ref)) < 1e-10 * np.max(np.abs(ref))
+
+
+def test_p6_chi_oblique_closed_form_and_isotropic_zero():
+    n, m = 16, (1, 2, 2)
+    C = np.array([[1.0, 0.4, -0.3], [0.4, -0.5, 0.25], [-0.3, 0.25, 0.2]]) * 1e-6
+    _, (phi, chi, _, _) = _solve_with_K(n, m, C)
+    kt = _kt(n, m)
+    k2 = kt @ kt
+    sig = 4.0 * C
+    ref_amp = -(3.0 / (4.0 * k2 * k2)) * (kt @ sig @ kt - k2 * np.trace(sig) / 3.0)
+    ref = ref_amp * _plane(n, m)
+    assert np.max(np.abs(chi - ref)) < 1e-11 * np.max(np.abs(ref))
+    _, (_, chi_iso, _, _) = _solve_with_K(n, m, np.eye(3) * 1e-6)
+    assert np.max(np.abs(chi_iso)) < 1e-12 * np.max(np.abs(ref))
+
+
+# --------------------------------------------------------------------------
+# P7: B
+# --------------------------------------------------------------------------
+
+def _solve_with_J(n, m, V):
+    s = _sim_with_deposit(n, pm.FULL, None)
+    a = s.bg.a(s.tau)
+    kap = s.bg.kappa(n, n ** 3) / a ** 2
+    dep = np.zeros((10, n, n, n))
+    dep[0] = s.bg.ebar(a) / kap
+    for i in range(3):
+        dep[1 + i] = V[i] * _plane(n, m) / kap
+    s.dep = dep
+    z = np.zeros((n, n, n))
+    return s._solve_once(z, z, 0.0, 0.0)
+
+
+def test_p7_b_closed_form_transverse_and_longitudinal():
+    n, m = 16, (2, -1, 1)
+    V = np.array([1.0, -2.0, 0.5]) * 1e-7
+    _, _, B, _ = _solve_with_J(n, m, V)
+    kt = _kt(n, m)
+    k2 = kt @ kt
+    ref = 4.0 / k2 * (V - kt * (kt @ V) / k2)
+    for i in range(3):
+        assert np.max(np.abs(B[i] - ref[i] * _plane(n, m))) < 1e-11 * np.max(np.abs(ref))
+    # a longitudinal current sources no frame dragging
+    _, _, B0, _ = _solve_with_J(n, m, kt / np.linalg.norm(kt) * 1e-7)
+    assert max(np.max(np.abs(b)) for b in B0) < 1e-12 * np.max(np.abs(ref))
+    # real-space check along an axis: -(1/4) lap B_y = S_y for k along x, V along y
+    m2 = (2, 0, 0)
+    _, _, B2, _ = _solve_with_J(n, m2, np.array([0.0, 1e-7, 0.0]))
+    assert np.max(np.abs(-0.25 * pm.laplacian7(B2[1], n) - 1e-7 * _plane(n, m2))) < 1e-10 * 1e-7
+
+
+# --------------------------------------------------------------------------
+# P8-P9: tensor sector and projectors
+# --------------------------------------------------------------------------
+
+def _rand_sym_spectra(n, seed):
+    r = np.random.default_rng(seed)
+    return [pm.fft3(r.standard_normal((n, n, n))) for _ in range(6)]
+
+
+def test_p8_tt_projection_is_transverse_traceless_idempotent():
+    n = 8
+    kt = pm.lattice_symbols(n)
+    sig = _rand_sym_spectra(n, 5)
+    tt = pm.tt_project(sig, kt)
+    tt2 = pm.tt_project(tt, kt)
+    scale = max(np.max(np.abs(t)) for t in tt)
+    for a_, b_ in zip(tt, tt2):
+        assert np.max(np.abs(a_ - b_)) < 1e-12 * scale
+    trace = tt[0] + tt[3] + tt[5]
+    assert np.max(np.abs(trace)) < 1e-12 * scale
+    for i in range(3):
+        kh = sum(kt[j] * tt[pm.SYM_INDEX[(i, j)]] for j in range(3))
+        assert np.max(np.abs(kh)) < 1e-9 * scale
+
+
+def test_p8_crank_nicolson_energy_and_static_fixed_point():
+    k2 = np.array([4.0, 100.0, 3e4])
+    h = np.array([1.0, -0.5, 0.2]) + 0j
+    pi = np.array([0.3, 2.0, -7.0]) + 0j
+    e0 = k2 * np.abs(h) ** 2 + np.abs(pi) ** 2
+    for _ in range(200):
+        h, pi = pm.crank_nicolson_tensor(h, pi, 0.0, k2, 0.05, 0.0)
+    e1 = k2 * np.abs(h) ** 2 + np.abs(pi) ** 2
+    assert np.max(np.abs(e1 - e0) / e0) < 1e-12
+    S = np.array([2.0, -1.0, 5.0]) + 0j
+    hs, ps = pm.crank_nicolson_tensor(S / k2, 0 * S, S, k2, 0.3, 1.7)
+    assert np.max(np.abs(hs - S / k2)) < 1e-15 and np.max(np.abs(ps)) < 1e-13
+
+
+def test_p9_svt_decomposition_completes_identity():
+    """Scalar (chi), vector and tensor parts add back to the trace-free source."""
+    n = 8
+    kt = pm.lattice_symbols(n)
+    k2 = kt[0] ** 2 + kt[1] ** 2 + kt[2] ** 2
+    sig = _rand_sym_spectra(n, 7)
+    tr = (sig[0] + sig[3] + sig[5]) / 3.0
+    tf = [s - (tr if i == j else 0.0) for s, (i, j) in zip(sig, pm.SYM)]
+    chi = pm.chi_from_sigma(sig, kt, n)
+    # the scalar part of Eq. 5 is 2 (-kt_i kt_j + delta_ij kt^2 / 3) chi
+    scal = [2.0 * (-kt[i] * kt[j] + (k2 / 3.0 if i == j else 0.0)) * chi for i, j in pm.SYM]
+    tt = pm.tt_project(sig, kt)
+    vec = [t - s_ - h_ for t, s_, h_ in zip(tf, scal, tt)]
+    mask = k2 > 0
+    scale = max(np.max(np.abs(t[mask])) for t in tf)
+    # the remainder is a pure vector mode: k_i k_j V_ij = 0, V_ii = 0 and Lambda^TT V = 0
+    kk = sum((1.0 if i == j else 2.0) * kt[i] * kt[j] * v for v, (i, j) in zip(vec, pm.SYM))
+    assert np.max(np.abs((kk / np.where(mask, k2, 1.0))[mask])) < 1e-10 * scale
+    assert np.max(np.abs((vec[0] + vec[3] + vec[5])[mask])) < 1e-10 * scale
+    assert max(np.max(np.abs(t[mask])) for t in pm.tt_project(vec, kt)) < 1e-10 * scale
+
+
+# --------------------------------------------------------------------------
+# P10: zero self-force and momentum conservation (Newtonian limit)
+# --------------------------------------------------------------------------
+
+def test_p10_zero_self_force_and_total_momentum():
+    n = 16
+    pos = np.array([[0.3141, 0.7182, 0.1618]])
+    s = pm.OracleSim(n=n, box_mpch=320.0, physics=pm.NEWTONIAN, pos=pos, u=np.zeros_like(pos), tau=30.0)
+    s.deposit()
+    s.solve(0.0)
+    g = s.gathered()[5:8, 0]
+    gscale = np.max(np.abs(pm.grad(s.phi, n)[0]))
+    assert np.max(np.abs(g)) < 1e-12 * gscale
+    pos, _ = _rand_particles(500, seed=11)
+    s = pm.OracleSim(n=n, box_mpch=320.0, physics=pm.NEWTONIAN, pos=pos, u=np.zeros_like(pos), tau=30.0)
+    s.deposit()
+    s.solve(0.0)
+    g = s.gathered()[5:8]
+    assert np.max(np.abs(g.sum(axis=1))) < 1e-11 * np.max(np.abs(g)) * pos.shape[0] ** 0.5
+
+
+# --------------------------------------------------------------------------
+# P11-P12: bulk flow, zero mode as exact roots of the constraint
+# --------------------------------------------------------------------------
+
+def test_p11_uniform_bulk_flow_drift():
+    n = 8
+    pos = lattice_positions(n)
+    s = pm.OracleSim(n=n, box_mpch=320.0, physics=pm.FULL, pos=pos, u=np.zeros_like(pos), tau=30.0)
+    a = s.bg.a(s.tau)
+    uvec = np.array([3.0, -4.0, 12.0]) / 13.0 * 10.0 * a  # |u| = 10 a: relativistic
+    s.u[:] = uvec
+    dtau = 0.4
+    s.deposit()
+    s.solve(0.0)
+    phibar = s.phi.mean()
+    for f in [s.phi - phibar, s.chi] + list(s.B):
+        assert np.max(np.abs(f)) < 1e-13 * max(1.0, abs(phibar))
+    s.update(dtau)
+    ah = s.bg.a(30.0 + 0.5 * dtau)
+    u2 = uvec @ uvec
+    eh = math.sqrt(ah * ah + u2)
+    vel = uvec / eh * (1 + (3 - u2 / eh ** 2) * phibar)
+    ref = pm.wrap_positions(pos + dtau * vel)
+    d = s.pos - ref
+    d -= np.round(d)
+    # round-off of the (exactly zero) gradients is the only perturbation
+    assert np.max(np.abs(d)) < 1e-13
+    assert np.allclose(s.u, uvec, rtol=1e-13, atol=0)
+
+
+def _uniform_sim(u_over_a):
+    n = 4
+    pos = lattice_positions(n)
+    s = pm.OracleSim(n=n, box_mpch=320.0, physics=pm.SCALAR, pos=pos, u=np.zeros_like(pos), tau=30.0)
+    a = s.bg.a(s.tau)
+    s.u[:, 0] = u_over_a * a
+    s.deposit()
+    return s
+
+
+def test_p12_zero_mode_quasistatic_root():
+    """Iterating the lagged solve to its fixed point solves (3/2) H^2 exp(-4 phi) = E exp(phi) exactly."""
+    s = _uniform_sim(0.3)
+    a = s.bg.a(s.tau)
+    E = s.bg.kappa(4, 64) / a ** 2 * s.dep[0].mean()
+    hc = s.bg.hconf(s.tau)
+    exact = math.log(1.5 * hc * hc / E) / 5.0
+    z = np.zeros((4, 4, 4))
+    phi, chi = z, z
+    for _ in range(60):
+        phi, chi, _, _ = s._solve_once(phi, chi, 0.0, 0.0)
+    assert abs(phi.mean() - exact) < 1e-13 * abs(exact)
+    assert np.max(np.abs(phi - phi.mean())) < 1e-15
+
+
+def test_p12_zero_mode_time_derivative_root():
+    """With an implicit time derivative, the fixed point solves (3/2)(H - phidot)^2 exp(-4 phi) = E exp(phi)."""
+    s = _uniform_sim(0.2)
+    a = s.bg.a(s.tau)
+    E = s.bg.kappa(4, 64) / a ** 2 * s.dep[0].mean()
+    hc = s.bg.hconf(s.tau)
+    phi_prev, dt = -0.0021, 0.9
+
+    def F(p):
+        pd = (p - phi_prev) / dt
+        return 1.5 * (hc - pd) ** 2 * math.exp(-4 * p) - E * math.exp(p)
+
+    exact = brentq(F, -0.05, 0.05, xtol=1e-16)
+    z = np.zeros((4, 4, 4))
+    phi = z + phi_prev
+    for _ in range(80):
+        pd = (phi - phi_prev) / dt
+        # the implicit part of the operator uses phi_prev; R takes the current iterate and its derivative
+        E_, J, K, gphi, gchi = s._sources(phi, z, pd)
+        eb = s.bg.ebar(a)
+        R = pm.hamiltonian_remainder(E_, eb, hc, phi, z, pd, gphi)
+        rhs = (E_ - eb) - 3 * hc / dt * phi_prev + R
+        phi = rhs / (-3 * hc / dt - 6 * hc * hc - eb)
+    assert abs(phi.mean() - exact) < 1e-12 * abs(exact)
+
+
+def test_p12_fixed_point_satisfies_full_constraint_pointwise():
+    """A spatially varying fixed point satisfies Eq. 4 / exp(2 phi) in real space (7-point Laplacian)."""
+    n = 8
+    r = np.random.default_rng(21)
+    pos = lattice_positions(n) + 0.3 / n * (r.random((n ** 3, 3)) - 0.5)
+    u = 0.05 * (r.random((n ** 3, 3)) - 0.5)
+    s = pm.OracleSim(n=n, box_mpch=4000.0, physics=pm.SCALAR, pos=pos, u=u, tau=3.0)
+    s.deposit()
+    a, hc = s.bg.a(s.tau), s.bg.hconf(s.tau)
+    eb = s.bg.ebar(a)
+    z = np.zeros((n, n, n))
+    phi, chi = z, z
+    for _ in range(60):
+        phi, chi, _, _ = s._solve_once(phi, chi, 0.0, 0.0)
+    E = s.bg.kappa(n, n ** 3) / a ** 2 * s.dep[0]
+    g = pm.grad(phi, n)
+    F = (pm.laplacian7(phi, n) - 0.5 * (g[0] ** 2 + g[1] ** 2 + g[2] ** 2)
+         + 1.5 * hc * hc * np.exp(-2 * (2 * phi - chi)) - E * np.exp(phi))
+    assert np.max(np.abs(F)) < 1e-10 * np.max(np.abs(E - eb))
+    assert np.max(np.abs(phi)) > 1e-4  # non-trivial field
+
+
+# --------------------------------------------------------------------------
+# P13-P14: linear plane wave; Zel'dovich growth
+# --------------------------------------------------------------------------
+
+def _project_wave(sim, q, k):
+    pos, u = sim.particles_by_id()
+    d = pos[:, 0] - q[:, 0]
+    d -= np.round(d)
+    s = np.sin(k * q[:, 0])
+    return (d * s).sum() / (s * s).sum(), (u[:, 0] * s).sum() / (s * s).sum()
+
+
+def _linear_recursion(bg, n, mode, U, P, tau, dtau, steps, physics):
+    dx = 1.0 / n
+    k = 2 * math.pi * mode
+    kt2 = (2 * n * math.sin(math.pi * mode / n)) ** 2
+    Phi_prev = None
+    dtp = 0.0
+    out = []
+    for it in range(steps):
+        a, hc = bg.a(tau), bg.hconf(tau)
+        eb = bg.ebar(a)
+        D = -(2 / dx) * math.sin(k * dx / 2) * U
+        if physics == pm.NEWTONIAN:
+            Phi = eb * D / (-kt2)
+        elif Phi_prev is None:
+            Phi = eb * D / (-kt2 - 6 * hc * hc - eb)
+        else:
+            Phi = (eb * D - 3 * hc / dtp * Phi_prev) / (-kt2 - 3 * hc / dtp - 6 * hc * hc - eb)
+        P = P + dtau * a * Phi * math.sin(k * dx) * math.cos(k * dx / 2) / dx
+        U = U + dtau * P / bg.a(tau + dtau / 2)
+        tau += dtau
+        Phi_prev, dtp = Phi, dtau
+        out.append((U, P))
+    return out
+
+
+@pytest.mark.parametrize("physics", [pm.NEWTONIAN, pm.SCALAR])
+def test_p13_linear_plane_wave_matches_scalar_recursion(physics):
+    n, mode = 32, 2
+    bg = pm.Background(320.0)
+    tau0 = bg.tau(0.02)
+    dtau = (bg.tau(0.05) - tau0) / 10
+    eps = 1e-6 / n
+    q = lattice_positions(n)
+    P0 = 0.3 * eps * bg.a(tau0) * bg.hconf(tau0)
+    pos, u = plane_wave_particles(n, n, eps, P0, mode=mode)
+    sim = pm.OracleSim(n=n, box_mpch=320.0, physics=physics, pos=pos, u=u, tau=tau0)
+    ref = _linear_recursion(bg, n, mode, eps, P0, tau0, dtau, 10, physics)
+    k = 2 * math.pi * mode
+    for it in range(10):
+        sim.step(dtau)
+        U, P = _project_wave(sim, q, k)
+        assert abs(U - ref[it][0]) < 1e-5 * abs(ref[it][0]), (it, U, ref[it][0])
+        assert abs(P - ref[it][1]) < 1e-5 * abs(ref[it][1]), (it, P, ref[it][1])
+
+
+def _growth_run(steps, n=32, mode=1):
+    bg = pm.Background(320.0)
+    tau0, tau1 = bg.tau(0.02), bg.tau(0.05)
+    dtau = (tau1 - tau0) / steps
+    gam = math.cos(math.pi * mode / n) ** 2
+    s = (-1 + math.sqrt(1 + 24 * gam)) / 2
+    U0 = 1e-6 / n
+    th = tau0 - dtau / 2
+    P0 = bg.a(th) * s * U0 * (th / tau0) ** s / th
+    # only the x-profile matters: use a thin lattice in y, z (n_p = n still, mesh n)
+    pos, u = plane_wave_particles(n, n, U0, P0, mode=mode)
+    sim = pm.OracleSim(n=n, box_mpch=320.0, physics=pm.NEWTONIAN, pos=pos, u=u, tau=tau0)
+    q = lattice_positions(n)
+    for _ in range(steps):
+        sim.step(dtau)
+    U, _ = _project_wave(sim, q, 2 * math.pi * mode)
+    return U / U0, (tau1 / tau0) ** s
+
+
+@pytest.mark.slow
+def test_p14_zeldovich_growth_second_order_convergence():
+    errs = []
+    for steps in (10, 20, 40):
+        g, exact = _growth_run(steps)
+        errs.append(abs(g - exact))
+    assert errs[0] < 5e-3 * 2.5
+    r1, r2 = errs[0] / errs[1], errs[1] / errs[2]
+    assert 3.3 < r1 < 4.7 and 3.3 < r2 < 4.7, errs
+
+
+# --------------------------------------------------------------------------
+# P15: translation by whole cells
+# --------------------------------------------------------------------------
+
+def test_p15_translation_by_whole_cells():
+    n = 16
+    r = np.random.default_rng(8)
+    pos = r.random((2000, 3))
+    u = 0.01 * (r.random((2000, 3)) - 0.5)
+    shift = np.array([3, 1, 5])
+    s1 = pm.OracleSim(n=n, box_mpch=320.0, physics=pm.FULL, pos=pos, u=u, tau=30.0)
+    s2 = pm.OracleSim(n=n, box_mpch=320.0, physics=pm.FULL, pos=pm.wrap_positions(pos + shift / n), u=u, tau=30.0)
+    for s in (s1, s2):
+        s.step(0.5)
+        s.step(0.5)
+    for f1, f2 in zip([s1.phi, s1.chi] + s1.B, [s2.phi, s2.chi] + s2.B):
+        rolled = np.roll(f1, shift=(shift[2], shift[1], shift[0]), axis=(0, 1, 2))
+        assert np.max(np.abs(rolled - f2)) < 1e-13 * np.max(np.abs(f1))
+    d = s2.pos - pm.wrap_positions(s1.pos + shift / n)
+    d -= np.round(d)
+    assert np.max(np.abs(d)) < 1e-13
