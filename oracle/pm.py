@@ -245,6 +245,23 @@ def momentum_source(J, phi, chi, phidot, gphi, gchi):
     return [ef * J[i] - phidot * (gphi[i] - gchi[i]) for i in range(3)]
 
 
+def nyquist_mask(n: int) -> np.ndarray:
+    """1 on the half spectrum except on the Nyquist planes (any |m_d| = n/2), where it is 0.
+
+    The scalar, vector and tensor projections contain factors such as
+    kt_x kt_y that are odd in one component.  On a Nyquist plane k_d and -k_d
+    are the same lattice mode, so such a factor has no well-defined sign there;
+    chi, B and h are therefore given no Nyquist-plane modes (phi, whose symbol
+    kt^2 is even, keeps them).
+    """
+    h = n // 2
+    m = np.arange(n)
+    ny = (m == h)
+    mx = (np.arange(n // 2 + 1) == h)
+    bad = ny[:, None, None] | ny[None, :, None] | mx[None, None, :]
+    return np.where(bad, 0.0, 1.0)
+
+
 def chi_from_sigma(sig_k, kt, n):
     """Scalar part of Eq. 5: chi(k) = -(3 / (4 kt^4)) (kt_i kt_j Sigma_ij - kt^2 Sigma_ii / 3); chi(0) = 0."""
     ktx, kty, ktz = kt
@@ -344,8 +361,9 @@ class OracleSim:
         self.B = [z.copy(), z.copy(), z.copy()]
         self.dtau_last = 0.0      # tau_{n-1} - tau_{n-2} (0: no time derivative yet)
         self.solved_once = False
-        self.h_k = None           # 6-component tensor spectrum
-        self.pi_k = None
+        hk0 = np.zeros((n, n, n // 2 + 1), dtype=np.complex128)
+        self.h_k = [hk0.copy() for _ in range(6)]   # 6-component tensor spectrum and its time derivative
+        self.pi_k = [hk0.copy() for _ in range(6)]
         self.last_sigma_k = None
 
     @property
@@ -385,12 +403,13 @@ class OracleSim:
         denom = -k2 - 3.0 * hc * inv_dtau - 6.0 * hc * hc - eb
         phi = ifft3(fft3(rhs) / denom, n)
         sig = traceless_source(K, phi1, chi1, gphi, gchi)
-        sig_k = [fft3(s) for s in sig]
+        nyq = nyquist_mask(n)
+        sig_k = [fft3(s) * nyq for s in sig]
         chi = ifft3(chi_from_sigma(sig_k, kt, n), n)
         B = None
         if self.physics == FULL:
             S = momentum_source(J, phi1, chi1, phidot, gphi, gchi)
-            B = [ifft3(bk, n) for bk in b_from_momentum([fft3(s) for s in S], kt)]
+            B = [ifft3(bk, n) for bk in b_from_momentum([fft3(s) * nyq for s in S], kt)]
         return phi, chi, B, sig_k
 
     def solve(self, dtau_prev: float):
@@ -422,7 +441,7 @@ class OracleSim:
             return
         kt = lattice_symbols(n)
         k2 = kt[0] ** 2 + kt[1] ** 2 + kt[2] ** 2
-        if dtau_prev <= 0.0 or not self.solved_once:
+        if dtau_prev <= 0.0:
             z = np.zeros((n, n, n))
             phi1, chi1 = z, z
             for _ in range(2):
@@ -457,8 +476,6 @@ class OracleSim:
 
     def h_real(self):
         """Real-space tensor perturbation h_ij (6 components), zero before the first evolution."""
-        if self.h_k is None:
-            return [np.zeros((self.n,) * 3) for _ in range(6)]
         return [ifft3(hk, self.n) for hk in self.h_k]
 
     # -- stage 3 ----------------------------------------------------------
