@@ -1,0 +1,215 @@
+#!/usr/bin/env python
+"""Particle updates per second of one relativistic PM step at 512^3 on one MI355X.
+
+Workload (clustered mixed-precision run): 512^3 particles on a 512^3 mesh in a
+2048 Mpc/h box; Zel'dovich initial conditions from a seeded Gaussian field with
+P(k) ~ k^-2 cut at the Nyquist wavenumber (rms displacement 0.2 cells at
+a = 0.02), evolved by the FP64 GPU path in 100 uniform-tau steps to a = 0.5 so
+that the particles are clustered.  From that snapshot the FP32 path (FP32
+fields, FFTs, deposit and momenta; FP64 positions and homogeneous mode) and the
+FP64 path are each timed over K steps of dtau = 0.01 tau with full
+scalar + vector + tensor physics.  One step = deposit + metric solve (15 FFTs
+and the Fourier-space solves) + gather/kick/drift + re-sort.
+
+Prints one JSON line.  `value` is the FP32 path's particle updates per second.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def log(msg: str) -> None:
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def stage_bytes(n: int, n_p: int, rs: int) -> dict:
+    """Algorithmic bytes of one launch of each stage's kernel (each unique input read and output written once)."""
+    F = n ** 3 * rs                      # one real field
+    S = n * n * (n // 2 + 1) * 2 * rs    # one half spectrum
+    P = 24 + 3 * rs                      # position + momentum of one particle
+    return {
+        "deposit": n_p * P + 10 * F,
+        "fft_x_fwd": 13 * F + 10 * S,
+        "fft_yz_fwd": 2 * 10 * S,        # per launch (two launches per stage)
+        "ksolve": 10 * S + 5 * S + 8 * S,
+        "fft_zy_inv": 2 * 5 * S,         # per launch (two launches per stage)
+        "fft_x_inv": 5 * S + 5 * F,
+        "kick_drift": n_p * (2 * P + 8) + 5 * F,
+        "sort": 16 * n ** 3 + n_p * (12 + 2 * (P + 4)),
+    }
+
+
+LAUNCHES = {"fft_yz_fwd": 2, "fft_zy_inv": 2}
+
+
+def run_gpu(args):
+    import numpy as np
+    import torch
+
+    from paper_2607_17929_amd import PMContext, tau_of_a
+    from synth import spectrum_power_law_m2, zeldovich_particles
+    from synth.ics import eds_a_of_tau
+
+    n = args.n
+    box = 2048.0 * n / 512
+    n_p = n ** 3
+    a0, a1 = 0.02, 0.5
+    tau0, tau1 = tau_of_a(box, a0), tau_of_a(box, a1)
+    dtau_ev = (tau1 - tau0) / args.evolve_steps
+    t0 = time.time()
+    pos, u = zeldovich_particles(n, 3, spectrum_power_law_m2, box, 0.2, 0.02, a0,
+                                 eds_a_of_tau(tau0 - 0.5 * dtau_ev, box))
+    log(f"initial conditions {n}^3 built in {time.time() - t0:.1f} s")
+
+    ctx64 = PMContext(n, n_p, box, physics="full", precision="fp64", timings=True)
+    ctx64.init_particles(pos, u, tau0)
+    del pos, u
+    t0 = time.time()
+    for i in range(args.evolve_steps):
+        ctx64.step(dtau_ev)
+        if (i + 1) % 20 == 0:
+            ctx64.sync()
+            log(f"fp64 evolution step {i + 1}/{args.evolve_steps}, a = {ctx64.time()[1]:.4f}")
+    ctx64.sync()
+    tau_s, a_s, _ = ctx64.time()
+    log(f"clustered snapshot at a = {a_s:.4f} after {time.time() - t0:.1f} s")
+    ctx64.timings()
+
+    def timed(ctx, label):
+        dtau = 0.01 * ctx.time()[0]
+        for _ in range(args.warmup):
+            ctx.step(dtau)
+        ctx.sync()
+        ctx.timings()  # reset the stage counters
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(ctx.stream)
+        for _ in range(args.steps):
+            ctx.step(dtau)
+        e1.record(ctx.stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / args.steps
+        st = ctx.timings()
+        ctx.sync()
+        log(f"{label}: {ms:.3f} ms/step, {n_p / ms * 1e3:.3e} particle updates/s")
+        return ms, st
+
+    # FP32 path from the same snapshot
+    pos_d, u_d = ctx64.get_particles(device=True)
+    ctx32 = PMContext(n, n_p, box, physics="full", precision="fp32", timings=True)
+    ctx32.init_particles(pos_d, u_d.to(torch.float32), tau_s)
+    del pos_d, u_d
+    torch.cuda.synchronize()
+    ms32, st32 = timed(ctx32, "fp32")
+    res = {"ms32": ms32, "st32": st32, "n": n, "n_p": n_p, "box": box, "a_snap": a_s,
+           "ws32": ctx32.ws_bytes, "ws64": ctx64.ws_bytes}
+    if not args.no_fp64:
+        ms64, st64 = timed(ctx64, "fp64")
+        res.update(ms64=ms64, st64=st64)
+    return res
+
+
+def cpu_baseline(n: int):
+    """The FP64 oracle timed on the host: one full-physics step (after the quasi-static first step) at n^3."""
+    import numpy as np
+
+    from oracle import pm as opm
+    from synth import spectrum_power_law_m2, zeldovich_particles
+    from synth.ics import eds_a_of_tau, eds_tau_of_a
+
+    box = 2048.0 * n / 512
+    tau0 = eds_tau_of_a(0.5, box)
+    dtau = 0.01 * tau0
+    pos, u = zeldovich_particles(n, 3, spectrum_power_law_m2, box, 0.2, 0.02, 0.5,
+                                 eds_a_of_tau(tau0 - 0.5 * dtau, box))
+    sim = opm.OracleSim(n=n, box_mpch=box, physics="full", pos=pos, u=u, tau=tau0)
+    sim.step(dtau)
+    t0 = time.time()
+    sim.step(dtau)
+    dt = time.time() - t0
+    cores = min(16, len(os.sched_getaffinity(0)))
+    return {"value": n ** 3 / dt, "unit": "particle updates/s", "cores": cores, "kind": "oracle",
+            "sample": (f"one FP64 oracle step (deposit + solve + kick/drift, full physics) of {n}^3 particles on a "
+                       f"{n}^3 mesh with the same cell size, spectrum and a = 0.5 Zel'dovich start, {dt:.1f} s; "
+                       f"numpy/scipy, FFTs on {cores} threads, deposit and gather single-threaded")}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--n", type=int, default=512)
+    ap.add_argument("--evolve-steps", type=int, default=100)
+    ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-n", type=int, default=128)
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(the PM step is measured on a single MI355X); use --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    r = run_gpu(args)
+    n, n_p = r["n"], r["n_p"]
+    st = r["st32"]
+    per_launch = {}
+    for k, (ms, calls) in st.items():
+        if calls:
+            per_launch[k] = ms / calls / LAUNCHES.get(k, 1)
+    totals = {k: ms for k, (ms, calls) in st.items()}
+    dom = max(totals, key=totals.get)
+    nbytes = stage_bytes(n, n_p, 4)
+    achieved = nbytes[dom] / (per_launch[dom] * 1e-3) / 1e9
+    roof = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+            "algorithmic_bytes_per_launch": nbytes[dom], "ms_per_launch": round(per_launch[dom], 4)}
+    stages = {k: {"ms_per_launch": round(per_launch.get(k, 0.0), 4),
+                  "GBs": round(nbytes[k] / (per_launch[k] * 1e-3) / 1e9, 1) if k in per_launch else None}
+              for k in st}
+    out = {
+        "metric": "particle updates/s per PM step at 512^3 (FP32 vs FP64); closure vs 2x mesh",
+        "value": n_p / r["ms32"] * 1e3,
+        "unit": "particle updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(r["ms32"], 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": (f"clustered mixed-precision run: {n}^3 particles on a {n}^3 mesh, box "
+                                f"{r['box']:.0f} Mpc/h, k^-2 Zel'dovich start at a=0.02 evolved by the FP64 GPU path "
+                                f"to a={r['a_snap']:.3f}, full scalar+vector+tensor physics, dtau = 0.01 tau"),
+                   "n_mesh": n, "n_particles": n_p, "physics": "full",
+                   "precision": "FP32 fields/FFT/deposit/momenta, FP64 positions and zero mode"},
+        "stages_fp32": stages,
+        "roofline": roof,
+        "workspace_GB": {"fp32": round(r["ws32"] / 1e9, 2), "fp64": round(r["ws64"] / 1e9, 2)},
+    }
+    if "ms64" in r:
+        out["fp64"] = {"value": n_p / r["ms64"] * 1e3, "ms_per_step": round(r["ms64"], 4),
+                       "stages": {k: round(ms / calls / LAUNCHES.get(k, 1), 4) for k, (ms, calls) in r["st64"].items()
+                                  if calls}}
+    if not args.no_cpu_baseline:
+        log(f"timing the CPU oracle at {args.cpu_n}^3")
+        out["cpu_baseline"] = cpu_baseline(args.cpu_n)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,185 @@
+/*
+ * pm.h -- C ABI of the MI355X (gfx950) relativistic particle-mesh step.
+ *
+ * The library implements one step of the particle-mesh (PM) method of
+ * Adamek & Christiansen, "gevolution 2.0" (arXiv:2607.17929):
+ *   (1) cloud-in-cell deposit of the particle stress-energy T00, T0i, Tij
+ *       (Sec. 3.1, Eqs. 11-13; the projection of Sec. 2.1),
+ *   (2) 3D real-to-complex FFTs and Fourier-space solves for phi (Hamiltonian
+ *       constraint, Eq. 4), chi = phi - psi and h_ij (trace-free space-space
+ *       equation, Eq. 5) and B_i (momentum constraint, Eq. 6),
+ *   (3) cloud-in-cell gather of the metric and the geodesic kick and drift
+ *       (Eqs. 8-10 expanded to first order in phi, psi and B, h neglected),
+ *       followed by a re-sort of the particles by mesh cell (Sec. 2.1).
+ * All work runs in HIP kernels on one GPU, enqueued on the caller's stream.
+ *
+ * Units: the box side is 1 and c = 1.  Positions are in [0, 1); momenta are
+ * the canonical momentum per unit mass u = q/m; conformal time tau is in units
+ * of box/c.  The background is Einstein-de Sitter: a = (H0 tau / 2)^2 with
+ * H0 = box_mpch / 2997.92458.  Mesh arrays are [z][y][x] with x fastest,
+ * n_mesh^3 vertices at x_v = v / n_mesh.
+ *
+ * Memory ownership: the caller allocates one device workspace of the size
+ * pm_query_workspace() reports and owns it; the library carves all its device
+ * buffers out of it and never allocates device memory itself.  Host pointers
+ * passed in are only read (or written) during the call.  pm_ctx is an opaque
+ * host object owned by the library until pm_destroy().
+ *
+ * Ordering and errors: every call enqueues work on the context's stream and
+ * returns without waiting, except calls that write to host memory, which
+ * synchronise the stream.  Functions return pm_status (0 = success, negative =
+ * error) and never throw.  A failed HIP call or a non-finite particle
+ * coordinate found on the device is reported as PM_EHIP / PM_ENAN by the next
+ * synchronising call and is sticky until pm_init_particles().  One context
+ * must not be used from two threads at once.
+ */
+#ifndef PM_H
+#define PM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum pm_status {
+  PM_OK = 0,
+  PM_EINVAL = -1,      /* bad argument (null pointer, size, id out of range) */
+  PM_EWORKSPACE = -2,  /* workspace null, too small or misaligned (256 B) */
+  PM_EHIP = -3,        /* a HIP runtime call failed */
+  PM_ENAN = -4,        /* non-finite particle data detected on the device */
+  PM_ESTATE = -5,      /* call out of order (e.g. solve before deposit) */
+  PM_ERANGE = -6,      /* size outside the supported range */
+  PM_EUNSUPPORTED = -7 /* option not built into this library */
+} pm_status;
+
+/* arithmetic of fields, FFTs, deposit and momenta; positions are always FP64 */
+enum { PM_FP32 = 0, PM_FP64 = 1 };
+
+/* physics: which metric components are solved for and act on particles */
+enum {
+  PM_NEWTONIAN = 0, /* Newtonian limit (Sec. 3.2): lap psi = 4 pi G a^2 delta rho, phi = psi */
+  PM_SCALAR = 1,    /* phi and chi (psi = phi - chi) */
+  PM_FULL = 2       /* phi, chi, B_i (elliptic, Eq. 6) and h_ij (Eq. 5, not fed back) */
+};
+
+enum { PM_FLAG_TIMINGS = 1u }; /* record per-stage device times (pm_get_timings) */
+
+/* field identifiers for pm_get_field / pm_set_field (real space, [z][y][x]) */
+enum {
+  PM_FIELD_N00 = 0, /* deposit sum W e, e = sqrt(a^2 + u^2) (Newtonian: a) */
+  PM_FIELD_N0X = 1, PM_FIELD_N0Y = 2, PM_FIELD_N0Z = 3, /* sum W u_i */
+  PM_FIELD_NXX = 4, PM_FIELD_NXY = 5, PM_FIELD_NXZ = 6, /* sum W u_i u_j / e */
+  PM_FIELD_NYY = 7, PM_FIELD_NYZ = 8, PM_FIELD_NZZ = 9,
+  PM_FIELD_PHI = 10,      /* latest phi (after a solve: phi_n) */
+  PM_FIELD_CHI = 11,      /* latest chi */
+  PM_FIELD_BX = 12, PM_FIELD_BY = 13, PM_FIELD_BZ = 14,
+  PM_FIELD_PHI_PREV = 15, /* phi of the solve before the latest one */
+  PM_FIELD_HXX = 16, PM_FIELD_HXY = 17, PM_FIELD_HXZ = 18, /* h_ij, get only */
+  PM_FIELD_HYY = 19, PM_FIELD_HYZ = 20, PM_FIELD_HZZ = 21,
+  PM_FIELD_COUNT = 22
+};
+
+/* timed stages (PM_FLAG_TIMINGS): each is one kernel or a pair of kernels of one kind */
+enum {
+  PM_STAGE_DEPOSIT = 0,    /* CIC deposit (+ FP64 energy sum) */
+  PM_STAGE_FFT_X_FWD = 1,  /* source assembly + R2C along x */
+  PM_STAGE_FFT_YZ_FWD = 2, /* complex FFTs along y, then z */
+  PM_STAGE_KSOLVE = 3,     /* Fourier-space solves */
+  PM_STAGE_FFT_ZY_INV = 4, /* inverse complex FFTs along z, then y */
+  PM_STAGE_FFT_X_INV = 5,  /* C2R along x */
+  PM_STAGE_KICK_DRIFT = 6, /* gather + kick + drift + cell key */
+  PM_STAGE_SORT = 7,       /* counting sort: scan + scatter */
+  PM_NSTAGES = 8
+};
+
+typedef struct pm_config {
+  int32_t n_mesh;       /* N: power of two, 16 .. 1024 */
+  int32_t precision;    /* PM_FP32 or PM_FP64 */
+  int64_t n_particles;  /* number of particles, 1 .. 2^31 - 1 */
+  double box_mpch;      /* box side in Mpc/h (sets H0 in box units) */
+  int32_t physics;      /* PM_NEWTONIAN, PM_SCALAR or PM_FULL */
+  uint32_t flags;       /* PM_FLAG_* */
+} pm_config;
+
+typedef struct pm_ctx pm_ctx;
+
+/* Device workspace (bytes) that pm_create needs for this configuration. */
+pm_status pm_query_workspace(const pm_config* cfg, size_t* bytes);
+
+/* Create a context on the current HIP device.  d_workspace: device pointer,
+ * 256-byte aligned, at least pm_query_workspace bytes, owned by the caller and
+ * kept alive until pm_destroy.  hip_stream: a hipStream_t (NULL = default). */
+pm_status pm_create(const pm_config* cfg, void* d_workspace, size_t bytes, void* hip_stream, pm_ctx** out);
+pm_status pm_destroy(pm_ctx* ctx);
+
+/* Load particles and reset the time-stepping state.
+ * pos: [n][3] doubles (x, y, z), wrapped into [0, 1) on the device.
+ * u:   [n][3] momenta per unit mass in the context precision (float or double).
+ * ids: [n] identifiers forming a permutation of 0..n-1, or NULL for 0..n-1.
+ * n must equal cfg.n_particles.  tau0 > 0 is the conformal time of pos (u is
+ * at tau0 - dtau/2, the leapfrog's half step).  src_on_device: pointers are
+ * device (1) or host (0) memory. */
+pm_status pm_init_particles(pm_ctx* ctx, const double* pos, const void* u, const uint32_t* ids, int64_t n,
+                            double tau0, int src_on_device);
+
+/* Stage 1: CIC deposit of e, u_i and u_i u_j / e at a(tau) (Sec. 3.1, Eqs. 11-13). */
+pm_status pm_deposit(pm_ctx* ctx);
+
+/* Stage 2: metric solve at the current tau from the last deposit.
+ * dtau_prev > 0: tau - tau_prev of the previous solve (semi-implicit time
+ * derivative, non-linear terms lagged, Sec. 3.1); dtau_prev <= 0: quasi-static
+ * start (two predictor-corrector passes). Requires a preceding pm_deposit. */
+pm_status pm_solve_metric(pm_ctx* ctx, double dtau_prev);
+
+/* Stage 3: gather + kick (u to tau + dtau/2) + drift (x to tau + dtau) + re-sort;
+ * tau += dtau.  Requires a preceding pm_solve_metric.  dtau > 0. */
+pm_status pm_update_particles(pm_ctx* ctx, double dtau);
+
+/* One whole step: deposit, solve (dtau_prev = the previous step's dtau, or a
+ * quasi-static solve on the first step after pm_init_particles), update. */
+pm_status pm_step(pm_ctx* ctx, double dtau);
+
+/* Copy a real-space field ([z][y][x], n_mesh^3 values of the context precision). */
+pm_status pm_get_field(pm_ctx* ctx, int field_id, void* dst, int dst_on_device);
+/* Overwrite a field (deposit components, PHI, CHI, B*, PHI_PREV); for tests and
+ * for the closure. Setting a deposit component marks the deposit as done. */
+pm_status pm_set_field(pm_ctx* ctx, int field_id, const void* src, int src_on_device);
+
+/* Particles in identifier order: pos [n][3] doubles, u [n][3] context precision,
+ * ids [n] (may be NULL; any of pos/u may be NULL). */
+pm_status pm_get_particles(pm_ctx* ctx, double* pos, void* u, uint32_t* ids, int dst_on_device);
+
+/* Current conformal time, scale factor and number of completed steps. */
+pm_status pm_get_time(pm_ctx* ctx, double* tau, double* a, int64_t* steps);
+
+/* Background of a configuration (host only): a(tau) and H_conf(tau) = d ln a / d tau. */
+pm_status pm_background(const pm_config* cfg, double tau, double* a, double* hconf);
+/* Conformal time at which the scale factor equals a. */
+pm_status pm_tau_of_a(const pm_config* cfg, double a, double* tau);
+
+/* Device milliseconds spent in each stage (ms[i]) and the number of times it ran
+ * (calls[i], may be NULL) since the previous pm_get_timings call or context
+ * creation; resets both.  Needs PM_FLAG_TIMINGS.  Synchronises the stream. */
+pm_status pm_get_timings(pm_ctx* ctx, double* ms, int64_t* calls, int n);
+
+/* Wait for the context's stream and report sticky device errors. */
+pm_status pm_sync(pm_ctx* ctx);
+
+/* Diagnostic: 3D real-to-complex FFT of a device array with the library's own
+ * kernels.  direction +1: in = real [z][y][x] (n^3), out = complex [z][y][kx]
+ * (n^2 (n/2+1) interleaved re,im), unnormalised.  direction -1: in = that
+ * half spectrum, out = real, scaled by 1/n^3.  Both device pointers, context
+ * precision; uses the context's spectrum buffer as scratch. */
+pm_status pm_debug_fft(pm_ctx* ctx, const void* d_in, void* d_out, int direction);
+
+const char* pm_status_string(pm_status s);
+/* Last error message recorded on this context (never NULL). */
+const char* pm_last_error(pm_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PM_H */

@@ -1,0 +1,99 @@
+"""ctypes declarations of the C ABI in include/pm.h (argument marshalling only)."""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libgpm.so")
+
+PM_OK, PM_EINVAL, PM_EWORKSPACE, PM_EHIP, PM_ENAN, PM_ESTATE, PM_ERANGE, PM_EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6, -7
+PM_FP32, PM_FP64 = 0, 1
+PM_NEWTONIAN, PM_SCALAR, PM_FULL = 0, 1, 2
+PM_FLAG_TIMINGS = 1
+
+FIELDS = {
+    "n00": 0, "n0x": 1, "n0y": 2, "n0z": 3, "nxx": 4, "nxy": 5, "nxz": 6, "nyy": 7, "nyz": 8, "nzz": 9,
+    "phi": 10, "chi": 11, "bx": 12, "by": 13, "bz": 14, "phi_prev": 15,
+    "hxx": 16, "hxy": 17, "hxz": 18, "hyy": 19, "hyz": 20, "hzz": 21,
+}
+STAGES = ("deposit", "fft_x_fwd", "fft_yz_fwd", "ksolve", "fft_zy_inv", "fft_x_inv", "kick_drift", "sort")
+
+# names of every function include/pm.h declares
+EXPORTS = (
+    "pm_query_workspace", "pm_create", "pm_destroy", "pm_init_particles", "pm_deposit", "pm_solve_metric",
+    "pm_update_particles", "pm_step", "pm_get_field", "pm_set_field", "pm_get_particles", "pm_get_time",
+    "pm_background", "pm_tau_of_a", "pm_get_timings", "pm_sync", "pm_debug_fft", "pm_status_string",
+    "pm_last_error",
+)
+
+
+class PMConfig(C.Structure):
+    _fields_ = [
+        ("n_mesh", C.c_int32),
+        ("precision", C.c_int32),
+        ("n_particles", C.c_int64),
+        ("box_mpch", C.c_double),
+        ("physics", C.c_int32),
+        ("flags", C.c_uint32),
+    ]
+
+
+class PMError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{msg} (status {status})")
+        self.status = status
+
+
+_lib = None
+
+
+def load():
+    """Load libgpm.so; raises if it has not been built (there is no fallback path)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with paper_2607_17929_amd/build.py (hipcc, gfx950)")
+    lib = C.CDLL(LIB_PATH)
+    vp, cfgp = C.c_void_p, C.POINTER(PMConfig)
+    sig = {
+        "pm_query_workspace": [cfgp, C.POINTER(C.c_size_t)],
+        "pm_create": [cfgp, vp, C.c_size_t, vp, C.POINTER(vp)],
+        "pm_destroy": [vp],
+        "pm_init_particles": [vp, vp, vp, vp, C.c_int64, C.c_double, C.c_int],
+        "pm_deposit": [vp],
+        "pm_solve_metric": [vp, C.c_double],
+        "pm_update_particles": [vp, C.c_double],
+        "pm_step": [vp, C.c_double],
+        "pm_get_field": [vp, C.c_int, vp, C.c_int],
+        "pm_set_field": [vp, C.c_int, vp, C.c_int],
+        "pm_get_particles": [vp, vp, vp, vp, C.c_int],
+        "pm_get_time": [vp, C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(C.c_int64)],
+        "pm_background": [cfgp, C.c_double, C.POINTER(C.c_double), C.POINTER(C.c_double)],
+        "pm_tau_of_a": [cfgp, C.c_double, C.POINTER(C.c_double)],
+        "pm_get_timings": [vp, C.POINTER(C.c_double), C.POINTER(C.c_int64), C.c_int],
+        "pm_sync": [vp],
+        "pm_debug_fft": [vp, vp, vp, C.c_int],
+    }
+    for name, args in sig.items():
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = C.c_int
+    lib.pm_status_string.argtypes = [C.c_int]
+    lib.pm_status_string.restype = C.c_char_p
+    lib.pm_last_error.argtypes = [vp]
+    lib.pm_last_error.restype = C.c_char_p
+    _lib = lib
+    return lib
+
+
+def check(status: int, ctx=None, what: str = "") -> None:
+    if status != PM_OK:
+        lib = load()
+        msg = lib.pm_status_string(status).decode()
+        if ctx:
+            detail = lib.pm_last_error(ctx).decode()
+            if detail:
+                msg += f": {detail}"
+        raise PMError(status, f"{what}: {msg}" if what else msg)

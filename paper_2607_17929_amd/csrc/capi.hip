@@ -1,0 +1,694 @@
+// C ABI of the PM library: context, workspace carving, the three stages and the getters.
+#include <math.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/pm.h"
+#include "kernels.h"
+
+using namespace gpm;
+
+namespace {
+
+constexpr size_t kAlign = 256;
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+int mode_of(int physics) {
+  return physics == PM_NEWTONIAN ? MODE_NEWTONIAN : (physics == PM_SCALAR ? MODE_SCALAR : MODE_FULL);
+}
+
+bool is_pow2(long v) { return v > 0 && (v & (v - 1)) == 0; }
+
+// byte offsets of every device buffer inside the workspace
+struct Layout {
+  size_t pos[2], mom[2], ids[2], key, rank, cnt, cell_start, bsum;
+  size_t dep, part, phi[3], chi, b[3], spec, hst[4], tw, kt, rowsum, scal, err;
+  size_t total;
+  int ndep, nsrc, nout, nhp;
+  long spec_comp;
+};
+
+Layout make_layout(const pm_config& c) {
+  Layout L;
+  memset(&L, 0, sizeof(L));
+  const long n = c.n_mesh, n3 = n * n * n, np = c.n_particles;
+  const size_t rs = c.precision == PM_FP64 ? 8 : 4;
+  const int mode = mode_of(c.physics);
+  L.ndep = mode == MODE_NEWTONIAN ? 1 : 10;
+  L.nsrc = mode_nsrc(mode);
+  L.nout = mode == MODE_FULL ? 5 : (mode == MODE_SCALAR ? 2 : 1);
+  L.nhp = (int)((n / 2 + 1 + 15) / 16 * 16);
+  L.spec_comp = n * n * (long)L.nhp;
+  const int nspec = L.nsrc < 6 && mode == MODE_FULL ? 6 : (L.nsrc < 1 ? 1 : L.nsrc);
+  size_t o = 0;
+  auto take = [&](size_t bytes) { size_t r = o; o = align_up(o + bytes); return r; };
+  for (int b = 0; b < 2; ++b) {
+    L.pos[b] = take(3 * np * 8);
+    L.mom[b] = take(3 * np * rs);
+    L.ids[b] = take(np * 4);
+  }
+  L.key = take(np * 4);
+  L.rank = take(np * 4);
+  L.cnt = take(n3 * 4);
+  L.cell_start = take((n3 + 1) * 4);
+  L.bsum = take(scan_block_sums_count(n3) * 4 + 64);
+  L.dep = take(L.ndep * n3 * rs);
+  L.part = take((n3 / 1024 + 1) * 8);
+  for (int i = 0; i < 3; ++i) L.phi[i] = take(n3 * rs);
+  L.chi = mode != MODE_NEWTONIAN ? take(n3 * rs) : 0;
+  for (int i = 0; i < 3; ++i) L.b[i] = mode == MODE_FULL ? take(n3 * rs) : 0;
+  L.spec = take((size_t)nspec * L.spec_comp * 2 * rs);
+  for (int i = 0; i < 4; ++i) L.hst[i] = mode == MODE_FULL ? take(L.spec_comp * 2 * rs) : 0;
+  L.tw = take(n * 2 * rs);
+  L.kt = take(n * rs);
+  L.rowsum = take(n * n * 8);
+  L.scal = take(8 * 8);
+  L.err = take(64);
+  L.total = o;
+  return L;
+}
+
+pm_status check_config(const pm_config* c) {
+  if (!c) return PM_EINVAL;
+  if (!is_pow2(c->n_mesh) || c->n_mesh < 16 || c->n_mesh > 1024) return PM_ERANGE;
+  if (c->precision != PM_FP32 && c->precision != PM_FP64) return PM_EINVAL;
+  if (c->physics < PM_NEWTONIAN || c->physics > PM_FULL) return PM_EINVAL;
+  if (c->n_particles < 1 || c->n_particles > 2147483647LL) return PM_ERANGE;
+  if (!(c->box_mpch > 0) || !isfinite(c->box_mpch)) return PM_EINVAL;
+  return PM_OK;
+}
+
+__global__ void zero_kernel(unsigned char* p, size_t bytes) {
+  const size_t i = ((size_t)blockIdx.x * blockDim.x + threadIdx.x) * 16;
+  if (i + 16 <= bytes) {
+    *reinterpret_cast<uint4*>(p + i) = make_uint4(0, 0, 0, 0);
+  } else {
+    for (size_t j = i; j < bytes; ++j) p[j] = 0;
+  }
+}
+
+}  // namespace
+
+struct pm_ctx {
+  pm_config cfg;
+  Layout L;
+  int n = 0, mode = 0;
+  long n3 = 0, np = 0;
+  size_t rs = 4;
+  hipStream_t st = nullptr;
+  unsigned char* ws = nullptr;
+  int cur = 0;                // particle buffer holding the sorted particles
+  int i_phi = 0, i_prev = 1;  // phi slots: latest, previous
+  double tau = 0, last_step = 0, dtau_last = 0;
+  int64_t steps = 0;
+  bool have_particles = false, deposited = false, solved = false, solved_once = false;
+  int sticky = 0;
+  std::string last_error;
+  // per-stage event pairs recorded since the last pm_get_timings (pool reused)
+  static constexpr int kEvCap = 256;
+  std::vector<hipEvent_t> ev0[PM_NSTAGES], ev1[PM_NSTAGES];
+  int ev_n[PM_NSTAGES] = {0};
+  double ev_ms[PM_NSTAGES] = {0};
+  int64_t ev_calls[PM_NSTAGES] = {0};
+
+  template <typename X> X* at(size_t off) { return reinterpret_cast<X*>(ws + off); }
+  double h0() const { return cfg.box_mpch / 2997.92458; }
+  double a_of(double t) const { const double x = 0.5 * h0() * t; return x * x; }
+  double hc_of(double t) const { return 2.0 / t; }
+  double ebar(double a) const { return 1.5 * h0() * h0() / a; }
+  double kappa() const { return 1.5 * h0() * h0() * (double)n3 / (double)np; }
+
+  pm_status fail(pm_status s, const char* msg) {
+    last_error = msg;
+    return s;
+  }
+  pm_status hip_check(const char* where) {
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) {
+      sticky = PM_EHIP;
+      last_error = std::string(where) + ": " + hipGetErrorString(e);
+      return PM_EHIP;
+    }
+    return PM_OK;
+  }
+  void zero(size_t off, size_t bytes) {
+    const size_t nthr = (bytes + 15) / 16;
+    hipLaunchKernelGGL(zero_kernel, dim3((unsigned)((nthr + 255) / 256)), dim3(256), 0, st, ws + off, bytes);
+  }
+  void drain_events() {
+    (void)hipStreamSynchronize(st);
+    for (int s = 0; s < PM_NSTAGES; ++s) {
+      for (int i = 0; i < ev_n[s]; ++i) {
+        float t = 0.f;
+        if (hipEventElapsedTime(&t, ev0[s][i], ev1[s][i]) == hipSuccess) ev_ms[s] += t;
+      }
+      ev_calls[s] += ev_n[s];
+      ev_n[s] = 0;
+    }
+  }
+  void stage_begin(int s) {
+    if (!(cfg.flags & PM_FLAG_TIMINGS)) return;
+    if (ev_n[s] == kEvCap) drain_events();
+    if ((int)ev0[s].size() <= ev_n[s]) {
+      hipEvent_t a, b;
+      (void)hipEventCreate(&a);
+      (void)hipEventCreate(&b);
+      ev0[s].push_back(a);
+      ev1[s].push_back(b);
+    }
+    (void)hipEventRecord(ev0[s][ev_n[s]], st);
+  }
+  void stage_end(int s) {
+    if (!(cfg.flags & PM_FLAG_TIMINGS)) return;
+    (void)hipEventRecord(ev1[s][ev_n[s]], st);
+    ev_n[s] += 1;
+  }
+
+  template <typename T> Particles<T> parts(int b) {
+    Particles<T> p;
+    double* pb = at<double>(L.pos[b]);
+    T* mb = at<T>(L.mom[b]);
+    p.px = pb; p.py = pb + np; p.pz = pb + 2 * np;
+    p.ux = mb; p.uy = mb + np; p.uz = mb + 2 * np;
+    p.id = at<uint32_t>(L.ids[b]);
+    return p;
+  }
+  void* field_ptr(int id) {
+    if (id >= PM_FIELD_N00 && id <= PM_FIELD_NZZ) {
+      if (id >= L.ndep) return nullptr;
+      return ws + L.dep + (size_t)id * n3 * rs;
+    }
+    switch (id) {
+      case PM_FIELD_PHI: return ws + L.phi[i_phi];
+      case PM_FIELD_PHI_PREV: return ws + L.phi[i_prev];
+      case PM_FIELD_CHI: return L.chi ? ws + L.chi : nullptr;
+      case PM_FIELD_BX: return L.b[0] ? ws + L.b[0] : nullptr;
+      case PM_FIELD_BY: return L.b[1] ? ws + L.b[1] : nullptr;
+      case PM_FIELD_BZ: return L.b[2] ? ws + L.b[2] : nullptr;
+      default: return nullptr;
+    }
+  }
+};
+
+namespace {
+
+template <typename T>
+void upload_tables(pm_ctx* c) {
+  const int n = c->n;
+  std::vector<T> tw(2 * n), kt(n);
+  for (int j = 0; j < n; ++j) {
+    const double ang = -2.0 * M_PI * (double)j / (double)n;
+    tw[2 * j] = (T)cos(ang);
+    tw[2 * j + 1] = (T)sin(ang);
+    const int ms = j <= n / 2 ? j : j - n;
+    kt[j] = (T)(2.0 * n * sin(M_PI * (double)ms / (double)n));
+  }
+  hipMemcpy(c->ws + c->L.tw, tw.data(), tw.size() * sizeof(T), hipMemcpyHostToDevice);
+  hipMemcpy(c->ws + c->L.kt, kt.data(), kt.size() * sizeof(T), hipMemcpyHostToDevice);
+}
+
+// one forward transform + solve + inverse transform
+template <typename T>
+void solve_pass(pm_ctx* c, const T* phi1, const T* phi2, const T* chi1, double inv_dt, double inv_dtl, T* phi_out,
+                int tensor_op, double dtau, double hc_half) {
+  const Layout& L = c->L;
+  const double a = c->a_of(c->tau), hc = c->hc_of(c->tau), eb = c->ebar(a);
+  SrcArgsH<T> s;
+  s.dep = c->at<T>(L.dep);
+  s.phi1 = phi1; s.phi2 = phi2; s.chi1 = chi1;
+  s.rowsum = c->mode == MODE_NEWTONIAN ? nullptr : c->at<double>(L.rowsum);
+  s.kap = c->kappa() / (a * a);
+  s.ebar = eb; s.hc = hc; s.inv_dt = inv_dt; s.inv_dtl = inv_dtl;
+  cplx<T>* spec = c->at<cplx<T>>(L.spec);
+  const cplx<T>* tw = c->at<cplx<T>>(L.tw);
+  c->stage_begin(PM_STAGE_FFT_X_FWD);
+  fft_r2c_x<T>(s, c->mode, c->n, L.nhp, spec, tw, c->st);
+  c->stage_end(PM_STAGE_FFT_X_FWD);
+  c->stage_begin(PM_STAGE_FFT_YZ_FWD);
+  fft_cols<T>(c->n, L.nhp, spec, L.nsrc, false, false, tw, c->st);
+  fft_cols<T>(c->n, L.nhp, spec, L.nsrc, false, true, tw, c->st);
+  c->stage_end(PM_STAGE_FFT_YZ_FWD);
+  double* dc = c->at<double>(L.scal);
+  c->stage_begin(PM_STAGE_KSOLVE);
+  if (c->mode != MODE_NEWTONIAN) launch_sum_f64(s.rowsum, (long)c->n * c->n, dc, c->st);
+  SolveArgs<T> sa;
+  sa.spec = spec; sa.comp_stride = L.spec_comp; sa.n = c->n; sa.nhp = L.nhp; sa.mode = c->mode;
+  sa.kt = c->at<T>(L.kt);
+  sa.hc = hc; sa.inv_dt = inv_dt; sa.ebar = eb; sa.inv_n3 = 1.0 / (double)c->n3;
+  sa.dc = c->mode == MODE_NEWTONIAN ? nullptr : dc;
+  sa.kap_a2 = c->kappa() / (a * a);
+  sa.n3_ebar = (double)c->n3 * eb;
+  sa.phibar_out = dc + 1;
+  sa.hp = L.hst[0] ? c->at<cplx<T>>(L.hst[0]) : nullptr;
+  sa.hx = L.hst[1] ? c->at<cplx<T>>(L.hst[1]) : nullptr;
+  sa.pp = L.hst[2] ? c->at<cplx<T>>(L.hst[2]) : nullptr;
+  sa.px = L.hst[3] ? c->at<cplx<T>>(L.hst[3]) : nullptr;
+  sa.tensor_op = c->mode == MODE_FULL ? tensor_op : 0;
+  sa.dtau = dtau; sa.hc_half = hc_half;
+  launch_solve<T>(sa, c->st);
+  c->stage_end(PM_STAGE_KSOLVE);
+  T* outs[8] = {phi_out, c->mode != MODE_NEWTONIAN ? c->at<T>(L.chi) : nullptr, nullptr, nullptr, nullptr,
+                nullptr, nullptr, nullptr};
+  if (c->mode == MODE_FULL)
+    for (int i = 0; i < 3; ++i) outs[2 + i] = c->at<T>(L.b[i]);
+  c->stage_begin(PM_STAGE_FFT_ZY_INV);
+  fft_cols<T>(c->n, L.nhp, spec, L.nout, true, true, tw, c->st);
+  fft_cols<T>(c->n, L.nhp, spec, L.nout, true, false, tw, c->st);
+  c->stage_end(PM_STAGE_FFT_ZY_INV);
+  c->stage_begin(PM_STAGE_FFT_X_INV);
+  fft_c2r_x<T>(c->n, L.nhp, spec, L.nout, outs, 1.0, tw, c->st);
+  c->stage_end(PM_STAGE_FFT_X_INV);
+}
+
+template <typename T>
+pm_status do_solve(pm_ctx* c, double dtau_prev) {
+  const Layout& L = c->L;
+  auto slot = [&](int i) { return c->at<T>(L.phi[i]); };
+  const T* chi = c->mode != MODE_NEWTONIAN ? c->at<T>(L.chi) : nullptr;
+  if (c->mode == MODE_NEWTONIAN) {
+    const int i_new = 3 - c->i_phi - c->i_prev;
+    solve_pass<T>(c, nullptr, nullptr, nullptr, 0, 0, slot(i_new), 0, 0, 0);
+    c->i_prev = c->i_phi;
+    c->i_phi = i_new;
+  } else if (dtau_prev <= 0) {
+    // quasi-static start: two passes from phi = chi = 0, no time derivatives
+    const int sa = 0, sb = 1, sc = 2;
+    solve_pass<T>(c, nullptr, nullptr, nullptr, 0, 0, slot(sa), 1, 0, 0);
+    solve_pass<T>(c, slot(sa), slot(sa), chi, 0, 0, slot(sb), 1, 0, 0);
+    hipMemcpyAsync(slot(sc), slot(sb), c->n3 * sizeof(T), hipMemcpyDeviceToDevice, c->st);
+    c->i_phi = sb;
+    c->i_prev = sc;
+    c->dtau_last = 0;
+  } else {
+    const int i_new = 3 - c->i_phi - c->i_prev;
+    const double inv_dtl = c->dtau_last > 0 ? 1.0 / c->dtau_last : 0.0;
+    const double hc_half = c->hc_of(c->tau - 0.5 * dtau_prev);
+    solve_pass<T>(c, slot(c->i_phi), slot(c->i_prev), chi, 1.0 / dtau_prev, inv_dtl, slot(i_new), 2, dtau_prev,
+                  hc_half);
+    c->i_prev = c->i_phi;
+    c->i_phi = i_new;
+    c->dtau_last = dtau_prev;
+  }
+  return c->hip_check("solve");
+}
+
+template <typename T>
+void sort_particles(pm_ctx* c) {
+  const Layout& L = c->L;
+  launch_scan(c->at<uint32_t>(L.cnt), c->at<uint32_t>(L.cell_start), c->n3, c->at<uint32_t>(L.bsum), c->st);
+  launch_scatter<T>(c->parts<T>(c->cur), c->parts<T>(1 - c->cur), c->np, c->at<uint32_t>(L.key),
+                    c->at<uint32_t>(L.rank), c->at<uint32_t>(L.cell_start), c->st);
+  c->cur = 1 - c->cur;
+}
+
+template <typename T>
+pm_status do_init(pm_ctx* c, const double* pos, const void* u, const uint32_t* ids, int on_device) {
+  const Layout& L = c->L;
+  const long np = c->np;
+  // staging for host data: the second particle buffer
+  const double* dpos = pos;
+  const T* du = reinterpret_cast<const T*>(u);
+  const uint32_t* dids = ids;
+  if (!on_device) {
+    double* sp = c->at<double>(L.pos[1]);
+    T* su = c->at<T>(L.mom[1]);
+    uint32_t* si = c->at<uint32_t>(L.ids[1]);
+    hipMemcpyAsync(sp, pos, 3 * np * sizeof(double), hipMemcpyHostToDevice, c->st);
+    hipMemcpyAsync(su, u, 3 * np * sizeof(T), hipMemcpyHostToDevice, c->st);
+    if (ids) hipMemcpyAsync(si, ids, np * sizeof(uint32_t), hipMemcpyHostToDevice, c->st);
+    dpos = sp; du = su; dids = ids ? si : nullptr;
+  }
+  // clear counts, error flag, fields and tensor state
+  c->zero(L.cnt, c->n3 * 4);
+  c->zero(L.err, 64);
+  for (int i = 0; i < 3; ++i) c->zero(L.phi[i], c->n3 * c->rs);
+  if (L.chi) c->zero(L.chi, c->n3 * c->rs);
+  for (int i = 0; i < 3; ++i)
+    if (L.b[i]) c->zero(L.b[i], c->n3 * c->rs);
+  for (int i = 0; i < 4; ++i)
+    if (L.hst[i]) c->zero(L.hst[i], L.spec_comp * 2 * c->rs);
+  Particles<T> p0 = c->parts<T>(0);
+  launch_ingest<T>(dpos, du, dids, np, p0, c->n, c->at<uint32_t>(L.key), c->at<uint32_t>(L.rank),
+                   c->at<uint32_t>(L.cnt), c->at<int>(L.err), c->st);
+  c->cur = 0;
+  sort_particles<T>(c);
+  if (!on_device) hipStreamSynchronize(c->st);  // host buffers may be released after return
+  return c->hip_check("init_particles");
+}
+
+template <typename T>
+pm_status do_update(pm_ctx* c, double dtau) {
+  const Layout& L = c->L;
+  GatherArgs<T> g;
+  g.phi = c->at<T>(L.phi[c->i_phi]);
+  g.chi = L.chi ? c->at<T>(L.chi) : nullptr;
+  g.bx = L.b[0] ? c->at<T>(L.b[0]) : nullptr;
+  g.by = L.b[1] ? c->at<T>(L.b[1]) : nullptr;
+  g.bz = L.b[2] ? c->at<T>(L.b[2]) : nullptr;
+  g.mode = c->mode;
+  g.dtau = dtau;
+  g.a = c->a_of(c->tau);
+  g.a_half = c->a_of(c->tau + 0.5 * dtau);
+  c->stage_begin(PM_STAGE_KICK_DRIFT);
+  launch_kick_drift<T>(c->parts<T>(c->cur), c->np, c->n, g, c->at<uint32_t>(L.key), c->at<uint32_t>(L.rank),
+                       c->at<uint32_t>(L.cnt), c->at<int>(L.err), c->st);
+  c->stage_end(PM_STAGE_KICK_DRIFT);
+  c->stage_begin(PM_STAGE_SORT);
+  sort_particles<T>(c);
+  c->stage_end(PM_STAGE_SORT);
+  c->tau += dtau;
+  c->steps += 1;
+  return c->hip_check("update_particles");
+}
+
+pm_status read_sticky(pm_ctx* c) {
+  if (c->sticky) return (pm_status)c->sticky;
+  int err = 0;
+  if (hipMemcpy(&err, c->ws + c->L.err, sizeof(int), hipMemcpyDeviceToHost) != hipSuccess) {
+    c->sticky = PM_EHIP;
+    c->last_error = "reading the device error flag failed";
+    return PM_EHIP;
+  }
+  if (err & 1) { c->sticky = PM_ENAN; c->last_error = "non-finite particle coordinate or momentum"; }
+  else if (err & 2) { c->sticky = PM_EINVAL; c->last_error = "particle identifier out of range"; }
+  return (pm_status)c->sticky;
+}
+
+#define DISPATCH(c, F, ...) ((c)->cfg.precision == PM_FP64 ? F<double>(__VA_ARGS__) : F<float>(__VA_ARGS__))
+
+}  // namespace
+
+extern "C" {
+
+pm_status pm_query_workspace(const pm_config* cfg, size_t* bytes) {
+  pm_status s = check_config(cfg);
+  if (s != PM_OK) return s;
+  if (!bytes) return PM_EINVAL;
+  *bytes = make_layout(*cfg).total;
+  return PM_OK;
+}
+
+pm_status pm_create(const pm_config* cfg, void* d_workspace, size_t bytes, void* hip_stream, pm_ctx** out) {
+  pm_status s = check_config(cfg);
+  if (s != PM_OK) return s;
+  if (!out) return PM_EINVAL;
+  *out = nullptr;
+  Layout L = make_layout(*cfg);
+  if (!d_workspace || bytes < L.total || ((uintptr_t)d_workspace % kAlign) != 0) return PM_EWORKSPACE;
+  pm_ctx* c = new (std::nothrow) pm_ctx();
+  if (!c) return PM_EINVAL;
+  c->cfg = *cfg;
+  c->L = L;
+  c->n = cfg->n_mesh;
+  c->n3 = (long)c->n * c->n * c->n;
+  c->np = cfg->n_particles;
+  c->mode = mode_of(cfg->physics);
+  c->rs = cfg->precision == PM_FP64 ? 8 : 4;
+  c->st = reinterpret_cast<hipStream_t>(hip_stream);
+  c->ws = reinterpret_cast<unsigned char*>(d_workspace);
+  if (cfg->precision == PM_FP64) upload_tables<double>(c); else upload_tables<float>(c);
+  if (c->hip_check("create") != PM_OK) {
+    delete c;
+    return PM_EHIP;
+  }
+  *out = c;
+  return PM_OK;
+}
+
+pm_status pm_destroy(pm_ctx* c) {
+  if (!c) return PM_EINVAL;
+  hipStreamSynchronize(c->st);
+  for (int i = 0; i < PM_NSTAGES; ++i) {
+    for (auto e : c->ev0[i]) (void)hipEventDestroy(e);
+    for (auto e : c->ev1[i]) (void)hipEventDestroy(e);
+  }
+  delete c;
+  return PM_OK;
+}
+
+pm_status pm_init_particles(pm_ctx* c, const double* pos, const void* u, const uint32_t* ids, int64_t n, double tau0,
+                            int src_on_device) {
+  if (!c || !pos || !u) return PM_EINVAL;
+  if (n != c->np) return c->fail(PM_EINVAL, "n differs from the configured particle count");
+  if (!(tau0 > 0) || !isfinite(tau0)) return c->fail(PM_EINVAL, "tau0 must be positive");
+  c->sticky = 0;
+  c->tau = tau0;
+  c->steps = 0;
+  c->last_step = 0;
+  c->dtau_last = 0;
+  c->i_phi = 0;
+  c->i_prev = 1;
+  c->deposited = c->solved = c->solved_once = false;
+  pm_status s = DISPATCH(c, do_init, c, pos, u, ids, src_on_device);
+  if (s != PM_OK) return s;
+  c->have_particles = true;
+  return PM_OK;
+}
+
+pm_status pm_deposit(pm_ctx* c) {
+  if (!c) return PM_EINVAL;
+  if (!c->have_particles) return c->fail(PM_ESTATE, "deposit before init_particles");
+  if (c->sticky) return (pm_status)c->sticky;
+  const double a = c->a_of(c->tau);
+  c->stage_begin(PM_STAGE_DEPOSIT);
+  if (c->cfg.precision == PM_FP64)
+    launch_deposit<double>(c->parts<double>(c->cur), c->at<uint32_t>(c->L.cell_start), c->n, c->L.ndep,
+                           c->mode != MODE_NEWTONIAN, a, c->at<double>(c->L.dep), c->at<double>(c->L.part),
+                           c->at<double>(c->L.scal) + 2, c->st);
+  else
+    launch_deposit<float>(c->parts<float>(c->cur), c->at<uint32_t>(c->L.cell_start), c->n, c->L.ndep,
+                          c->mode != MODE_NEWTONIAN, a, c->at<float>(c->L.dep), c->at<double>(c->L.part),
+                          c->at<double>(c->L.scal) + 2, c->st);
+  c->stage_end(PM_STAGE_DEPOSIT);
+  c->deposited = true;
+  return c->hip_check("deposit");
+}
+
+pm_status pm_solve_metric(pm_ctx* c, double dtau_prev) {
+  if (!c) return PM_EINVAL;
+  if (!c->deposited) return c->fail(PM_ESTATE, "solve_metric needs a preceding deposit");
+  if (c->sticky) return (pm_status)c->sticky;
+  if (!isfinite(dtau_prev)) return c->fail(PM_EINVAL, "dtau_prev must be finite");
+  if (dtau_prev >= c->tau) return c->fail(PM_EINVAL, "dtau_prev must be smaller than tau");
+  pm_status s = DISPATCH(c, do_solve, c, dtau_prev);
+  if (s != PM_OK) return s;
+  c->deposited = false;
+  c->solved = true;
+  c->solved_once = true;
+  return PM_OK;
+}
+
+pm_status pm_update_particles(pm_ctx* c, double dtau) {
+  if (!c) return PM_EINVAL;
+  if (!c->solved) return c->fail(PM_ESTATE, "update_particles needs a preceding solve_metric");
+  if (c->sticky) return (pm_status)c->sticky;
+  if (!(dtau > 0) || !isfinite(dtau)) return c->fail(PM_EINVAL, "dtau must be positive");
+  pm_status s = DISPATCH(c, do_update, c, dtau);
+  if (s != PM_OK) return s;
+  c->solved = false;
+  c->last_step = dtau;
+  return PM_OK;
+}
+
+pm_status pm_step(pm_ctx* c, double dtau) {
+  if (!c) return PM_EINVAL;
+  if (!(dtau > 0) || !isfinite(dtau)) return c->fail(PM_EINVAL, "dtau must be positive");
+  const double dtau_prev = c->solved_once ? c->last_step : 0.0;
+  pm_status s = pm_deposit(c);
+  if (s != PM_OK) return s;
+  s = pm_solve_metric(c, dtau_prev);
+  if (s != PM_OK) return s;
+  return pm_update_particles(c, dtau);
+}
+
+pm_status pm_get_field(pm_ctx* c, int id, void* dst, int dst_on_device) {
+  if (!c || !dst) return PM_EINVAL;
+  if (id < 0 || id >= PM_FIELD_COUNT) return c->fail(PM_EINVAL, "unknown field id");
+  const size_t bytes = c->n3 * c->rs;
+  const void* src = nullptr;
+  if (id >= PM_FIELD_HXX && id <= PM_FIELD_HZZ) {
+    if (c->mode != MODE_FULL) return c->fail(PM_EINVAL, "h_ij needs PM_FULL physics");
+    // rebuild the six components into the spectrum buffer and transform the requested one
+    const int comp = id - PM_FIELD_HXX;
+    const Layout& L = c->L;
+    if (c->cfg.precision == PM_FP64) {
+      cplx<double>* spec = c->at<cplx<double>>(L.spec);
+      launch_tensor_components<double>(spec, L.spec_comp, c->n, L.nhp, c->at<double>(L.kt),
+                                       c->at<cplx<double>>(L.hst[0]), c->at<cplx<double>>(L.hst[1]), 0, c->st);
+      double* out[1] = {c->at<double>(L.dep)};
+      fft_inverse<double>(c->n, L.nhp, spec + comp * L.spec_comp, 1, out, 1.0 / c->n3, c->at<cplx<double>>(L.tw), c->st);
+    } else {
+      cplx<float>* spec = c->at<cplx<float>>(L.spec);
+      launch_tensor_components<float>(spec, L.spec_comp, c->n, L.nhp, c->at<float>(L.kt), c->at<cplx<float>>(L.hst[0]),
+                                      c->at<cplx<float>>(L.hst[1]), 0, c->st);
+      float* out[1] = {c->at<float>(L.dep)};
+      fft_inverse<float>(c->n, L.nhp, spec + comp * L.spec_comp, 1, out, 1.0 / c->n3, c->at<cplx<float>>(L.tw), c->st);
+    }
+    c->deposited = false;  // the deposit buffer served as scratch
+    src = c->ws + L.dep;
+  } else {
+    src = c->field_ptr(id);
+    if (!src) return c->fail(PM_EINVAL, "field not present for this physics");
+  }
+  if (dst_on_device) {
+    hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, c->st);
+  } else {
+    hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, c->st);
+    hipStreamSynchronize(c->st);
+  }
+  pm_status s = c->hip_check("get_field");
+  if (s != PM_OK) return s;
+  return dst_on_device ? PM_OK : read_sticky(c);
+}
+
+pm_status pm_set_field(pm_ctx* c, int id, const void* src, int src_on_device) {
+  if (!c || !src) return PM_EINVAL;
+  if (id < 0 || id >= PM_FIELD_HXX) return c->fail(PM_EINVAL, "field cannot be set");
+  void* dst = c->field_ptr(id);
+  if (!dst) return c->fail(PM_EINVAL, "field not present for this physics");
+  hipMemcpyAsync(dst, src, c->n3 * c->rs, src_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, c->st);
+  if (!src_on_device) hipStreamSynchronize(c->st);
+  if (id == PM_FIELD_N00 && c->mode != MODE_NEWTONIAN) {
+    // the homogeneous mode then comes from the mesh: sum of n00 in FP64
+    if (c->cfg.precision == PM_FP64)
+      launch_sum_f64(c->at<double>(c->L.dep), c->n3, c->at<double>(c->L.scal) + 2, c->st);
+    else
+      launch_sum_as_f64(c->at<float>(c->L.dep), c->n3, c->at<double>(c->L.scal) + 2, c->st);
+  }
+  if (id <= PM_FIELD_NZZ) c->deposited = true;
+  else if (id != PM_FIELD_PHI_PREV) c->solved = true;
+  return c->hip_check("set_field");
+}
+
+pm_status pm_get_particles(pm_ctx* c, double* pos, void* u, uint32_t* ids, int dst_on_device) {
+  if (!c) return PM_EINVAL;
+  if (!c->have_particles) return c->fail(PM_ESTATE, "no particles");
+  const Layout& L = c->L;
+  const long np = c->np;
+  const int other = 1 - c->cur;
+  double* sp = dst_on_device ? pos : (pos ? c->at<double>(L.pos[other]) : nullptr);
+  void* su = dst_on_device ? u : (u ? (void*)(c->ws + L.mom[other]) : nullptr);
+  uint32_t* si = dst_on_device ? ids : (ids ? c->at<uint32_t>(L.ids[other]) : nullptr);
+  if (c->cfg.precision == PM_FP64)
+    launch_export<double>(c->parts<double>(c->cur), np, sp, reinterpret_cast<double*>(su), si, c->st);
+  else
+    launch_export<float>(c->parts<float>(c->cur), np, sp, reinterpret_cast<float*>(su), si, c->st);
+  if (!dst_on_device) {
+    if (pos) hipMemcpyAsync(pos, sp, 3 * np * sizeof(double), hipMemcpyDeviceToHost, c->st);
+    if (u) hipMemcpyAsync(u, su, 3 * np * c->rs, hipMemcpyDeviceToHost, c->st);
+    if (ids) hipMemcpyAsync(ids, si, np * sizeof(uint32_t), hipMemcpyDeviceToHost, c->st);
+    hipStreamSynchronize(c->st);
+  }
+  pm_status s = c->hip_check("get_particles");
+  if (s != PM_OK) return s;
+  return dst_on_device ? PM_OK : read_sticky(c);
+}
+
+pm_status pm_get_time(pm_ctx* c, double* tau, double* a, int64_t* steps) {
+  if (!c) return PM_EINVAL;
+  if (tau) *tau = c->tau;
+  if (a) *a = c->a_of(c->tau);
+  if (steps) *steps = c->steps;
+  return PM_OK;
+}
+
+pm_status pm_background(const pm_config* cfg, double tau, double* a, double* hconf) {
+  if (!cfg || !(cfg->box_mpch > 0) || !(tau > 0)) return PM_EINVAL;
+  const double h0 = cfg->box_mpch / 2997.92458;
+  const double x = 0.5 * h0 * tau;
+  if (a) *a = x * x;
+  if (hconf) *hconf = 2.0 / tau;
+  return PM_OK;
+}
+
+pm_status pm_tau_of_a(const pm_config* cfg, double a, double* tau) {
+  if (!cfg || !(cfg->box_mpch > 0) || !(a > 0) || !tau) return PM_EINVAL;
+  *tau = 2.0 * sqrt(a) / (cfg->box_mpch / 2997.92458);
+  return PM_OK;
+}
+
+pm_status pm_get_timings(pm_ctx* c, double* ms, int64_t* calls, int n) {
+  if (!c || !ms) return PM_EINVAL;
+  if (!(c->cfg.flags & PM_FLAG_TIMINGS)) return c->fail(PM_EUNSUPPORTED, "context created without PM_FLAG_TIMINGS");
+  c->drain_events();
+  for (int i = 0; i < n && i < PM_NSTAGES; ++i) {
+    ms[i] = c->ev_ms[i];
+    if (calls) calls[i] = c->ev_calls[i];
+  }
+  for (int i = 0; i < PM_NSTAGES; ++i) {
+    c->ev_ms[i] = 0;
+    c->ev_calls[i] = 0;
+  }
+  return c->hip_check("get_timings");
+}
+
+pm_status pm_sync(pm_ctx* c) {
+  if (!c) return PM_EINVAL;
+  if (hipStreamSynchronize(c->st) != hipSuccess) {
+    c->sticky = PM_EHIP;
+    c->last_error = "stream synchronisation failed";
+    return PM_EHIP;
+  }
+  pm_status s = c->hip_check("sync");
+  if (s != PM_OK) return s;
+  return read_sticky(c);
+}
+
+pm_status pm_debug_fft(pm_ctx* c, const void* d_in, void* d_out, int direction) {
+  if (!c || !d_in || !d_out) return PM_EINVAL;
+  if (direction != 1 && direction != -1) return PM_EINVAL;
+  const Layout& L = c->L;
+  if (c->cfg.precision == PM_FP64) {
+    cplx<double>* spec = c->at<cplx<double>>(L.spec);
+    if (direction == 1) {
+      SrcArgsH<double> s;
+      s.raw = reinterpret_cast<const double*>(d_in);
+      fft_forward<double>(s, MODE_RAW, c->n, L.nhp, spec, 1, c->at<cplx<double>>(L.tw), c->st);
+      launch_copy_unpad<double>(spec, c->n, L.nhp, reinterpret_cast<cplx<double>*>(d_out), false, c->st);
+    } else {
+      launch_copy_unpad<double>(spec, c->n, L.nhp, const_cast<cplx<double>*>(reinterpret_cast<const cplx<double>*>(d_in)),
+                                true, c->st);
+      double* out[1] = {reinterpret_cast<double*>(d_out)};
+      fft_inverse<double>(c->n, L.nhp, spec, 1, out, 1.0 / c->n3, c->at<cplx<double>>(L.tw), c->st);
+    }
+  } else {
+    cplx<float>* spec = c->at<cplx<float>>(L.spec);
+    if (direction == 1) {
+      SrcArgsH<float> s;
+      s.raw = reinterpret_cast<const float*>(d_in);
+      fft_forward<float>(s, MODE_RAW, c->n, L.nhp, spec, 1, c->at<cplx<float>>(L.tw), c->st);
+      launch_copy_unpad<float>(spec, c->n, L.nhp, reinterpret_cast<cplx<float>*>(d_out), false, c->st);
+    } else {
+      launch_copy_unpad<float>(spec, c->n, L.nhp, const_cast<cplx<float>*>(reinterpret_cast<const cplx<float>*>(d_in)),
+                               true, c->st);
+      float* out[1] = {reinterpret_cast<float*>(d_out)};
+      fft_inverse<float>(c->n, L.nhp, spec, 1, out, 1.0 / c->n3, c->at<cplx<float>>(L.tw), c->st);
+    }
+  }
+  c->deposited = false;
+  return c->hip_check("debug_fft");
+}
+
+const char* pm_status_string(pm_status s) {
+  switch (s) {
+    case PM_OK: return "ok";
+    case PM_EINVAL: return "invalid argument";
+    case PM_EWORKSPACE: return "workspace missing, too small or misaligned";
+    case PM_EHIP: return "HIP runtime error";
+    case PM_ENAN: return "non-finite particle data";
+    case PM_ESTATE: return "call out of order";
+    case PM_ERANGE: return "size out of supported range";
+    case PM_EUNSUPPORTED: return "unsupported option";
+    default: return "unknown status";
+  }
+}
+
+const char* pm_last_error(pm_ctx* c) {
+  if (!c) return "null context";
+  return c->last_error.c_str();
+}
+
+}  // extern "C"

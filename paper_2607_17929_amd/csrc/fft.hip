@@ -1,0 +1,487 @@
+// 3D real-to-complex FFT passes for an n^3 periodic mesh on gfx950.
+//
+// Layouts (x fastest, as in the paper's rod decomposition, Sec. 2):
+//   real field      [z][y][x]                  n^3 values
+//   half spectrum   [z][y][kx], kx = 0 .. n/2  rows padded to NHP complex values
+// A forward 3D transform is three passes, each reading and writing the whole
+// half spectrum once:
+//   pass X  (rows along x, contiguous): source assembly fused in, R2C by the
+//           half-length complex FFT with the usual even/odd post-processing;
+//   pass Y  (columns along y) and pass Z (columns along z): batched complex
+//           FFTs on LDS tiles of n elements x C contiguous kx columns, so that
+//           every global access is a C*sizeof(complex) = 128-byte segment.
+// The inverse runs pass Z, pass Y and the C2R pass X.  Each 1D FFT is a
+// Stockham auto-sort radix-8/4/2 transform done in place in LDS: every thread
+// loads its butterflies' inputs into registers, the workgroup synchronises,
+// and the results are written back, so one tile buffer suffices.  The first
+// stage of a column pass reads straight from global memory and its last stage
+// writes straight to global memory.  Twiddles come from a table of
+// exp(-2 pi i j / n) computed in FP64 on the host.
+#include "common.h"
+#include "kernels.h"
+
+namespace gpm {
+
+// ---------------------------------------------------------------------------
+// Column passes (Y and Z)
+// ---------------------------------------------------------------------------
+// One Stockham stage over a tile of C columns x N elements held in LDS as
+// [element][column].  Job j -> column j % C (fastest, so a wave touches
+// consecutive LDS words), butterfly index j / C.
+template <typename T, int N, int C, int NT, int S, bool INV, bool FROM_G, bool TO_G>
+__device__ __forceinline__ void col_stage(cplx<T>* sm, cplx<T>* g, long es, int cvalid, const cplx<T>* __restrict__ tw) {
+  constexpr int R = stage_radix(N, S);
+  constexpr int NS = stage_ns(N, S);
+  constexpr int J = N * C / R;
+  constexpr int PER = (J + NT - 1) / NT;
+  const int tid = threadIdx.x;
+  cplx<T> v[PER][R];
+#pragma unroll
+  for (int p = 0; p < PER; ++p) {
+    const int job = tid + p * NT;
+    if (J % NT == 0 || job < J) {
+      const int col = job % C, i = job / C;
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const int e = i + r * (N / R);
+        if (FROM_G) {
+          v[p][r] = (col < cvalid) ? g[(long)e * es + col] : mk<T>(0, 0);
+        } else {
+          v[p][r] = sm[e * C + col];
+        }
+      }
+    }
+  }
+  if (!FROM_G) __syncthreads();
+#pragma unroll
+  for (int p = 0; p < PER; ++p) {
+    const int job = tid + p * NT;
+    if (J % NT == 0 || job < J) {
+      const int col = job % C, i = job / C;
+      const int k = i % NS;
+      if (NS > 1) {
+#pragma unroll
+        for (int r = 1; r < R; ++r) {
+          const cplx<T> w = tw[(r * k) * (N / (NS * R))];
+          v[p][r] = INV ? cmulc(v[p][r], w) : cmul(v[p][r], w);
+        }
+      }
+      dftR<T, R, INV>(v[p]);
+      const int j0 = (i / NS) * NS * R + k;
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const int e = j0 + r * NS;
+        if (TO_G) {
+          if (col < cvalid) g[(long)e * es + col] = v[p][r];
+        } else {
+          sm[e * C + col] = v[p][r];
+        }
+      }
+    }
+  }
+  if (!TO_G) __syncthreads();
+}
+
+template <typename T, int N, int C, int NT, int S, bool INV>
+__device__ __forceinline__ void col_stages(cplx<T>* sm, cplx<T>* g, long es, int cvalid, const cplx<T>* tw) {
+  constexpr int NSTG = nstages(N);
+  if constexpr (S < NSTG) {
+    col_stage<T, N, C, NT, S, INV, S == 0, S == NSTG - 1>(sm, g, es, cvalid, tw);
+    col_stages<T, N, C, NT, S + 1, INV>(sm, g, es, cvalid, tw);
+  }
+}
+
+// grid: x = column tile, y = outer index, z = component
+template <typename T, int N, int C, int NT, bool INV>
+__global__ __launch_bounds__(NT) void fft_cols_kernel(cplx<T>* data, long es, long outer_stride, long comp_stride,
+                                                      int ncols, const cplx<T>* __restrict__ tw) {
+  __shared__ cplx<T> sm[N * C];
+  const int col0 = blockIdx.x * C;
+  cplx<T>* g = data + (long)blockIdx.z * comp_stride + (long)blockIdx.y * outer_stride + col0;
+  const int cvalid = min(C, ncols - col0);
+  col_stages<T, N, C, NT, 0, INV>(sm, g, es, cvalid, tw);
+}
+
+// ---------------------------------------------------------------------------
+// Row FFTs in LDS (pass X): L lines of M complex values, line stride LS.
+// Job j -> line j / (M/R), butterfly j % (M/R).
+// ---------------------------------------------------------------------------
+template <typename T, int M, int L, int LS, int NT, int S, bool INV>
+__device__ __forceinline__ void row_stage(cplx<T>* sm, const cplx<T>* __restrict__ tw, int twstep) {
+  constexpr int R = stage_radix(M, S);
+  constexpr int NS = stage_ns(M, S);
+  constexpr int B = M / R;
+  constexpr int J = L * B;
+  constexpr int PER = (J + NT - 1) / NT;
+  const int tid = threadIdx.x;
+  cplx<T> v[PER][R];
+#pragma unroll
+  for (int p = 0; p < PER; ++p) {
+    const int job = tid + p * NT;
+    if (J % NT == 0 || job < J) {
+      const int line = job / B, i = job % B;
+#pragma unroll
+      for (int r = 0; r < R; ++r) v[p][r] = sm[line * LS + i + r * B];
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int p = 0; p < PER; ++p) {
+    const int job = tid + p * NT;
+    if (J % NT == 0 || job < J) {
+      const int line = job / B, i = job % B;
+      const int k = i % NS;
+      if (NS > 1) {
+#pragma unroll
+        for (int r = 1; r < R; ++r) {
+          const cplx<T> w = tw[(r * k) * (M / (NS * R)) * twstep];
+          v[p][r] = INV ? cmulc(v[p][r], w) : cmul(v[p][r], w);
+        }
+      }
+      dftR<T, R, INV>(v[p]);
+      const int j0 = (i / NS) * NS * R + k;
+#pragma unroll
+      for (int r = 0; r < R; ++r) sm[line * LS + j0 + r * NS] = v[p][r];
+    }
+  }
+  __syncthreads();
+}
+
+template <typename T, int M, int L, int LS, int NT, int S, bool INV>
+__device__ __forceinline__ void row_stages(cplx<T>* sm, const cplx<T>* tw, int twstep) {
+  if constexpr (S < nstages(M)) {
+    row_stage<T, M, L, LS, NT, S, INV>(sm, tw, twstep);
+    row_stages<T, M, L, LS, NT, S + 1, INV>(sm, tw, twstep);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Source assembly (the paper's per-site mesh kernel, Sec. 2.2), fused into pass X.
+// ---------------------------------------------------------------------------
+template <typename T> __device__ __forceinline__ T expm1_minus_x(T x) {
+  // exp(x) - 1 - x; Taylor series for small |x| keeps full relative precision
+  if (fabs(x) < (T)1e-2) {
+    return x * x * ((T)0.5 + x * ((T)(1.0 / 6) + x * ((T)(1.0 / 24) + x * ((T)(1.0 / 120) + x * (T)(1.0 / 720)))));
+  }
+  return expm1(x) - x;
+}
+
+template <typename T>
+struct SrcArgs {
+  const T* dep;    // deposit components, stride n^3
+  const T* phi1;   // lagged phi_{n-1} (null: zero)
+  const T* phi2;   // phi_{n-2}
+  const T* chi1;   // lagged chi
+  const T* raw;    // MODE_RAW: the field to transform
+  double* rowsum;  // FP64 row sums [z][y] of the phi source without its E - ebar term (may be null)
+  T kap;           // 4 pi G m / dx^3 / a^2
+  T ebar;          // 4 pi G a^2 rho_bar
+  T hc;            // H_conf at the solve time
+  T inv_dt;        // 1 / (tau_n - tau_{n-1}), 0 for a quasi-static solve
+  T inv_dtl;       // 1 / (tau_{n-1} - tau_{n-2}) for the lagged phi-dot, 0 if unknown
+  T half_n;        // n / 2: centred difference factor
+};
+
+// Writes the n_src sources of vertex (x, y, z) to out[c * cstride].
+template <typename T, int MODE>
+__device__ __forceinline__ T assemble_point(const SrcArgs<T>& a, int n, int x, int y, int z, T* out, int cstride) {
+  const long nn = (long)n * n;
+  const long idx = (long)z * nn + (long)y * n + x;
+  if constexpr (MODE == MODE_RAW) {
+    out[0] = a.raw[idx];
+    return out[0];
+  } else if constexpr (MODE == MODE_NEWTONIAN) {
+    const T s = a.kap * a.dep[idx] - a.ebar;
+    out[0] = s;
+    return s;
+  } else {
+    const long n3 = nn * n;
+    const T E = a.kap * a.dep[idx];
+    T p = 0, c = 0, pd = 0, gp[3] = {0, 0, 0}, gc[3] = {0, 0, 0};
+    if (a.phi1) {
+      const int xm = wrapi(x - 1, n), xp = wrapi(x + 1, n);
+      const int ym = wrapi(y - 1, n), yp = wrapi(y + 1, n);
+      const int zm = wrapi(z - 1, n), zp = wrapi(z + 1, n);
+      const long rz = (long)z * nn, ry = (long)y * n;
+      const long ix[3][2] = {{rz + ry + xp, rz + ry + xm},
+                             {rz + (long)yp * n + x, rz + (long)ym * n + x},
+                             {(long)zp * nn + ry + x, (long)zm * nn + ry + x}};
+      p = a.phi1[idx];
+      c = a.chi1[idx];
+      pd = (p - a.phi2[idx]) * a.inv_dtl;
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        gp[d] = (a.phi1[ix[d][0]] - a.phi1[ix[d][1]]) * a.half_n;
+        gc[d] = (a.chi1[ix[d][0]] - a.chi1[ix[d][1]]) * a.half_n;
+      }
+    }
+    const T hc = a.hc, eb = a.ebar;
+    // non-linear remainder of the Hamiltonian constraint (lagged fields)
+    const T w = (T)2 * p - c;
+    const T g2 = gp[0] * gp[0] + gp[1] * gp[1] + gp[2] * gp[2];
+    const T hmd = hc - pd;
+    const T R = (T)0.5 * g2 + (E - eb) * p + E * expm1_minus_x(p) -
+                (T)1.5 * (hmd * hmd * expm1_minus_x((T)-2 * w) + (T)2 * w * ((T)2 * hc * pd - pd * pd) + pd * pd);
+    // the mean of E - ebar is taken from an FP64 sum over particles; the rest is summed here
+    const T rest = R - (T)3 * hc * a.inv_dt * p - (T)3 * hc * hc * c;
+    const T rhs = (E - eb) + rest;
+    out[0] = rhs;
+    // trace-free space-space source (symmetric, order xx xy xz yy yz zz)
+    const T e3 = exp((T)3 * p);
+    const int si[6] = {0, 0, 0, 1, 1, 2}, sj[6] = {0, 1, 2, 1, 2, 2};
+#pragma unroll
+    for (int s = 0; s < 6; ++s) {
+      const int i = si[s], j = sj[s];
+      const T K = a.kap * a.dep[(4 + s) * n3 + idx];
+      out[(1 + s) * cstride] = (T)4 * e3 * K + (T)4 * gp[i] * gp[j] - (T)4 * (gp[i] * gc[j] + gc[i] * gp[j]) +
+                               (T)2 * gc[i] * gc[j];
+    }
+    if constexpr (MODE == MODE_FULL) {
+      const T ef = exp((p - c) + (T)3 * p);
+#pragma unroll
+      for (int i = 0; i < 3; ++i) {
+        const T J = a.kap * a.dep[(1 + i) * n3 + idx];
+        out[(7 + i) * cstride] = ef * J - pd * (gp[i] - gc[i]);
+      }
+    }
+    return rest;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Pass X forward: assembly + R2C.  grid: x = y-chunk (RY rows), y = z plane.
+// ---------------------------------------------------------------------------
+template <typename T, int N, int MODE, int RY, int NT>
+__global__ __launch_bounds__(NT) void fft_x_r2c_kernel(SrcArgs<T> a, cplx<T>* spec, long comp_stride, int nhp,
+                                                       const cplx<T>* __restrict__ tw) {
+  constexpr int M = N / 2;
+  constexpr int NSRC = mode_nsrc(MODE);
+  constexpr int L = NSRC * RY;
+  __shared__ T sm[NSRC * RY * N];
+  __shared__ double red[NT];
+  const int y0 = blockIdx.x * RY, z = blockIdx.y;
+  const int tid = threadIdx.x;
+  // 1. assemble the sources of RY rows into LDS rows [c][r][x]
+  double acc[RY];
+#pragma unroll
+  for (int r = 0; r < RY; ++r) acc[r] = 0.0;
+  for (int p = tid; p < RY * N; p += NT) {
+    const int r = p / N, x = p % N;
+    const T s0 = assemble_point<T, MODE>(a, N, x, y0 + r, z, sm + r * N + x, RY * N);
+#pragma unroll
+    for (int rr = 0; rr < RY; ++rr)
+      if (rr == r) acc[rr] += (double)s0;
+  }
+  if (a.rowsum) {
+#pragma unroll
+    for (int r = 0; r < RY; ++r) {
+      red[tid] = acc[r];
+      __syncthreads();
+      for (int s = NT / 2; s > 0; s >>= 1) {
+        if (tid < s) red[tid] += red[tid + s];
+        __syncthreads();
+      }
+      if (tid == 0) a.rowsum[(long)z * N + y0 + r] = red[0];
+      __syncthreads();
+    }
+  } else {
+    __syncthreads();
+  }
+  // 2. half-length complex FFT of every row (pairs of reals are complex values)
+  cplx<T>* cs = reinterpret_cast<cplx<T>*>(sm);
+  row_stages<T, M, L, M, NT, 0, false>(cs, tw, 2);
+  // 3. post-process Z_k -> X_k (k = 0..M) and store the rows
+  for (int job = tid; job < L * (M + 1); job += NT) {
+    const int line = job / (M + 1), k = job % (M + 1);
+    const cplx<T> zk = cs[line * M + (k == M ? 0 : k)];
+    const cplx<T> zc = conj(cs[line * M + (k == 0 ? 0 : M - k)]);
+    const cplx<T> ev = scale(zk + zc, (T)0.5);
+    const cplx<T> od = scale(zk - zc, (T)0.5);  // = i * O_k
+    // X_k = E_k + W^k O_k with O_k = -i * od
+    const cplx<T> w = tw[k == M ? 0 : k];
+    const cplx<T> wk = (k == M) ? mk<T>(-1, 0) : w;
+    const cplx<T> o = mk(od.y, -od.x);
+    const cplx<T> xk = ev + cmul(wk, o);
+    const int c = line / RY, r = line % RY;
+    spec[c * comp_stride + ((long)z * N + (y0 + r)) * nhp + k] = xk;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Pass X inverse: C2R of NOUT components into separate real arrays.
+// ---------------------------------------------------------------------------
+template <typename T>
+struct OutPtrs {
+  T* p[8];
+};
+
+template <typename T, int N, int NOUT, int RY, int NT>
+__global__ __launch_bounds__(NT) void fft_x_c2r_kernel(const cplx<T>* spec, long comp_stride, int nhp, OutPtrs<T> out,
+                                                       T out_scale, const cplx<T>* __restrict__ tw) {
+  constexpr int M = N / 2;
+  constexpr int L = NOUT * RY;
+  __shared__ cplx<T> cs[L * M];
+  const int y0 = blockIdx.x * RY, z = blockIdx.y;
+  const int tid = threadIdx.x;
+  // 1. pre-process X_k -> Z_k = E_k + i O_k, E_k = X_k + conj X_{M-k}, O_k = (X_k - conj X_{M-k}) W^-k
+  for (int job = tid; job < L * M; job += NT) {
+    const int line = job / M, k = job % M;
+    const int c = line / RY, r = line % RY;
+    const cplx<T>* row = spec + c * comp_stride + ((long)z * N + (y0 + r)) * nhp;
+    cplx<T> xk = row[k];
+    cplx<T> xm = row[M - k];
+    if (k == 0) {
+      xk.y = 0;
+      xm.y = 0;
+    }
+    const cplx<T> xmc = conj(xm);
+    const cplx<T> ev = xk + xmc;
+    const cplx<T> od = cmulc(xk - xmc, tw[k]);
+    cs[line * M + k] = mk(ev.x - od.y, ev.y + od.x);
+  }
+  __syncthreads();
+  row_stages<T, M, L, M, NT, 0, true>(cs, tw, 2);
+  // 2. z_n = x_{2n} + i x_{2n+1}: the LDS row is the real output row
+  const T* rs = reinterpret_cast<const T*>(cs);
+  for (int job = tid; job < L * N; job += NT) {
+    const int line = job / N, x = job % N;
+    const int c = line / RY, r = line % RY;
+    out.p[c][((long)z * N + (y0 + r)) * N + x] = rs[line * N + x] * out_scale;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// host launchers
+// ---------------------------------------------------------------------------
+template <typename T, int N> constexpr int rows_per_block() {
+  constexpr int r = 4096 / (N * (int)sizeof(T));
+  return r < 1 ? 1 : (r > N ? N : r);
+}
+template <typename T> constexpr int col_tile() { return 128 / (int)sizeof(cplx<T>); }
+
+template <typename T, int N>
+static void launch_cols(cplx<T>* spec, int ncomp, bool inv, bool along_z, int nhp, const cplx<T>* tw, hipStream_t st) {
+  constexpr int C = col_tile<T>();
+  constexpr int NT = (N * C / 8 < 256) ? (N * C / 8 < 64 ? 64 : N * C / 8) : 256;
+  const long comp_stride = (long)N * N * nhp;
+  const int ncols = N / 2 + 1;
+  dim3 grid((ncols + C - 1) / C, N, ncomp);
+  const long es = along_z ? (long)N * nhp : (long)nhp;
+  const long os = along_z ? (long)nhp : (long)N * nhp;
+  if (inv)
+    hipLaunchKernelGGL((fft_cols_kernel<T, N, C, NT, true>), grid, dim3(NT), 0, st, spec, es, os, comp_stride, ncols, tw);
+  else
+    hipLaunchKernelGGL((fft_cols_kernel<T, N, C, NT, false>), grid, dim3(NT), 0, st, spec, es, os, comp_stride, ncols, tw);
+}
+
+template <typename T, int N>
+static void launch_r2c(const SrcArgs<T>& a, int mode, cplx<T>* spec, int nhp, const cplx<T>* tw, hipStream_t st) {
+  constexpr int RY = rows_per_block<T, N>();
+  constexpr int NT = 256;
+  const long comp_stride = (long)N * N * nhp;
+  dim3 grid(N / RY, N);
+  switch (mode) {
+    case MODE_RAW:
+      hipLaunchKernelGGL((fft_x_r2c_kernel<T, N, MODE_RAW, RY, NT>), grid, dim3(NT), 0, st, a, spec, comp_stride, nhp, tw);
+      break;
+    case MODE_NEWTONIAN:
+      hipLaunchKernelGGL((fft_x_r2c_kernel<T, N, MODE_NEWTONIAN, RY, NT>), grid, dim3(NT), 0, st, a, spec, comp_stride,
+                         nhp, tw);
+      break;
+    case MODE_SCALAR:
+      hipLaunchKernelGGL((fft_x_r2c_kernel<T, N, MODE_SCALAR, RY, NT>), grid, dim3(NT), 0, st, a, spec, comp_stride, nhp,
+                         tw);
+      break;
+    default:
+      hipLaunchKernelGGL((fft_x_r2c_kernel<T, N, MODE_FULL, RY, NT>), grid, dim3(NT), 0, st, a, spec, comp_stride, nhp,
+                         tw);
+      break;
+  }
+}
+
+template <typename T, int N, int NOUT>
+static void launch_c2r_n(const cplx<T>* spec, int nhp, const OutPtrs<T>& out, T scale_, const cplx<T>* tw,
+                         hipStream_t st) {
+  constexpr int RY0 = rows_per_block<T, N>();
+  constexpr int RY = (NOUT > 2 && RY0 > 1) ? RY0 / 2 : RY0;
+  constexpr int NT = 256;
+  const long comp_stride = (long)N * N * nhp;
+  dim3 grid(N / RY, N);
+  hipLaunchKernelGGL((fft_x_c2r_kernel<T, N, NOUT, RY, NT>), grid, dim3(NT), 0, st, spec, comp_stride, nhp, out, scale_,
+                     tw);
+}
+
+template <typename T, int N>
+static void launch_c2r(const cplx<T>* spec, int nhp, int nout, const OutPtrs<T>& out, T scale_, const cplx<T>* tw,
+                       hipStream_t st) {
+  switch (nout) {
+    case 1: launch_c2r_n<T, N, 1>(spec, nhp, out, scale_, tw, st); break;
+    case 2: launch_c2r_n<T, N, 2>(spec, nhp, out, scale_, tw, st); break;
+    case 3: launch_c2r_n<T, N, 3>(spec, nhp, out, scale_, tw, st); break;
+    case 5: launch_c2r_n<T, N, 5>(spec, nhp, out, scale_, tw, st); break;
+    default: launch_c2r_n<T, N, 6>(spec, nhp, out, scale_, tw, st); break;
+  }
+}
+
+#define GPM_FOR_EACH_N(X) X(16) X(32) X(64) X(128) X(256) X(512) X(1024)
+
+template <typename T>
+void fft_r2c_x(const SrcArgsH<T>& ah, int mode, int n, int nhp, cplx<T>* spec, const cplx<T>* tw, hipStream_t st) {
+  SrcArgs<T> a;
+  a.dep = ah.dep; a.phi1 = ah.phi1; a.phi2 = ah.phi2; a.chi1 = ah.chi1; a.raw = ah.raw; a.rowsum = ah.rowsum;
+  a.kap = (T)ah.kap; a.ebar = (T)ah.ebar; a.hc = (T)ah.hc; a.inv_dt = (T)ah.inv_dt; a.inv_dtl = (T)ah.inv_dtl;
+  a.half_n = (T)(0.5 * n);
+  switch (n) {
+#define X(NN) case NN: launch_r2c<T, NN>(a, mode, spec, nhp, tw, st); break;
+    GPM_FOR_EACH_N(X)
+#undef X
+  }
+}
+
+template <typename T>
+void fft_cols(int n, int nhp, cplx<T>* spec, int ncomp, bool inv, bool along_z, const cplx<T>* tw, hipStream_t st) {
+  switch (n) {
+#define X(NN) case NN: launch_cols<T, NN>(spec, ncomp, inv, along_z, nhp, tw, st); break;
+    GPM_FOR_EACH_N(X)
+#undef X
+  }
+}
+
+template <typename T>
+void fft_c2r_x(int n, int nhp, const cplx<T>* spec, int nout, T* const* outp, double out_scale, const cplx<T>* tw,
+               hipStream_t st) {
+  OutPtrs<T> o;
+  for (int i = 0; i < 8; ++i) o.p[i] = (i < nout) ? outp[i] : nullptr;
+  switch (n) {
+#define X(NN) case NN: launch_c2r<T, NN>(spec, nhp, nout, o, (T)out_scale, tw, st); break;
+    GPM_FOR_EACH_N(X)
+#undef X
+  }
+}
+
+template <typename T>
+void fft_forward(const SrcArgsH<T>& ah, int mode, int n, int nhp, cplx<T>* spec, int ncomp, const cplx<T>* tw,
+                 hipStream_t st) {
+  fft_r2c_x<T>(ah, mode, n, nhp, spec, tw, st);
+  fft_cols<T>(n, nhp, spec, ncomp, false, false, tw, st);
+  fft_cols<T>(n, nhp, spec, ncomp, false, true, tw, st);
+}
+
+template <typename T>
+void fft_inverse(int n, int nhp, cplx<T>* spec, int nout, T* const* outp, double out_scale, const cplx<T>* tw,
+                 hipStream_t st) {
+  fft_cols<T>(n, nhp, spec, nout, true, true, tw, st);
+  fft_cols<T>(n, nhp, spec, nout, true, false, tw, st);
+  fft_c2r_x<T>(n, nhp, spec, nout, outp, out_scale, tw, st);
+}
+
+#define GPM_FFT_INST(T)                                                                                          \
+  template void fft_r2c_x<T>(const SrcArgsH<T>&, int, int, int, cplx<T>*, const cplx<T>*, hipStream_t);          \
+  template void fft_cols<T>(int, int, cplx<T>*, int, bool, bool, const cplx<T>*, hipStream_t);                   \
+  template void fft_c2r_x<T>(int, int, const cplx<T>*, int, T* const*, double, const cplx<T>*, hipStream_t);      \
+  template void fft_forward<T>(const SrcArgsH<T>&, int, int, int, cplx<T>*, int, const cplx<T>*, hipStream_t);    \
+  template void fft_inverse<T>(int, int, cplx<T>*, int, T* const*, double, const cplx<T>*, hipStream_t);
+GPM_FFT_INST(float)
+GPM_FFT_INST(double)
+
+}  // namespace gpm

@@ -1,0 +1,104 @@
+// Host-side declarations of the PM kernels' launchers (one header for all .hip units).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "common.h"
+
+namespace gpm {
+
+// source assembly modes of the forward pass X
+enum { MODE_RAW = 0, MODE_NEWTONIAN = 1, MODE_SCALAR = 2, MODE_FULL = 3 };
+__host__ __device__ constexpr int mode_nsrc(int mode) {
+  return mode == MODE_FULL ? 10 : (mode == MODE_SCALAR ? 7 : 1);
+}
+
+// host-side (FP64) arguments of the forward transform with source assembly
+template <typename T>
+struct SrcArgsH {
+  const T* dep = nullptr;
+  const T* phi1 = nullptr;
+  const T* phi2 = nullptr;
+  const T* chi1 = nullptr;
+  const T* raw = nullptr;
+  double* rowsum = nullptr;
+  double kap = 0, ebar = 0, hc = 0, inv_dt = 0, inv_dtl = 0;
+};
+
+// ---- fft.hip ----
+template <typename T>
+void fft_r2c_x(const SrcArgsH<T>& a, int mode, int n, int nhp, cplx<T>* spec, const cplx<T>* tw, hipStream_t st);
+template <typename T>
+void fft_cols(int n, int nhp, cplx<T>* spec, int ncomp, bool inv, bool along_z, const cplx<T>* tw, hipStream_t st);
+template <typename T>
+void fft_c2r_x(int n, int nhp, const cplx<T>* spec, int nout, T* const* outp, double out_scale, const cplx<T>* tw,
+               hipStream_t st);
+template <typename T>
+void fft_forward(const SrcArgsH<T>& a, int mode, int n, int nhp, cplx<T>* spec, int ncomp, const cplx<T>* tw,
+                 hipStream_t st);
+template <typename T>
+void fft_inverse(int n, int nhp, cplx<T>* spec, int nout, T* const* outp, double out_scale, const cplx<T>* tw,
+                 hipStream_t st);
+
+// ---- solve.hip ----
+template <typename T>
+struct SolveArgs {
+  cplx<T>* spec;      // [comp][z][y][kx] sources in, solutions out
+  long comp_stride;   // complex values per component
+  int n, nhp;
+  int mode;           // MODE_NEWTONIAN / MODE_SCALAR / MODE_FULL
+  const T* kt;        // kt[m] = 2 n sin(pi m_signed / n), m = 0 .. n-1
+  double hc, inv_dt, ebar, inv_n3;
+  // FP64 homogeneous mode of the phi source: dc[0] = mesh sum of every term but E - ebar,
+  // dc[2] = sum over particles of e; k = 0 source = dc[0] + kap_a2 dc[2] - n3 ebar
+  const double* dc;
+  double kap_a2, n3_ebar;
+  double* phibar_out; // FP64 mean of the new phi (may be null)
+  // tensor state: polarisation amplitudes and their time derivatives
+  cplx<T>* hp; cplx<T>* hx; cplx<T>* pp; cplx<T>* px;
+  int tensor_op;      // 0: none, 1: reset to zero, 2: Crank-Nicolson step
+  double dtau, hc_half;
+};
+template <typename T> void launch_solve(const SolveArgs<T>& a, hipStream_t st);
+// rebuild the six h_ij half spectra from the polarisation state (diagnostic)
+template <typename T>
+void launch_tensor_components(cplx<T>* spec, long comp_stride, int n, int nhp, const T* kt, const cplx<T>* hp,
+                              const cplx<T>* hx, double inv_n3, hipStream_t st);
+void launch_sum_f64(const double* in, long count, double* out, hipStream_t st);
+void launch_sum_as_f64(const float* in, long count, double* out, hipStream_t st);
+
+// ---- particles.hip ----
+template <typename T>
+struct Particles {
+  double* px; double* py; double* pz;  // SoA positions
+  T* ux; T* uy; T* uz;                 // SoA momenta
+  uint32_t* id;
+};
+
+template <typename T>
+void launch_ingest(const double* pos_aos, const T* u_aos, const uint32_t* ids, long n, Particles<T> out, int nmesh,
+                   uint32_t* key, uint32_t* rank, uint32_t* cnt, int* err, hipStream_t st);
+template <typename T>
+void launch_deposit(const Particles<T>& p, const uint32_t* cell_start, int n, int ncomp, bool relativistic, double a,
+                    T* dep, double* esum_part, double* esum, hipStream_t st);
+template <typename T>
+struct GatherArgs {
+  const T* phi; const T* chi; const T* bx; const T* by; const T* bz;
+  int mode;
+  double dtau, a, a_half;
+};
+template <typename T>
+void launch_kick_drift(const Particles<T>& p, long np, int n, const GatherArgs<T>& g, uint32_t* key, uint32_t* rank,
+                       uint32_t* cnt, int* err, hipStream_t st);
+void launch_scan(uint32_t* cnt, uint32_t* cell_start, long ncell, uint32_t* block_sums, hipStream_t st);
+size_t scan_block_sums_count(long ncell);
+template <typename T>
+void launch_scatter(const Particles<T>& src, Particles<T> dst, long np, const uint32_t* key, const uint32_t* rank,
+                    const uint32_t* cell_start, hipStream_t st);
+template <typename T>
+void launch_export(const Particles<T>& p, long np, double* pos_aos, T* u_aos, uint32_t* ids, hipStream_t st);
+template <typename T>
+void launch_copy_unpad(const cplx<T>* spec, int n, int nhp, cplx<T>* out, bool to_padded, hipStream_t st);
+
+}  // namespace gpm

@@ -1,0 +1,184 @@
+"""Python binding of the PM library: same call names as the C ABI, argument marshalling only.
+
+PyTorch provides the device workspace and the stream; every step of the
+particle-mesh path runs in the library's HIP kernels.
+"""
+from __future__ import annotations
+
+import ctypes as C
+
+import numpy as np
+import torch
+
+from . import _lib as L
+
+_PHYS = {"newtonian": L.PM_NEWTONIAN, "scalar": L.PM_SCALAR, "full": L.PM_FULL}
+_PREC = {"fp32": L.PM_FP32, "fp64": L.PM_FP64}
+
+
+def make_config(n_mesh: int, n_particles: int, box_mpch: float, physics: str = "full", precision: str = "fp32",
+                timings: bool = False) -> L.PMConfig:
+    return L.PMConfig(n_mesh=n_mesh, precision=_PREC[precision], n_particles=n_particles, box_mpch=box_mpch,
+                      physics=_PHYS[physics], flags=L.PM_FLAG_TIMINGS if timings else 0)
+
+
+def query_workspace(cfg: L.PMConfig) -> int:
+    lib = L.load()
+    b = C.c_size_t(0)
+    L.check(lib.pm_query_workspace(C.byref(cfg), C.byref(b)), what="pm_query_workspace")
+    return int(b.value)
+
+
+def background(box_mpch: float, tau: float):
+    """(a, H_conf) of the library's Einstein-de Sitter background at conformal time tau."""
+    lib = L.load()
+    cfg = make_config(16, 1, box_mpch)
+    a, h = C.c_double(), C.c_double()
+    L.check(lib.pm_background(C.byref(cfg), tau, C.byref(a), C.byref(h)), what="pm_background")
+    return a.value, h.value
+
+
+def tau_of_a(box_mpch: float, a: float) -> float:
+    lib = L.load()
+    cfg = make_config(16, 1, box_mpch)
+    t = C.c_double()
+    L.check(lib.pm_tau_of_a(C.byref(cfg), a, C.byref(t)), what="pm_tau_of_a")
+    return t.value
+
+
+def _ptr(t: torch.Tensor) -> int:
+    return t.data_ptr()
+
+
+class PMContext:
+    """One particle-mesh simulation on one GPU (wraps pm_ctx)."""
+
+    def __init__(self, n_mesh: int, n_particles: int, box_mpch: float, physics: str = "full",
+                 precision: str = "fp32", timings: bool = False, device: str | torch.device = "cuda:0",
+                 stream: torch.cuda.Stream | None = None):
+        self.lib = L.load()
+        self.cfg = make_config(n_mesh, n_particles, box_mpch, physics, precision, timings)
+        self.n = n_mesh
+        self.np = n_particles
+        self.physics = physics
+        self.precision = precision
+        self.dtype = torch.float64 if precision == "fp64" else torch.float32
+        self.np_dtype = np.float64 if precision == "fp64" else np.float32
+        self.device = torch.device(device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self.ws_bytes = query_workspace(self.cfg)
+        self.workspace = torch.empty(self.ws_bytes, dtype=torch.uint8, device=self.device)
+        self.ctx = C.c_void_p()
+        L.check(self.lib.pm_create(C.byref(self.cfg), C.c_void_p(_ptr(self.workspace)), self.ws_bytes,
+                                   C.c_void_p(self.stream.cuda_stream), C.byref(self.ctx)), what="pm_create")
+
+    def close(self):
+        if self.ctx:
+            self.lib.pm_destroy(self.ctx)
+            self.ctx = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _chk(self, status, what):
+        L.check(status, self.ctx, what)
+
+    # -- the five calls of the boundary -----------------------------------
+    def init_particles(self, pos, u, tau0: float, ids=None):
+        """pos [n][3] float64, u [n][3] context precision; numpy (host) or CUDA tensors (device)."""
+        if isinstance(pos, torch.Tensor):
+            if not (pos.is_cuda and u.is_cuda):
+                raise ValueError("pos and u must both be device tensors or both numpy arrays")
+            pos = pos.to(torch.float64).contiguous()
+            u = u.to(self.dtype).contiguous()
+            idp = ids.to(torch.int32).contiguous() if ids is not None else None
+            self._keep = (pos, u, idp)
+            self._chk(self.lib.pm_init_particles(self.ctx, C.c_void_p(_ptr(pos)), C.c_void_p(_ptr(u)),
+                                                 C.c_void_p(_ptr(idp)) if idp is not None else None,
+                                                 pos.shape[0], tau0, 1), "pm_init_particles")
+        else:
+            pos = np.ascontiguousarray(pos, dtype=np.float64)
+            u = np.ascontiguousarray(u, dtype=self.np_dtype)
+            idh = np.ascontiguousarray(ids, dtype=np.uint32) if ids is not None else None
+            self._chk(self.lib.pm_init_particles(self.ctx, pos.ctypes.data, u.ctypes.data,
+                                                 idh.ctypes.data if idh is not None else None,
+                                                 pos.shape[0], tau0, 0), "pm_init_particles")
+
+    def deposit(self):
+        self._chk(self.lib.pm_deposit(self.ctx), "pm_deposit")
+
+    def solve_metric(self, dtau_prev: float):
+        self._chk(self.lib.pm_solve_metric(self.ctx, dtau_prev), "pm_solve_metric")
+
+    def update_particles(self, dtau: float):
+        self._chk(self.lib.pm_update_particles(self.ctx, dtau), "pm_update_particles")
+
+    def step(self, dtau: float):
+        self._chk(self.lib.pm_step(self.ctx, dtau), "pm_step")
+
+    # -- getters / setters -----------------------------------------------
+    def get_field(self, name: str, device: bool = False):
+        fid = L.FIELDS[name]
+        if device:
+            out = torch.empty((self.n,) * 3, dtype=self.dtype, device=self.device)
+            self._chk(self.lib.pm_get_field(self.ctx, fid, C.c_void_p(_ptr(out)), 1), "pm_get_field")
+            return out
+        out = np.empty((self.n,) * 3, dtype=self.np_dtype)
+        self._chk(self.lib.pm_get_field(self.ctx, fid, out.ctypes.data, 0), "pm_get_field")
+        return out
+
+    def set_field(self, name: str, arr):
+        fid = L.FIELDS[name]
+        if isinstance(arr, torch.Tensor):
+            t = arr.to(device=self.device, dtype=self.dtype).contiguous()
+            self._keep_field = t
+            self._chk(self.lib.pm_set_field(self.ctx, fid, C.c_void_p(_ptr(t)), 1), "pm_set_field")
+        else:
+            a = np.ascontiguousarray(arr, dtype=self.np_dtype)
+            assert a.size == self.n ** 3
+            self._chk(self.lib.pm_set_field(self.ctx, fid, a.ctypes.data, 0), "pm_set_field")
+
+    def get_particles(self, device: bool = False):
+        """(pos [n][3] float64, u [n][3]) in identifier order."""
+        if device:
+            pos = torch.empty((self.np, 3), dtype=torch.float64, device=self.device)
+            u = torch.empty((self.np, 3), dtype=self.dtype, device=self.device)
+            self._chk(self.lib.pm_get_particles(self.ctx, C.c_void_p(_ptr(pos)), C.c_void_p(_ptr(u)), None, 1),
+                      "pm_get_particles")
+            return pos, u
+        pos = np.empty((self.np, 3), dtype=np.float64)
+        u = np.empty((self.np, 3), dtype=self.np_dtype)
+        self._chk(self.lib.pm_get_particles(self.ctx, pos.ctypes.data, u.ctypes.data, None, 0), "pm_get_particles")
+        return pos, u
+
+    def time(self):
+        tau, a, steps = C.c_double(), C.c_double(), C.c_int64()
+        self._chk(self.lib.pm_get_time(self.ctx, C.byref(tau), C.byref(a), C.byref(steps)), "pm_get_time")
+        return tau.value, a.value, steps.value
+
+    def timings(self) -> dict:
+        """{stage: (total device ms, calls)} since the previous call; resets the counters."""
+        ms = (C.c_double * 8)()
+        calls = (C.c_int64 * 8)()
+        self._chk(self.lib.pm_get_timings(self.ctx, ms, calls, 8), "pm_get_timings")
+        return {name: (ms[i], calls[i]) for i, name in enumerate(L.STAGES)}
+
+    def sync(self):
+        self._chk(self.lib.pm_sync(self.ctx), "pm_sync")
+
+    def debug_fft(self, x: torch.Tensor, direction: int) -> torch.Tensor:
+        n = self.n
+        if direction == 1:
+            x = x.to(device=self.device, dtype=self.dtype).contiguous()
+            cdt = torch.complex128 if self.precision == "fp64" else torch.complex64
+            out = torch.empty((n, n, n // 2 + 1), dtype=cdt, device=self.device)
+        else:
+            cdt = torch.complex128 if self.precision == "fp64" else torch.complex64
+            x = x.to(device=self.device, dtype=cdt).contiguous()
+            out = torch.empty((n, n, n), dtype=self.dtype, device=self.device)
+        self._chk(self.lib.pm_debug_fft(self.ctx, C.c_void_p(_ptr(x)), C.c_void_p(_ptr(out)), direction),
+                  "pm_debug_fft")
+        return out

@@ -1,0 +1,60 @@
+"""Host-side checks of the C ABI (no GPU needed): the library loads, exports every declared
+function, validates its arguments and computes the host-only quantities."""
+import ctypes as C
+import math
+import os
+import re
+
+import pytest
+
+from paper_2607_17929_amd import _lib as L
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "pm.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(pm_[a-z_0-9]+)\s*\(", src)))
+
+
+def test_every_declared_function_is_exported():
+    lib = L.load()
+    names = _declared()
+    assert set(names) == set(L.EXPORTS)
+    for name in names:
+        assert hasattr(lib, name), name
+
+
+def test_query_workspace_and_validation():
+    lib = L.load()
+    cfg = L.PMConfig(n_mesh=64, precision=L.PM_FP32, n_particles=64 ** 3, box_mpch=256.0, physics=L.PM_FULL, flags=0)
+    b = C.c_size_t()
+    assert lib.pm_query_workspace(C.byref(cfg), C.byref(b)) == L.PM_OK
+    n3 = 64 ** 3
+    # at least: two particle buffers (40 B each), 10 deposits, 7 real fields, 10 + 4 half spectra
+    assert b.value > n3 * (2 * 40 + 4 * 17) + 14 * 64 * 64 * 33 * 8
+    bad = L.PMConfig(n_mesh=48, precision=L.PM_FP32, n_particles=10, box_mpch=256.0, physics=L.PM_FULL, flags=0)
+    assert lib.pm_query_workspace(C.byref(bad), C.byref(b)) == L.PM_ERANGE
+    bad.n_mesh = 2048
+    assert lib.pm_query_workspace(C.byref(bad), C.byref(b)) == L.PM_ERANGE
+    bad.n_mesh, bad.precision = 64, 7
+    assert lib.pm_query_workspace(C.byref(bad), C.byref(b)) == L.PM_EINVAL
+    ctx = C.c_void_p()
+    assert lib.pm_create(C.byref(cfg), None, 0, None, C.byref(ctx)) == L.PM_EWORKSPACE
+    assert lib.pm_create(C.byref(cfg), C.c_void_p(256), 16, None, C.byref(ctx)) == L.PM_EWORKSPACE
+    assert lib.pm_deposit(None) == L.PM_EINVAL
+    assert lib.pm_status_string(L.PM_ESTATE) == b"call out of order"
+
+
+def test_background_host_functions():
+    lib = L.load()
+    cfg = L.PMConfig(n_mesh=32, precision=L.PM_FP64, n_particles=1, box_mpch=320.0, physics=L.PM_SCALAR, flags=0)
+    tau = C.c_double()
+    assert lib.pm_tau_of_a(C.byref(cfg), 0.02, C.byref(tau)) == L.PM_OK
+    a, h = C.c_double(), C.c_double()
+    assert lib.pm_background(C.byref(cfg), tau.value, C.byref(a), C.byref(h)) == L.PM_OK
+    assert abs(a.value - 0.02) < 1e-15
+    # Einstein-de Sitter: H_conf = H0 / sqrt(a), H0 = box / (c / 100 km/s/Mpc)
+    assert abs(h.value - (320.0 / 2997.92458) / math.sqrt(0.02)) < 1e-12
+    assert lib.pm_background(C.byref(cfg), -1.0, C.byref(a), C.byref(h)) == L.PM_EINVAL
