@@ -6,7 +6,7 @@
 #include <string>
 #include <vector>
 
-#include "../../include/pm.h"
+#include "pm.h"
 #include "kernels.h"
 
 using namespace gpm;
@@ -56,7 +56,7 @@ Layout make_layout(const pm_config& c) {
   L.cell_start = take((n3 + 1) * 4);
   L.bsum = take(scan_block_sums_count(n3) * 4 + 64);
   L.dep = take(L.ndep * n3 * rs);
-  L.part = take((n3 / 1024 + 1) * 8);
+  L.part = take((n3 / 512 + 64) * 8);  // one FP64 partial per deposit block (16 x 8 x 4 vertices)
   for (int i = 0; i < 3; ++i) L.phi[i] = take(n3 * rs);
   L.chi = mode != MODE_NEWTONIAN ? take(n3 * rs) : 0;
   for (int i = 0; i < 3; ++i) L.b[i] = mode == MODE_FULL ? take(n3 * rs) : 0;
@@ -353,8 +353,8 @@ pm_status do_update(pm_ctx* c, double dtau) {
   g.a = c->a_of(c->tau);
   g.a_half = c->a_of(c->tau + 0.5 * dtau);
   c->stage_begin(PM_STAGE_KICK_DRIFT);
-  launch_kick_drift<T>(c->parts<T>(c->cur), c->np, c->n, g, c->at<uint32_t>(L.key), c->at<uint32_t>(L.rank),
-                       c->at<uint32_t>(L.cnt), c->at<int>(L.err), c->st);
+  launch_kick_drift<T>(c->parts<T>(c->cur), c->np, c->n, c->at<uint32_t>(L.cell_start), g, c->at<uint32_t>(L.key),
+                       c->at<uint32_t>(L.rank), c->at<uint32_t>(L.cnt), c->at<int>(L.err), c->st);
   c->stage_end(PM_STAGE_KICK_DRIFT);
   c->stage_begin(PM_STAGE_SORT);
   sort_particles<T>(c);

@@ -89,8 +89,8 @@ struct GatherArgs {
   double dtau, a, a_half;
 };
 template <typename T>
-void launch_kick_drift(const Particles<T>& p, long np, int n, const GatherArgs<T>& g, uint32_t* key, uint32_t* rank,
-                       uint32_t* cnt, int* err, hipStream_t st);
+void launch_kick_drift(const Particles<T>& p, long np, int n, const uint32_t* cell_start, const GatherArgs<T>& g,
+                       uint32_t* key, uint32_t* rank, uint32_t* cnt, int* err, hipStream_t st);
 void launch_scan(uint32_t* cnt, uint32_t* cell_start, long ncell, uint32_t* block_sums, hipStream_t st);
 size_t scan_block_sums_count(long ncell);
 template <typename T>

@@ -69,123 +69,146 @@ void launch_ingest(const double* pos_aos, const T* u_aos, const uint32_t* ids, l
 }
 
 // ---------------------------------------------------------------------------
-// CIC deposit, owner computes: one workgroup owns a TX x TY x TZ block of
-// vertices, accumulates in LDS every particle of the (TX+1)(TY+1)(TZ+1) cells
-// that touch it (found through cell_start: each cell row is two contiguous
-// particle ranges), and writes its block once with plain stores.  No global
-// atomics and no zero-fill of the mesh are needed.
+// CIC deposit without atomics.  A workgroup owns a TX x TY x TZ block of
+// vertices; the particles of the (TX+1)(TY+1)(TZ+1) cells touching it form
+// (TY+1)(TZ+1) cell rows, each two contiguous ranges of the cell-sorted store
+// (the cell below the block in x, then the block's own x-range).  They are
+// streamed through LDS in chunks (cell fractions, momenta, energy).  Each
+// thread owns whole vertices and sums, in registers, the contributions of the
+// particles of the vertex's 8 adjacent cells -- 4 contiguous ranges, one per
+// cell row -- over all chunks, then stores the 10 components once.
 // ---------------------------------------------------------------------------
-constexpr int DEP_TX = 16, DEP_TY = 8, DEP_TZ = 8, DEP_NT = 256;
-constexpr int DEP_MAXSEG = 2 * (DEP_TY + 1) * (DEP_TZ + 1);
+constexpr int DEP_TX = 16, DEP_TY = 8, DEP_TZ = 4, DEP_NT = 256;
+constexpr int DEP_ROWS = (DEP_TY + 1) * (DEP_TZ + 1);
+constexpr int DEP_CX = DEP_TX + 1;
+constexpr int DEP_NV = DEP_TX * DEP_TY * DEP_TZ;
+constexpr int DEP_VPT = DEP_NV / DEP_NT;  // vertices per thread
+static_assert(DEP_NV % DEP_NT == 0, "whole vertices per thread");
+
+template <typename T> constexpr int dep_capacity() { return sizeof(T) == 4 ? 1024 : 512; }
 
 template <typename T, int NC, bool REL>
 __global__ __launch_bounds__(DEP_NT) void deposit_kernel(Particles<T> p, const uint32_t* __restrict__ cell_start, int n,
                                                          T a, T* __restrict__ dep, double* __restrict__ esum) {
-  extern __shared__ __align__(16) unsigned char dsm[];
-  T* acc = reinterpret_cast<T*>(dsm);  // [NC][TZ][TY][TX]
-  __shared__ uint32_t seg_begin[DEP_MAXSEG];
-  __shared__ uint32_t seg_off[DEP_MAXSEG + 1];
-  __shared__ unsigned char seg_own[DEP_MAXSEG];
+  constexpr int CAP = dep_capacity<T>();
+  constexpr int TX = DEP_TX, TY = DEP_TY, TZ = DEP_TZ, CX = DEP_CX, ROWS = DEP_ROWS, GW = TX + 3;
+  __shared__ T sfx[CAP], sfy[CAP], sfz[CAP], sux[CAP], suy[CAP], suz[CAP], se[CAP];
+  __shared__ uint32_t cstart[ROWS * CX];  // row-relative staged start of local cell (row, lx); lx = 0 is cell x0 - 1
+  __shared__ uint32_t gcs[ROWS * GW];     // halo start/end, then starts of cells x0 .. x0 + TX
+  __shared__ uint32_t row_off[ROWS + 1];
   __shared__ double red[DEP_NT];
-  const int TX = min(DEP_TX, n), TY = min(DEP_TY, n), TZ = min(DEP_TZ, n);
-  const int nv = TX * TY * TZ;
+  const int m = n - 1;
   const int x0 = blockIdx.x * TX, y0 = blockIdx.y * TY, z0 = blockIdx.z * TZ;
   const int tid = threadIdx.x;
-  const int m = n - 1;
-  for (int i = tid; i < NC * nv; i += DEP_NT) acc[i] = (T)0;
-  // segment table: rows (cy, cz) of cells touching the block
-  const int ry = (TY == n) ? TY : TY + 1, ry0 = (TY == n) ? y0 : y0 - 1;
-  const int rz = (TZ == n) ? TZ : TZ + 1, rz0 = (TZ == n) ? z0 : z0 - 1;
-  const bool halo_x = (TX != n);
-  const int nrow = ry * rz;
-  const int nseg = nrow * 2;
-  if (tid < nseg) {
-    const int row = tid >> 1, part = tid & 1;
-    const int cy = (ry0 + row % ry) & m, cz = (rz0 + row / ry) & m;
-    const uint32_t rowbase = ((uint32_t)cz * n + cy) * (uint32_t)n;
-    uint32_t b, e;
-    if (part == 0) {  // the halo cell x0 - 1
-      if (halo_x) {
-        const uint32_t c = rowbase + ((x0 - 1) & m);
-        b = cell_start[c];
-        e = cell_start[c + 1];
-      } else {
-        b = e = 0;
-      }
-    } else {  // cells x0 .. x0 + TX - 1
-      b = cell_start[rowbase + x0];
-      e = cell_start[rowbase + x0 + TX];
-    }
-    seg_begin[tid] = b;
-    seg_off[tid + 1] = e - b;
-    // particles of the block's own cells are counted once in the FP64 energy sum
-    const bool own_y = (ry == TY) || (row % ry) != 0;
-    const bool own_z = (rz == TZ) || (row / ry) != 0;
-    seg_own[tid] = (part == 1 && own_y && own_z) ? 1 : 0;
+  // 1. cell_start values of every touching cell, read in parallel.  Local cell (lx, ly, lz) is
+  //    global (x0 - 1 + lx, y0 - 1 + ly, z0 - 1 + lz); on a 16^3 mesh the block spans x and the
+  //    first and last local x-layers are the same cells, but each vertex reads each cell once.
+  for (int q = tid; q < ROWS * GW; q += DEP_NT) {
+    const int r = q / GW, j = q % GW;
+    const int ly = r % (TY + 1), lz = r / (TY + 1);
+    const int cy = (y0 - 1 + ly) & m, cz = (z0 - 1 + lz) & m;
+    const uint32_t rb = ((uint32_t)cz * n + cy) * (uint32_t)n;
+    const uint32_t hc = rb + ((x0 - 1) & m);
+    gcs[q] = cell_start[j == 0 ? hc : (j == 1 ? hc + 1 : rb + x0 + (j - 2))];
   }
   __syncthreads();
+  for (int q = tid; q < ROWS * CX; q += DEP_NT) {
+    const int r = q / CX, lx = q % CX;
+    const uint32_t* g = gcs + r * GW;
+    cstart[q] = (lx == 0) ? 0u : (g[1] - g[0]) + (g[lx + 1] - g[2]);
+  }
   if (tid == 0) {
-    uint32_t s = 0;
-    seg_off[0] = 0;
-    for (int i = 1; i <= nseg; ++i) {
-      s += seg_off[i];
-      seg_off[i] = s;
+    uint32_t acc = 0;
+    row_off[0] = 0;
+    for (int r = 0; r < ROWS; ++r) {
+      const uint32_t* g = gcs + r * GW;
+      acc += (g[1] - g[0]) + (g[TX + 2] - g[2]);
+      row_off[r + 1] = acc;
     }
   }
   __syncthreads();
-  const uint32_t total = seg_off[nseg];
+  const uint32_t total = row_off[ROWS];
+  // 2. accumulate chunk by chunk
+  T acc[DEP_VPT][NC];
+#pragma unroll
+  for (int k = 0; k < DEP_VPT; ++k)
+#pragma unroll
+    for (int c = 0; c < NC; ++c) acc[k][c] = (T)0;
   const double ad = (double)a;
   double e_own = 0.0;
-  for (uint32_t i = tid; i < total; i += DEP_NT) {
-    // segment containing flattened index i
-    int lo = 0, hi = nseg;  // seg_off[lo] <= i < seg_off[hi]
-    while (hi - lo > 1) {
-      const int mid = (lo + hi) >> 1;
-      if (seg_off[mid] <= i) lo = mid; else hi = mid;
-    }
-    const uint32_t pi = seg_begin[lo] + (i - seg_off[lo]);
-    int ix, iy, iz;
-    double fxd, fyd, fzd;
-    cell_of(p.px[pi], n, ix, fxd);
-    cell_of(p.py[pi], n, iy, fyd);
-    cell_of(p.pz[pi], n, iz, fzd);
-    const T fx = (T)fxd, fy = (T)fyd, fz = (T)fzd;
-    T q[NC];
-    if constexpr (NC == 1) {
-      q[0] = a;
-    } else {
-      const T ux = p.ux[pi], uy = p.uy[pi], uz = p.uz[pi];
-      const T e = REL ? sqrt(a * a + ux * ux + uy * uy + uz * uz) : a;
-      const T ie = (T)1 / e;
-      q[0] = e; q[1] = ux; q[2] = uy; q[3] = uz;
-      q[4] = ux * ux * ie; q[5] = ux * uy * ie; q[6] = ux * uz * ie;
-      q[7] = uy * uy * ie; q[8] = uy * uz * ie; q[9] = uz * uz * ie;
-      if (seg_own[lo]) {
-        const double dx = ux, dy = uy, dz = uz;
-        e_own += REL ? sqrt(ad * ad + dx * dx + dy * dy + dz * dz) : ad;
+  for (uint32_t c0 = 0; c0 < total; c0 += CAP) {
+    const uint32_t c1 = min(total, c0 + (uint32_t)CAP);
+    int r = 0;
+    for (uint32_t i = c0 + tid; i < c1; i += DEP_NT) {
+      while (row_off[r + 1] <= i) ++r;
+      const uint32_t k = i - row_off[r];
+      const uint32_t* g = gcs + r * GW;
+      const uint32_t halo_n = g[1] - g[0];
+      const uint32_t gi = (k < halo_n) ? g[0] + k : g[2] + (k - halo_n);
+      const double sx = p.px[gi] * (double)n, sy = p.py[gi] * (double)n, sz = p.pz[gi] * (double)n;
+      const uint32_t l = i - c0;
+      sfx[l] = (T)(sx - floor(sx));
+      sfy[l] = (T)(sy - floor(sy));
+      sfz[l] = (T)(sz - floor(sz));
+      if constexpr (NC > 1) {
+        const T ux = p.ux[gi], uy = p.uy[gi], uz = p.uz[gi];
+        sux[l] = ux; suy[l] = uy; suz[l] = uz;
+        se[l] = REL ? sqrt(a * a + ux * ux + uy * uy + uz * uz) : a;
       }
     }
-    const T wx[2] = {(T)1 - fx, fx}, wy[2] = {(T)1 - fy, fy}, wz[2] = {(T)1 - fz, fz};
+    __syncthreads();
 #pragma unroll
-    for (int cz = 0; cz < 2; ++cz) {
-      const int lz = (iz + cz - z0) & m;
-      if (lz >= TZ) continue;
+    for (int k = 0; k < DEP_VPT; ++k) {
+      const int v = tid + k * DEP_NT;
+      const int lvx = v % TX, lvy = (v / TX) % TY, lvz = v / (TX * TY);
 #pragma unroll
-      for (int cy = 0; cy < 2; ++cy) {
-        const int ly = (iy + cy - y0) & m;
-        if (ly >= TY) continue;
-        const T wyz = wy[cy] * wz[cz];
+      for (int dz = 0; dz < 2; ++dz) {
 #pragma unroll
-        for (int cx = 0; cx < 2; ++cx) {
-          const int lx = (ix + cx - x0) & m;
-          if (lx >= TX) continue;
-          const T w = wx[cx] * wyz;
-          const int v = (lz * TY + ly) * TX + lx;
-#pragma unroll
-          for (int c = 0; c < NC; ++c) atomicAdd(&acc[c * nv + v], w * q[c]);
+        for (int dy = 0; dy < 2; ++dy) {
+          // cell row (lvy + dy, lvz + dz); dy = 0 is the row below the vertex (vertex = upper y corner)
+          const int rr = (lvz + dz) * (TY + 1) + (lvy + dy);
+          const int cb = rr * CX + lvx;  // cell below the vertex in x (vertex = its upper x corner)
+          const uint32_t ro = row_off[rr];
+          const uint32_t s1 = ro + cstart[cb + 1];
+          const uint32_t s2 = ro + ((lvx + 2 <= TX) ? cstart[cb + 2] : row_off[rr + 1] - ro);
+          const uint32_t b = max(ro + cstart[cb], c0), e = min(s2, c1);
+          const bool own = dy == 1 && dz == 1;
+          for (uint32_t i = b; i < e; ++i) {
+            const uint32_t l = i - c0;
+            const bool upper_x = i < s1;
+            const T fx = sfx[l];
+            const T wx = upper_x ? fx : (T)1 - fx;
+            const T wy = dy == 0 ? sfy[l] : (T)1 - sfy[l];
+            const T wz = dz == 0 ? sfz[l] : (T)1 - sfz[l];
+            const T w = wx * wy * wz;
+            if constexpr (NC == 1) {
+              acc[k][0] += w * a;
+            } else {
+              const T ux = sux[l], uy = suy[l], uz = suz[l], e_p = se[l];
+              const T wi = w / e_p;
+              acc[k][0] += w * e_p; acc[k][1] += w * ux; acc[k][2] += w * uy; acc[k][3] += w * uz;
+              acc[k][4] += wi * ux * ux; acc[k][5] += wi * ux * uy; acc[k][6] += wi * ux * uz;
+              acc[k][7] += wi * uy * uy; acc[k][8] += wi * uy * uz; acc[k][9] += wi * uz * uz;
+              if (own && !upper_x) {
+                const double dx = ux, dy2 = uy, dz2 = uz;
+                e_own += REL ? sqrt(ad * ad + dx * dx + dy2 * dy2 + dz2 * dz2) : ad;
+              }
+            }
+          }
         }
       }
     }
+    __syncthreads();
+  }
+  // 3. store the block's vertices (consecutive threads -> consecutive x)
+  const long n3 = (long)n * n * n;
+#pragma unroll
+  for (int k = 0; k < DEP_VPT; ++k) {
+    const int v = tid + k * DEP_NT;
+    const int lvx = v % TX, lvy = (v / TX) % TY, lvz = v / (TX * TY);
+    const long o = ((long)(z0 + lvz) * n + (y0 + lvy)) * n + (x0 + lvx);
+#pragma unroll
+    for (int c = 0; c < NC; ++c) dep[c * n3 + o] = acc[k][c];
   }
   if (esum) {
     red[tid] = e_own;
@@ -196,51 +219,48 @@ __global__ __launch_bounds__(DEP_NT) void deposit_kernel(Particles<T> p, const u
     }
     if (tid == 0) esum[(blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x] = red[0];
   }
-  __syncthreads();
-  const long n3 = (long)n * n * n;
-  for (int i = tid; i < NC * nv; i += DEP_NT) {
-    const int c = i / nv, v = i % nv;
-    const int lx = v % TX, ly = (v / TX) % TY, lz = v / (TX * TY);
-    dep[c * n3 + ((long)(z0 + lz) * n + (y0 + ly)) * n + (x0 + lx)] = acc[i];
-  }
 }
 
 template <typename T>
 void launch_deposit(const Particles<T>& p, const uint32_t* cell_start, int n, int ncomp, bool relativistic, double a,
                     T* dep, double* esum_part, double* esum, hipStream_t st) {
-  const int TX = n < DEP_TX ? n : DEP_TX, TY = n < DEP_TY ? n : DEP_TY, TZ = n < DEP_TZ ? n : DEP_TZ;
-  dim3 grid(n / TX, n / TY, n / TZ);
-  const size_t shm = (size_t)ncomp * TX * TY * TZ * sizeof(T);
-  // the FP64 accumulator (80 KB) exceeds the default dynamic LDS limit
-  (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&deposit_kernel<T, 1, false>),
-                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
-  (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&deposit_kernel<T, 10, true>),
-                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
-  (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&deposit_kernel<T, 10, false>),
-                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+  dim3 grid(n / DEP_TX, n / DEP_TY, n / DEP_TZ);  // n >= 16
   if (ncomp == 1) {
-    hipLaunchKernelGGL((deposit_kernel<T, 1, false>), grid, dim3(DEP_NT), shm, st, p, cell_start, n, (T)a, dep,
+    hipLaunchKernelGGL((deposit_kernel<T, 1, false>), grid, dim3(DEP_NT), 0, st, p, cell_start, n, (T)a, dep,
                        (double*)nullptr);
     return;
   }
   if (relativistic)
-    hipLaunchKernelGGL((deposit_kernel<T, 10, true>), grid, dim3(DEP_NT), shm, st, p, cell_start, n, (T)a, dep,
+    hipLaunchKernelGGL((deposit_kernel<T, 10, true>), grid, dim3(DEP_NT), 0, st, p, cell_start, n, (T)a, dep,
                        esum_part);
   else
-    hipLaunchKernelGGL((deposit_kernel<T, 10, false>), grid, dim3(DEP_NT), shm, st, p, cell_start, n, (T)a, dep,
+    hipLaunchKernelGGL((deposit_kernel<T, 10, false>), grid, dim3(DEP_NT), 0, st, p, cell_start, n, (T)a, dep,
                        esum_part);
   launch_sum_f64(esum_part, (long)grid.x * grid.y * grid.z, esum, st);
 }
 
 // ---------------------------------------------------------------------------
-// gather + kick + drift + new key.  Fields at x^n, CIC-interpolated together
-// with their centred-difference gradients (the interpolation of the vertex
-// gradients, written out per corner).
+// gather + kick + drift + new key.  A workgroup takes the particles of a
+// TX x TY x TZ block of cells (TY*TZ contiguous row ranges of the sorted
+// store) and first copies the fields it needs -- the block's vertices plus a
+// margin of one below and two above, enough for the centred differences at
+// the 8 corners of every cell -- into LDS.  Each particle then interpolates
+// phi, chi, B and their centred-difference gradients from LDS (the CIC
+// interpolation of the vertex gradients, written out per corner), kicks, drifts
+// and computes its new cell key and its rank inside that cell.
 // ---------------------------------------------------------------------------
+constexpr int KD_TX = 16, KD_TY = 8, KD_TZ = 4, KD_NT = 256;
+constexpr int KD_GX = KD_TX + 3, KD_GY = KD_TY + 3, KD_GZ = KD_TZ + 3;
+constexpr int KD_G = KD_GX * KD_GY * KD_GZ;
+
 template <typename T>
-__device__ __forceinline__ void gather_one(const T* __restrict__ f, const long* zo, const long* yo, const int* xo,
-                                           const T* wx, const T* wy, const T* wz, T half_n, T& val, T* g) {
+__device__ __forceinline__ void gather_lds(const T* __restrict__ f, int zo0, int yo0, int xo0, const T* wx, const T* wy,
+                                           const T* wz, T half_n, T& val, T* g) {
+  // f: LDS tile with x stride 1, y stride KD_GX, z stride KD_GX*KD_GY whose index 0 is the vertex one
+  // below the block in every axis; (xo0, yo0, zo0) = the particle's cell relative to the block, so the
+  // cell's lower corner is tile index (xo0 + 1, yo0 + 1, zo0 + 1)
   T v = 0, gx = 0, gy = 0, gz = 0;
+  constexpr int SY = KD_GX, SZ = KD_GX * KD_GY;
 #pragma unroll
   for (int cz = 0; cz < 2; ++cz) {
 #pragma unroll
@@ -248,12 +268,11 @@ __device__ __forceinline__ void gather_one(const T* __restrict__ f, const long* 
 #pragma unroll
       for (int cx = 0; cx < 2; ++cx) {
         const T w = wx[cx] * wy[cy] * wz[cz];
-        const int X = cx + 1, Y = cy + 1, Z = cz + 1;
-        const long zy = zo[Z] + yo[Y];
-        v += w * f[zy + xo[X]];
-        gx += w * (f[zy + xo[X + 1]] - f[zy + xo[X - 1]]);
-        gy += w * (f[zo[Z] + yo[Y + 1] + xo[X]] - f[zo[Z] + yo[Y - 1] + xo[X]]);
-        gz += w * (f[zo[Z + 1] + yo[Y] + xo[X]] - f[zo[Z - 1] + yo[Y] + xo[X]]);
+        const int b = (zo0 + cz + 1) * SZ + (yo0 + cy + 1) * SY + (xo0 + cx + 1);
+        v += w * f[b];
+        gx += w * (f[b + 1] - f[b - 1]);
+        gy += w * (f[b + SY] - f[b - SY]);
+        gz += w * (f[b + SZ] - f[b - SZ]);
       }
     }
   }
@@ -264,90 +283,124 @@ __device__ __forceinline__ void gather_one(const T* __restrict__ f, const long* 
 }
 
 template <typename T, int MODE>
-__global__ __launch_bounds__(256) void kick_drift_kernel(Particles<T> p, long np, int n, GatherArgs<T> ga,
-                                                         uint32_t* key, uint32_t* rank, uint32_t* cnt, int* err) {
-  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= np) return;
+__global__ __launch_bounds__(KD_NT) void kick_drift_kernel(Particles<T> p, const uint32_t* __restrict__ cell_start, int n,
+                                                           GatherArgs<T> ga, uint32_t* key, uint32_t* rank,
+                                                           uint32_t* cnt, int* err) {
+  constexpr int NF = MODE == MODE_FULL ? 5 : (MODE == MODE_SCALAR ? 2 : 1);
+  __shared__ T tile[NF][KD_G];
+  __shared__ uint32_t rbeg[KD_TY * KD_TZ], roff[KD_TY * KD_TZ + 1];
   const int m = n - 1;
-  double x = p.px[i], y = p.py[i], z = p.pz[i];
-  int ix, iy, iz;
-  double fxd, fyd, fzd;
-  cell_of(x, n, ix, fxd);
-  cell_of(y, n, iy, fyd);
-  cell_of(z, n, iz, fzd);
-  const T wx[2] = {(T)1 - (T)fxd, (T)fxd}, wy[2] = {(T)1 - (T)fyd, (T)fyd}, wz[2] = {(T)1 - (T)fzd, (T)fzd};
+  const int x0 = blockIdx.x * KD_TX, y0 = blockIdx.y * KD_TY, z0 = blockIdx.z * KD_TZ;
+  const int tid = threadIdx.x;
   const long nn = (long)n * n;
-  const long zo[4] = {((iz - 1) & m) * nn, iz * nn, ((iz + 1) & m) * nn, ((iz + 2) & m) * nn};
-  const long yo[4] = {(long)((iy - 1) & m) * n, (long)iy * n, (long)((iy + 1) & m) * n, (long)((iy + 2) & m) * n};
-  const int xo[4] = {(ix - 1) & m, ix, (ix + 1) & m, (ix + 2) & m};
+  // particle rows of the block
+  if (tid < KD_TY * KD_TZ) {
+    const int ly = tid % KD_TY, lz = tid / KD_TY;
+    const long rb = ((long)(z0 + lz) * n + (y0 + ly)) * n;
+    const uint32_t b = cell_start[rb + x0], e = cell_start[rb + x0 + KD_TX];
+    rbeg[tid] = b;
+    roff[tid + 1] = e - b;
+  }
+  // field tile with periodic wrap: local (gx, gy, gz) <-> global (x0 - 1 + gx, ...)
+  const T* src[5] = {ga.phi, ga.chi, ga.bx, ga.by, ga.bz};
+  for (int q = tid; q < KD_G; q += KD_NT) {
+    const int gx = q % KD_GX, gy = (q / KD_GX) % KD_GY, gz = q / (KD_GX * KD_GY);
+    const long o = (long)((z0 - 1 + gz) & m) * nn + (long)((y0 - 1 + gy) & m) * n + ((x0 - 1 + gx) & m);
+#pragma unroll
+    for (int f = 0; f < NF; ++f) tile[f][q] = src[f][o];
+  }
+  __syncthreads();
+  if (tid == 0) {
+    roff[0] = 0;
+    for (int r = 1; r <= KD_TY * KD_TZ; ++r) roff[r] += roff[r - 1];
+  }
+  __syncthreads();
+  const uint32_t total = roff[KD_TY * KD_TZ];
   const T hn = (T)(0.5 * n);
-  T phi_p, gphi[3];
-  gather_one(ga.phi, zo, yo, xo, wx, wy, wz, hn, phi_p, gphi);
-  T ux = p.ux[i], uy = p.uy[i], uz = p.uz[i];
   const T dt = (T)ga.dtau;
   const T a = (T)ga.a, ah = (T)ga.a_half;
-  T vx, vy, vz;
-  if constexpr (MODE == MODE_NEWTONIAN) {
-    ux -= dt * a * gphi[0];
-    uy -= dt * a * gphi[1];
-    uz -= dt * a * gphi[2];
-    const T ia = (T)1 / ah;
-    vx = ux * ia; vy = uy * ia; vz = uz * ia;
-  } else {
-    T chi_p, gchi[3];
-    gather_one(ga.chi, zo, yo, xo, wx, wy, wz, hn, chi_p, gchi);
-    const T u2 = ux * ux + uy * uy + uz * uz;
-    const T e = sqrt(a * a + u2);
-    const T cphi = -(a * a + (T)2 * u2) / e;
-    T fx = cphi * gphi[0] + e * gchi[0];
-    T fy = cphi * gphi[1] + e * gchi[1];
-    T fz = cphi * gphi[2] + e * gchi[2];
-    T B[3] = {0, 0, 0};
-    if constexpr (MODE == MODE_FULL) {
-      T gb[3][3];  // gb[j][i] = d_i B_j
-      gather_one(ga.bx, zo, yo, xo, wx, wy, wz, hn, B[0], gb[0]);
-      gather_one(ga.by, zo, yo, xo, wx, wy, wz, hn, B[1], gb[1]);
-      gather_one(ga.bz, zo, yo, xo, wx, wy, wz, hn, B[2], gb[2]);
-      fx -= ux * gb[0][0] + uy * gb[1][0] + uz * gb[2][0];
-      fy -= ux * gb[0][1] + uy * gb[1][1] + uz * gb[2][1];
-      fz -= ux * gb[0][2] + uy * gb[1][2] + uz * gb[2][2];
+  int r = 0;
+  for (uint32_t i = tid; i < total; i += KD_NT) {
+    while (roff[r + 1] <= i) ++r;  // i increases, so the row index only moves forward
+    const uint32_t pi = rbeg[r] + (i - roff[r]);
+    double x = p.px[pi], y = p.py[pi], z = p.pz[pi];
+    int ix, iy, iz;
+    double fxd, fyd, fzd;
+    cell_of(x, n, ix, fxd);
+    cell_of(y, n, iy, fyd);
+    cell_of(z, n, iz, fzd);
+    const T wx[2] = {(T)1 - (T)fxd, (T)fxd}, wy[2] = {(T)1 - (T)fyd, (T)fyd}, wz[2] = {(T)1 - (T)fzd, (T)fzd};
+    const int lx = ix - x0, ly = iy - y0, lz = iz - z0;  // in [0, T*) by construction of the rows
+    T phi_p, gphi[3];
+    gather_lds(tile[0], lz, ly, lx, wx, wy, wz, hn, phi_p, gphi);
+    T ux = p.ux[pi], uy = p.uy[pi], uz = p.uz[pi];
+    T vx, vy, vz;
+    if constexpr (MODE == MODE_NEWTONIAN) {
+      ux -= dt * a * gphi[0];
+      uy -= dt * a * gphi[1];
+      uz -= dt * a * gphi[2];
+      const T ia = (T)1 / ah;
+      vx = ux * ia; vy = uy * ia; vz = uz * ia;
+    } else {
+      T chi_p, gchi[3];
+      gather_lds(tile[1], lz, ly, lx, wx, wy, wz, hn, chi_p, gchi);
+      const T u2 = ux * ux + uy * uy + uz * uz;
+      const T e = sqrt(a * a + u2);
+      const T cphi = -(a * a + (T)2 * u2) / e;
+      T fx = cphi * gphi[0] + e * gchi[0];
+      T fy = cphi * gphi[1] + e * gchi[1];
+      T fz = cphi * gphi[2] + e * gchi[2];
+      T B[3] = {0, 0, 0};
+      if constexpr (MODE == MODE_FULL) {
+        T gb[3][3];  // gb[j][i] = d_i B_j
+        gather_lds(tile[2 % NF], lz, ly, lx, wx, wy, wz, hn, B[0], gb[0]);
+        gather_lds(tile[3 % NF], lz, ly, lx, wx, wy, wz, hn, B[1], gb[1]);
+        gather_lds(tile[4 % NF], lz, ly, lx, wx, wy, wz, hn, B[2], gb[2]);
+        fx -= ux * gb[0][0] + uy * gb[1][0] + uz * gb[2][0];
+        fy -= ux * gb[0][1] + uy * gb[1][1] + uz * gb[2][1];
+        fz -= ux * gb[0][2] + uy * gb[1][2] + uz * gb[2][2];
+      }
+      ux += dt * fx;
+      uy += dt * fy;
+      uz += dt * fz;
+      const T v2 = ux * ux + uy * uy + uz * uz;
+      const T eh2 = ah * ah + v2;
+      const T ieh = (T)1 / sqrt(eh2);
+      const T fac = ((T)1 + ((T)3 - v2 / eh2) * phi_p - chi_p) * ieh;
+      vx = ux * fac + B[0];
+      vy = uy * fac + B[1];
+      vz = uz * fac + B[2];
     }
-    ux += dt * fx;
-    uy += dt * fy;
-    uz += dt * fz;
-    const T v2 = ux * ux + uy * uy + uz * uz;
-    const T eh2 = ah * ah + v2;
-    const T ieh = (T)1 / sqrt(eh2);
-    const T fac = ((T)1 + ((T)3 - v2 / eh2) * phi_p - chi_p) * ieh;
-    vx = ux * fac + B[0];
-    vy = uy * fac + B[1];
-    vz = uz * fac + B[2];
+    x += ga.dtau * (double)vx;
+    y += ga.dtau * (double)vy;
+    z += ga.dtau * (double)vz;
+    if (!(isfinite(x) && isfinite(y) && isfinite(z))) {
+      atomicOr(err, 1);
+      x = y = z = 0.0;
+    }
+    x = wrap01(x); y = wrap01(y); z = wrap01(z);
+    p.px[pi] = x; p.py[pi] = y; p.pz[pi] = z;
+    p.ux[pi] = ux; p.uy[pi] = uy; p.uz[pi] = uz;
+    const uint32_t k = cell_key(x, y, z, n);
+    key[pi] = k;
+    rank[pi] = atomicAdd(&cnt[k], 1u);
   }
-  x += ga.dtau * (double)vx;
-  y += ga.dtau * (double)vy;
-  z += ga.dtau * (double)vz;
-  if (!(isfinite(x) && isfinite(y) && isfinite(z))) {
-    atomicOr(err, 1);
-    x = y = z = 0.0;
-  }
-  x = wrap01(x); y = wrap01(y); z = wrap01(z);
-  p.px[i] = x; p.py[i] = y; p.pz[i] = z;
-  p.ux[i] = ux; p.uy[i] = uy; p.uz[i] = uz;
-  const uint32_t k = cell_key(x, y, z, n);
-  key[i] = k;
-  rank[i] = atomicAdd(&cnt[k], 1u);
 }
 
 template <typename T>
-void launch_kick_drift(const Particles<T>& p, long np, int n, const GatherArgs<T>& g, uint32_t* key, uint32_t* rank,
-                       uint32_t* cnt, int* err, hipStream_t st) {
-  dim3 grid((unsigned)((np + 255) / 256));
+void launch_kick_drift(const Particles<T>& p, long np, int n, const uint32_t* cell_start, const GatherArgs<T>& g,
+                       uint32_t* key, uint32_t* rank, uint32_t* cnt, int* err, hipStream_t st) {
+  (void)np;
+  dim3 grid(n / KD_TX, n / KD_TY, n / KD_TZ);
   if (g.mode == MODE_NEWTONIAN)
-    hipLaunchKernelGGL((kick_drift_kernel<T, MODE_NEWTONIAN>), grid, dim3(256), 0, st, p, np, n, g, key, rank, cnt, err);
+    hipLaunchKernelGGL((kick_drift_kernel<T, MODE_NEWTONIAN>), grid, dim3(KD_NT), 0, st, p, cell_start, n, g, key, rank,
+                       cnt, err);
   else if (g.mode == MODE_SCALAR)
-    hipLaunchKernelGGL((kick_drift_kernel<T, MODE_SCALAR>), grid, dim3(256), 0, st, p, np, n, g, key, rank, cnt, err);
+    hipLaunchKernelGGL((kick_drift_kernel<T, MODE_SCALAR>), grid, dim3(KD_NT), 0, st, p, cell_start, n, g, key, rank,
+                       cnt, err);
   else
-    hipLaunchKernelGGL((kick_drift_kernel<T, MODE_FULL>), grid, dim3(256), 0, st, p, np, n, g, key, rank, cnt, err);
+    hipLaunchKernelGGL((kick_drift_kernel<T, MODE_FULL>), grid, dim3(KD_NT), 0, st, p, cell_start, n, g, key, rank, cnt,
+                       err);
 }
 
 // ---------------------------------------------------------------------------
@@ -358,13 +411,16 @@ constexpr int SCAN_NT = 256, SCAN_PER = 16, SCAN_CHUNK = SCAN_NT * SCAN_PER;
 
 size_t scan_block_sums_count(long ncell) { return (size_t)((ncell + SCAN_CHUNK - 1) / SCAN_CHUNK); }
 
+// block sums; the order inside a block does not matter, so loads are striped (coalesced)
 __global__ __launch_bounds__(SCAN_NT) void scan_reduce_kernel(const uint32_t* cnt, long ncell, uint32_t* bsum) {
   __shared__ uint32_t red[SCAN_NT];
-  const long base = (long)blockIdx.x * SCAN_CHUNK + (long)threadIdx.x * SCAN_PER;
+  const long base = (long)blockIdx.x * SCAN_CHUNK + threadIdx.x;
   uint32_t s = 0;
 #pragma unroll
-  for (int j = 0; j < SCAN_PER; ++j)
-    if (base + j < ncell) s += cnt[base + j];
+  for (int j = 0; j < SCAN_PER; ++j) {
+    const long i = base + (long)j * SCAN_NT;
+    if (i < ncell) s += cnt[i];
+  }
   red[threadIdx.x] = s;
   __syncthreads();
   for (int w = SCAN_NT / 2; w > 0; w >>= 1) {
@@ -401,34 +457,51 @@ __global__ __launch_bounds__(1024) void scan_blocks_kernel(uint32_t* bsum, long 
   }
 }
 
+// exclusive scan of one chunk: striped coalesced loads into LDS, per-thread scan of 16
+// consecutive values (padded LDS rows), block scan of the thread totals, striped stores
 __global__ __launch_bounds__(SCAN_NT) void scan_apply_kernel(uint32_t* cnt, long ncell, const uint32_t* boff,
                                                              uint32_t* cell_start) {
+  constexpr int PAD = SCAN_PER + 1;
+  __shared__ uint32_t buf[SCAN_NT * PAD];
   __shared__ uint32_t part[SCAN_NT];
-  const long base = (long)blockIdx.x * SCAN_CHUNK + (long)threadIdx.x * SCAN_PER;
-  uint32_t v[SCAN_PER];
+  const long base = (long)blockIdx.x * SCAN_CHUNK;
+  const int t = threadIdx.x;
+#pragma unroll
+  for (int j = 0; j < SCAN_PER; ++j) {
+    const int q = t + j * SCAN_NT;  // element of the chunk
+    const long i = base + q;
+    buf[(q / SCAN_PER) * PAD + q % SCAN_PER] = (i < ncell) ? cnt[i] : 0u;
+    if (i < ncell) cnt[i] = 0u;
+  }
+  __syncthreads();
   uint32_t s = 0;
 #pragma unroll
-  for (int j = 0; j < SCAN_PER; ++j) {
-    v[j] = (base + j < ncell) ? cnt[base + j] : 0u;
-    s += v[j];
-  }
-  part[threadIdx.x] = s;
+  for (int j = 0; j < SCAN_PER; ++j) s += buf[t * PAD + j];
+  part[t] = s;
   __syncthreads();
   for (int off = 1; off < SCAN_NT; off <<= 1) {
-    const uint32_t t = (threadIdx.x >= (unsigned)off) ? part[threadIdx.x - off] : 0u;
+    const uint32_t v = (t >= off) ? part[t - off] : 0u;
     __syncthreads();
-    part[threadIdx.x] += t;
+    part[t] += v;
     __syncthreads();
   }
-  uint32_t run = boff[blockIdx.x] + ((threadIdx.x == 0) ? 0u : part[threadIdx.x - 1]);
+  uint32_t run = boff[blockIdx.x] + ((t == 0) ? 0u : part[t - 1]);
 #pragma unroll
   for (int j = 0; j < SCAN_PER; ++j) {
-    if (base + j < ncell) {
-      cell_start[base + j] = run;
-      cnt[base + j] = 0u;
-      run += v[j];
-      if (base + j == ncell - 1) cell_start[ncell] = run;
-    }
+    const uint32_t v = buf[t * PAD + j];
+    buf[t * PAD + j] = run;
+    run += v;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < SCAN_PER; ++j) {
+    const int q = t + j * SCAN_NT;
+    const long i = base + q;
+    if (i < ncell) cell_start[i] = buf[(q / SCAN_PER) * PAD + q % SCAN_PER];
+  }
+  if (base + SCAN_CHUNK >= ncell && t == SCAN_NT - 1) {
+    // the last block also writes the total at cell_start[ncell]
+    cell_start[ncell] = boff[blockIdx.x] + part[SCAN_NT - 1];
   }
 }
 
@@ -509,8 +582,8 @@ void launch_copy_unpad(const cplx<T>* spec, int n, int nhp, cplx<T>* out, bool t
                                  uint32_t*, uint32_t*, int*, hipStream_t);                                             \
   template void launch_deposit<T>(const Particles<T>&, const uint32_t*, int, int, bool, double, T*, double*, double*, \
                                   hipStream_t);                                                                       \
-  template void launch_kick_drift<T>(const Particles<T>&, long, int, const GatherArgs<T>&, uint32_t*, uint32_t*,       \
-                                     uint32_t*, int*, hipStream_t);                                                    \
+  template void launch_kick_drift<T>(const Particles<T>&, long, int, const uint32_t*, const GatherArgs<T>&, uint32_t*, \
+                                     uint32_t*, uint32_t*, int*, hipStream_t);                                         \
   template void launch_scatter<T>(const Particles<T>&, Particles<T>, long, const uint32_t*, const uint32_t*,           \
                                   const uint32_t*, hipStream_t);                                                       \
   template void launch_export<T>(const Particles<T>&, long, double*, T*, uint32_t*, hipStream_t);                      \
