@@ -14,6 +14,7 @@ using namespace gpm;
 namespace {
 
 constexpr size_t kAlign = 256;
+constexpr size_t kSkew = 5 * 256;
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 int mode_of(int physics) {
@@ -44,10 +45,13 @@ Layout make_layout(const pm_config& c) {
   L.spec_comp = n * n * (long)L.nhp;
   const int nspec = L.nsrc < 6 && mode == MODE_FULL ? 6 : (L.nsrc < 1 ? 1 : L.nsrc);
   size_t o = 0;
-  auto take = [&](size_t bytes) { size_t r = o; o = align_up(o + bytes); return r; };
+  // every buffer (and every component inside the particle blocks) starts kSkew bytes further
+  // from a large power-of-two boundary than the previous one, so that the same index in
+  // different arrays does not fall on the same HBM channel
+  auto take = [&](size_t bytes) { size_t r = o; o = align_up(o + bytes) + kSkew; return r; };
   for (int b = 0; b < 2; ++b) {
-    L.pos[b] = take(3 * np * 8);
-    L.mom[b] = take(3 * np * rs);
+    L.pos[b] = take(3 * np * 8 + 2 * kSkew);
+    L.mom[b] = take(3 * np * rs + 2 * kSkew);
     L.ids[b] = take(np * 4);
   }
   L.key = take(np * 4);
@@ -65,7 +69,7 @@ Layout make_layout(const pm_config& c) {
   L.tw = take(n * 2 * rs);
   L.kt = take(n * rs);
   L.rowsum = take(n * n * 8);
-  L.scal = take(8 * 8);
+  L.scal = take(1024 * 8);  // FP64 scalars [0..8) and reduction scratch [8..1024)
   L.err = take(64);
   L.total = o;
   return L;
@@ -171,8 +175,9 @@ struct pm_ctx {
     Particles<T> p;
     double* pb = at<double>(L.pos[b]);
     T* mb = at<T>(L.mom[b]);
-    p.px = pb; p.py = pb + np; p.pz = pb + 2 * np;
-    p.ux = mb; p.uy = mb + np; p.uz = mb + 2 * np;
+    const long sd = (long)(kSkew / sizeof(double)), st_ = (long)(kSkew / sizeof(T));
+    p.px = pb; p.py = pb + np + sd; p.pz = pb + 2 * (np + sd);
+    p.ux = mb; p.uy = mb + np + st_; p.uz = mb + 2 * (np + st_);
     p.id = at<uint32_t>(L.ids[b]);
     return p;
   }

@@ -90,4 +90,11 @@ __host__ __device__ constexpr int stage_ns(int m, int s) {
 
 __device__ __forceinline__ int wrapi(int i, int n) { return i & (n - 1); }
 
+// Reciprocal and reciprocal square root: the FP32 path uses the hardware
+// instructions (about 1 ulp), the FP64 path the correctly rounded operations.
+template <typename T> __device__ __forceinline__ T rcp(T x) { return (T)1 / x; }
+template <> __device__ __forceinline__ float rcp<float>(float x) { return __builtin_amdgcn_rcpf(x); }
+template <typename T> __device__ __forceinline__ T rsqrt_(T x) { return (T)1 / sqrt(x); }
+template <> __device__ __forceinline__ float rsqrt_<float>(float x) { return __builtin_amdgcn_rsqf(x); }
+
 }  // namespace gpm

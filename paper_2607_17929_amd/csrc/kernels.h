@@ -65,6 +65,7 @@ template <typename T> void launch_solve(const SolveArgs<T>& a, hipStream_t st);
 template <typename T>
 void launch_tensor_components(cplx<T>* spec, long comp_stride, int n, int nhp, const T* kt, const cplx<T>* hp,
                               const cplx<T>* hx, double inv_n3, hipStream_t st);
+// FP64 sum of count values into out[0]; out[8 .. 8 + 512) is used as scratch
 void launch_sum_f64(const double* in, long count, double* out, hipStream_t st);
 void launch_sum_as_f64(const float* in, long count, double* out, hipStream_t st);
 

@@ -92,7 +92,7 @@ __global__ __launch_bounds__(DEP_NT) void deposit_kernel(Particles<T> p, const u
                                                          T a, T* __restrict__ dep, double* __restrict__ esum) {
   constexpr int CAP = dep_capacity<T>();
   constexpr int TX = DEP_TX, TY = DEP_TY, TZ = DEP_TZ, CX = DEP_CX, ROWS = DEP_ROWS, GW = TX + 3;
-  __shared__ T sfx[CAP], sfy[CAP], sfz[CAP], sux[CAP], suy[CAP], suz[CAP], se[CAP];
+  __shared__ T sfx[CAP], sfy[CAP], sfz[CAP], sux[CAP], suy[CAP], suz[CAP], se[CAP], sie[CAP];
   __shared__ uint32_t cstart[ROWS * CX];  // row-relative staged start of local cell (row, lx); lx = 0 is cell x0 - 1
   __shared__ uint32_t gcs[ROWS * GW];     // halo start/end, then starts of cells x0 .. x0 + TX
   __shared__ uint32_t row_off[ROWS + 1];
@@ -153,7 +153,9 @@ __global__ __launch_bounds__(DEP_NT) void deposit_kernel(Particles<T> p, const u
       if constexpr (NC > 1) {
         const T ux = p.ux[gi], uy = p.uy[gi], uz = p.uz[gi];
         sux[l] = ux; suy[l] = uy; suz[l] = uz;
-        se[l] = REL ? sqrt(a * a + ux * ux + uy * uy + uz * uz) : a;
+        const T e = REL ? sqrt(a * a + ux * ux + uy * uy + uz * uz) : a;
+        se[l] = e;
+        sie[l] = rcp(e);
       }
     }
     __syncthreads();
@@ -185,7 +187,7 @@ __global__ __launch_bounds__(DEP_NT) void deposit_kernel(Particles<T> p, const u
               acc[k][0] += w * a;
             } else {
               const T ux = sux[l], uy = suy[l], uz = suz[l], e_p = se[l];
-              const T wi = w / e_p;
+              const T wi = w * sie[l];
               acc[k][0] += w * e_p; acc[k][1] += w * ux; acc[k][2] += w * uy; acc[k][3] += w * uz;
               acc[k][4] += wi * ux * ux; acc[k][5] += wi * ux * uy; acc[k][6] += wi * ux * uz;
               acc[k][7] += wi * uy * uy; acc[k][8] += wi * uy * uz; acc[k][9] += wi * uz * uz;
@@ -301,13 +303,20 @@ __global__ __launch_bounds__(KD_NT) void kick_drift_kernel(Particles<T> p, const
     rbeg[tid] = b;
     roff[tid + 1] = e - b;
   }
-  // field tile with periodic wrap: local (gx, gy, gz) <-> global (x0 - 1 + gx, ...)
+  // field tile with periodic wrap: local (gx, gy, gz) <-> global (x0 - 1 + gx, ...); lanes run along
+  // x in groups of 32 (KD_GX = 19 of them load), one (gy, gz) row per group
   const T* src[5] = {ga.phi, ga.chi, ga.bx, ga.by, ga.bz};
-  for (int q = tid; q < KD_G; q += KD_NT) {
-    const int gx = q % KD_GX, gy = (q / KD_GX) % KD_GY, gz = q / (KD_GX * KD_GY);
-    const long o = (long)((z0 - 1 + gz) & m) * nn + (long)((y0 - 1 + gy) & m) * n + ((x0 - 1 + gx) & m);
+  {
+    const int lane = tid & 31, grp = tid >> 5;
+    const int gxo = (x0 - 1 + lane) & m;
+    for (int row = grp; row < KD_GY * KD_GZ; row += KD_NT / 32) {
+      const int gy = row % KD_GY, gz = row / KD_GY;
+      const long o = (long)((z0 - 1 + gz) & m) * nn + (long)((y0 - 1 + gy) & m) * n + gxo;
+      if (lane < KD_GX) {
 #pragma unroll
-    for (int f = 0; f < NF; ++f) tile[f][q] = src[f][o];
+        for (int f = 0; f < NF; ++f) tile[f][row * KD_GX + lane] = src[f][o];
+      }
+    }
   }
   __syncthreads();
   if (tid == 0) {
@@ -339,14 +348,15 @@ __global__ __launch_bounds__(KD_NT) void kick_drift_kernel(Particles<T> p, const
       ux -= dt * a * gphi[0];
       uy -= dt * a * gphi[1];
       uz -= dt * a * gphi[2];
-      const T ia = (T)1 / ah;
+      const T ia = rcp(ah);
       vx = ux * ia; vy = uy * ia; vz = uz * ia;
     } else {
       T chi_p, gchi[3];
       gather_lds(tile[1], lz, ly, lx, wx, wy, wz, hn, chi_p, gchi);
       const T u2 = ux * ux + uy * uy + uz * uz;
-      const T e = sqrt(a * a + u2);
-      const T cphi = -(a * a + (T)2 * u2) / e;
+      const T ie = rsqrt_(a * a + u2);
+      const T e = (a * a + u2) * ie;
+      const T cphi = -(a * a + (T)2 * u2) * ie;
       T fx = cphi * gphi[0] + e * gchi[0];
       T fy = cphi * gphi[1] + e * gchi[1];
       T fz = cphi * gphi[2] + e * gchi[2];
@@ -365,8 +375,8 @@ __global__ __launch_bounds__(KD_NT) void kick_drift_kernel(Particles<T> p, const
       uz += dt * fz;
       const T v2 = ux * ux + uy * uy + uz * uz;
       const T eh2 = ah * ah + v2;
-      const T ieh = (T)1 / sqrt(eh2);
-      const T fac = ((T)1 + ((T)3 - v2 / eh2) * phi_p - chi_p) * ieh;
+      const T ieh = rsqrt_(eh2);
+      const T fac = ((T)1 + ((T)3 - v2 * ieh * ieh) * phi_p - chi_p) * ieh;
       vx = ux * fac + B[0];
       vy = uy * fac + B[1];
       vz = uz * fac + B[2];
@@ -515,23 +525,43 @@ void launch_scan(uint32_t* cnt, uint32_t* cell_start, long ncell, uint32_t* bloc
 // ---------------------------------------------------------------------------
 // scatter into the other buffer at cell_start[key] + rank
 // ---------------------------------------------------------------------------
+constexpr int SC_PER = 4;  // particles per thread: independent load chains in flight
+
 template <typename T>
 __global__ __launch_bounds__(256) void scatter_kernel(Particles<T> s, Particles<T> d, long np,
                                                       const uint32_t* __restrict__ key, const uint32_t* __restrict__ rank,
                                                       const uint32_t* __restrict__ cell_start) {
-  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= np) return;
-  const long j = (long)cell_start[key[i]] + rank[i];
-  d.px[j] = s.px[i]; d.py[j] = s.py[i]; d.pz[j] = s.pz[i];
-  d.ux[j] = s.ux[i]; d.uy[j] = s.uy[i]; d.uz[j] = s.uz[i];
-  d.id[j] = s.id[i];
+  const long base = (long)blockIdx.x * (256 * SC_PER) + threadIdx.x;
+  uint32_t k[SC_PER], r[SC_PER];
+  long j[SC_PER];
+#pragma unroll
+  for (int q = 0; q < SC_PER; ++q) {
+    const long i = base + q * 256;
+    k[q] = (i < np) ? key[i] : 0u;
+    r[q] = (i < np) ? rank[i] : 0u;
+  }
+#pragma unroll
+  for (int q = 0; q < SC_PER; ++q) j[q] = (long)cell_start[k[q]] + r[q];
+#pragma unroll
+  for (int q = 0; q < SC_PER; ++q) {
+    const long i = base + q * 256;
+    if (i < np) {
+      const double x = s.px[i], y = s.py[i], z = s.pz[i];
+      const T ux = s.ux[i], uy = s.uy[i], uz = s.uz[i];
+      const uint32_t id = s.id[i];
+      d.px[j[q]] = x; d.py[j[q]] = y; d.pz[j[q]] = z;
+      d.ux[j[q]] = ux; d.uy[j[q]] = uy; d.uz[j[q]] = uz;
+      d.id[j[q]] = id;
+    }
+  }
 }
 
 template <typename T>
 void launch_scatter(const Particles<T>& src, Particles<T> dst, long np, const uint32_t* key, const uint32_t* rank,
                     const uint32_t* cell_start, hipStream_t st) {
-  hipLaunchKernelGGL((scatter_kernel<T>), dim3((unsigned)((np + 255) / 256)), dim3(256), 0, st, src, dst, np, key, rank,
-                     cell_start);
+  const long per_block = 256 * SC_PER;
+  hipLaunchKernelGGL((scatter_kernel<T>), dim3((unsigned)((np + per_block - 1) / per_block)), dim3(256), 0, st, src, dst,
+                     np, key, rank, cell_start);
 }
 
 // ---------------------------------------------------------------------------

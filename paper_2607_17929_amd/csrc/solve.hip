@@ -189,28 +189,47 @@ void launch_tensor_components(cplx<T>* spec, long comp_stride, int n, int nhp, c
                      comp_stride, n, nhp, kt, hp, hx);
 }
 
-// deterministic single-workgroup FP64 sum (input values widened to FP64)
+// deterministic FP64 sum (input values widened to FP64): a fixed number of
+// workgroups reduce contiguous slices, then one workgroup adds the partials
+constexpr int SUM_BLOCKS = 512;
+
 template <typename T>
-__global__ __launch_bounds__(1024) void sum_f64_kernel(const T* in, long count, double* out) {
-  __shared__ double red[1024];
+__global__ __launch_bounds__(256) void sum_partial_kernel(const T* in, long count, double* part) {
+  __shared__ double red[256];
+  const long per = (count + SUM_BLOCKS - 1) / SUM_BLOCKS;
+  const long b = (long)blockIdx.x * per, e = min(count, b + per);
   double acc = 0.0;
-  for (long i = threadIdx.x; i < count; i += 1024) acc += (double)in[i];
+  for (long i = b + threadIdx.x; i < e; i += 256) acc += (double)in[i];
   red[threadIdx.x] = acc;
   __syncthreads();
-  for (int s = 512; s > 0; s >>= 1) {
+  for (int s = 128; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+__global__ __launch_bounds__(256) void sum_final_kernel(const double* part, double* out) {
+  __shared__ double red[256];
+  red[threadIdx.x] = part[threadIdx.x] + part[threadIdx.x + 256];
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
     if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
     __syncthreads();
   }
   if (threadIdx.x == 0) out[0] = red[0];
 }
 
-void launch_sum_f64(const double* in, long count, double* out, hipStream_t st) {
-  hipLaunchKernelGGL((sum_f64_kernel<double>), dim3(1), dim3(1024), 0, st, in, count, out);
+// out[0] = sum; out[1 .. SUM_BLOCKS] is scratch for the partials
+template <typename T>
+static void sum_to_f64(const T* in, long count, double* out, hipStream_t st) {
+  static_assert(SUM_BLOCKS == 512, "final kernel adds two partials per thread");
+  hipLaunchKernelGGL((sum_partial_kernel<T>), dim3(SUM_BLOCKS), dim3(256), 0, st, in, count, out + 8);
+  hipLaunchKernelGGL(sum_final_kernel, dim3(1), dim3(256), 0, st, out + 8, out);
 }
 
-void launch_sum_as_f64(const float* in, long count, double* out, hipStream_t st) {
-  hipLaunchKernelGGL((sum_f64_kernel<float>), dim3(1), dim3(1024), 0, st, in, count, out);
-}
+void launch_sum_f64(const double* in, long count, double* out, hipStream_t st) { sum_to_f64<double>(in, count, out, st); }
+void launch_sum_as_f64(const float* in, long count, double* out, hipStream_t st) { sum_to_f64<float>(in, count, out, st); }
 
 template void launch_solve<float>(const SolveArgs<float>&, hipStream_t);
 template void launch_solve<double>(const SolveArgs<double>&, hipStream_t);
