@@ -64,7 +64,10 @@ enum {
   PM_FULL = 2       /* phi, chi, B_i (elliptic, Eq. 6) and h_ij (Eq. 5, not fed back) */
 };
 
-enum { PM_FLAG_TIMINGS = 1u }; /* record per-stage device times (pm_get_timings) */
+enum {
+  PM_FLAG_TIMINGS = 1u, /* record per-stage device times (pm_get_timings) */
+  PM_FLAG_CLOSURE = 2u  /* reserve workspace for the learned closure (pm_closure_*) */
+};
 
 /* field identifiers for pm_get_field / pm_set_field (real space, [z][y][x]) */
 enum {
@@ -173,6 +176,40 @@ pm_status pm_sync(pm_ctx* ctx);
  * half spectrum, out = real, scaled by 1/n^3.  Both device pointers, context
  * precision; uses the context's spectrum buffer as scratch. */
 pm_status pm_debug_fft(pm_ctx* ctx, const void* d_in, void* d_out, int direction);
+
+/* Gradient of phi (centred differences, CIC-interpolated, as used by the kick)
+ * at every particle, [n][3] in identifier order, context precision. */
+pm_status pm_gather_grad_phi(pm_ctx* ctx, void* out, int dst_on_device);
+
+/* ---- learned force closure (an addition to the paper's method) --------------
+ * A 3-layer convolutional network on the mesh, conv(4->16)-ReLU-conv(16->16)-
+ * ReLU-conv(16->3) with 3x3x3 periodic kernels, bfloat16 weights and
+ * activations with FP32 accumulation, predicts a correction to grad phi from
+ * sign(delta) log(1+|delta|) (delta from the last deposit's n00) and
+ * grad phi / rms|grad phi|; the output is in units of rms|grad phi|.  When
+ * enabled, pm_update_particles adds the CIC-interpolated, rescaled output to
+ * the gathered grad phi.  Needs PM_FLAG_CLOSURE; training needs n_mesh <= 256.
+ * Parameters: one FP32 vector of PM_CLOSURE_NPARAM values laid out as
+ * W1[16][4][27] b1[16] W2[16][16][27] b2[16] W3[3][16][27] b3[3], tap index
+ * 9 (dz+1) + 3 (dy+1) + (dx+1), y[co](p) = b[co] + sum W[co][ci][t] x[ci](p + d_t). */
+enum { PM_CLOSURE_NPARAM = 9971 };
+pm_status pm_closure_set_params(pm_ctx* ctx, const float* params, int src_on_device);
+pm_status pm_closure_enable(pm_ctx* ctx, int on);
+/* Run the network on the current deposit and phi (after pm_solve_metric); output kept in the
+ * context; scaled = 1 multiplies by rms|grad phi| (force units). */
+pm_status pm_closure_forward(pm_ctx* ctx, int scaled);
+/* rms|grad phi| of the last pm_closure_forward (the output's unit); synchronises. */
+pm_status pm_closure_scale(pm_ctx* ctx, double* rms);
+/* Network output at the particles, [n][3] FP32, identifier order. */
+pm_status pm_closure_gather(pm_ctx* ctx, float* out, int dst_on_device);
+/* Gradient of sum_p dpred_p . out_p with respect to the parameters (device pointers:
+ * d_dpred [n][3] in identifier order, d_grad [PM_CLOSURE_NPARAM], overwritten), using the
+ * activations of the last pm_closure_forward. */
+pm_status pm_closure_backward(pm_ctx* ctx, const float* d_dpred, float* d_grad);
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected, step >= 1) on FP32
+ * device vectors, then the context's bfloat16 weights are refreshed from d_params. */
+pm_status pm_closure_adam(pm_ctx* ctx, float* d_params, float* d_m, float* d_v, const float* d_grad, int step,
+                          double lr);
 
 const char* pm_status_string(pm_status s);
 /* Last error message recorded on this context (never NULL). */

@@ -11,6 +11,8 @@ PM_OK, PM_EINVAL, PM_EWORKSPACE, PM_EHIP, PM_ENAN, PM_ESTATE, PM_ERANGE, PM_EUNS
 PM_FP32, PM_FP64 = 0, 1
 PM_NEWTONIAN, PM_SCALAR, PM_FULL = 0, 1, 2
 PM_FLAG_TIMINGS = 1
+PM_FLAG_CLOSURE = 2
+PM_CLOSURE_NPARAM = 9971
 
 FIELDS = {
     "n00": 0, "n0x": 1, "n0y": 2, "n0z": 3, "nxx": 4, "nxy": 5, "nxz": 6, "nyy": 7, "nyz": 8, "nzz": 9,
@@ -24,7 +26,8 @@ EXPORTS = (
     "pm_query_workspace", "pm_create", "pm_destroy", "pm_init_particles", "pm_deposit", "pm_solve_metric",
     "pm_update_particles", "pm_step", "pm_get_field", "pm_set_field", "pm_get_particles", "pm_get_time",
     "pm_background", "pm_tau_of_a", "pm_get_timings", "pm_sync", "pm_debug_fft", "pm_status_string",
-    "pm_last_error",
+    "pm_last_error", "pm_gather_grad_phi", "pm_closure_set_params", "pm_closure_enable", "pm_closure_forward",
+    "pm_closure_gather", "pm_closure_backward", "pm_closure_adam", "pm_closure_scale",
 )
 
 
@@ -75,6 +78,14 @@ def load():
         "pm_get_timings": [vp, C.POINTER(C.c_double), C.POINTER(C.c_int64), C.c_int],
         "pm_sync": [vp],
         "pm_debug_fft": [vp, vp, vp, C.c_int],
+        "pm_gather_grad_phi": [vp, vp, C.c_int],
+        "pm_closure_set_params": [vp, vp, C.c_int],
+        "pm_closure_enable": [vp, C.c_int],
+        "pm_closure_forward": [vp, C.c_int],
+        "pm_closure_gather": [vp, vp, C.c_int],
+        "pm_closure_backward": [vp, vp, vp],
+        "pm_closure_adam": [vp, vp, vp, vp, vp, C.c_int, C.c_double],
+        "pm_closure_scale": [vp, C.POINTER(C.c_double)],
     }
     for name, args in sig.items():
         f = getattr(lib, name)

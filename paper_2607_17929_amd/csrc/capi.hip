@@ -27,6 +27,9 @@ bool is_pow2(long v) { return v > 0 && (v & (v - 1)) == 0; }
 struct Layout {
   size_t pos[2], mom[2], ids[2], key, rank, cnt, cell_start, bsum;
   size_t dep, part, phi[3], chi, b[3], spec, hst[4], tw, kt, rowsum, scal, err;
+  // learned closure (PM_FLAG_CLOSURE): activations, gradients, packed weights, partials
+  size_t cl_act[3], cl_dact[3], cl_corr, cl_dcorr, cl_wf, cl_wb, cl_bias, cl_part, cl_scal;
+  bool closure, cl_train;
   size_t total;
   int ndep, nsrc, nout, nhp;
   long spec_comp;
@@ -70,6 +73,22 @@ Layout make_layout(const pm_config& c) {
   L.kt = take(n * rs);
   L.rowsum = take(n * n * 8);
   L.scal = take(1024 * 8);  // FP64 scalars [0..8) and reduction scratch [8..1024)
+  L.closure = (c.flags & PM_FLAG_CLOSURE) != 0;
+  if (L.closure) {
+    for (int i = 0; i < 3; ++i) L.cl_act[i] = take(n3 * 32);
+    L.cl_corr = take(3 * n3 * 4);
+    L.cl_wf = take(3 * 27 * 256 * 2);
+    L.cl_wb = take(3 * 27 * 256 * 2);
+    L.cl_bias = take(3 * 16 * 4);
+    L.cl_scal = take(1024 * 8);
+    // training buffers only on meshes up to 256^3 (weight-gradient partials grow with n^3)
+    L.cl_train = n <= 256;
+    if (L.cl_train) {
+      for (int i = 0; i < 3; ++i) L.cl_dact[i] = take(n3 * 32);
+      L.cl_dcorr = take(3 * n3 * 4);
+      L.cl_part = take((n3 / 512) * (27 * 256 + 16) * 4);
+    }
+  }
   L.err = take(64);
   L.total = o;
   return L;
@@ -109,6 +128,7 @@ struct pm_ctx {
   double tau = 0, last_step = 0, dtau_last = 0;
   int64_t steps = 0;
   bool have_particles = false, deposited = false, solved = false, solved_once = false;
+  bool cl_params = false, cl_on = false, cl_forwarded = false;
   int sticky = 0;
   std::string last_error;
   // per-stage event pairs recorded since the last pm_get_timings (pool reused)
@@ -344,6 +364,29 @@ pm_status do_init(pm_ctx* c, const double* pos, const void* u, const uint32_t* i
   return c->hip_check("init_particles");
 }
 
+// features of the last deposit (n00) and the latest phi -> three convolutions -> FP32 SoA output
+// (scaled by rms |grad phi| when `scaled`, i.e. in force units)
+template <typename T>
+void closure_forward_impl(pm_ctx* c, bool scaled) {
+  const Layout& L = c->L;
+  double* cs = c->at<double>(L.cl_scal);
+  float* rms = reinterpret_cast<float*>(cs + 1);
+  // FP64 sum of n00 into cs[0], partials in cs[8..]
+  if (c->cfg.precision == PM_FP64) launch_sum_f64(c->at<double>(L.dep), c->n3, cs, c->st);
+  else launch_sum_as_f64(c->at<float>(L.dep), c->n3, cs, c->st);
+  uint16_t* a0 = c->at<uint16_t>(L.cl_act[0]);
+  uint16_t* a1 = c->at<uint16_t>(L.cl_act[1]);
+  uint16_t* a2 = c->at<uint16_t>(L.cl_act[2]);
+  closure_features<T>(c->at<T>(L.dep), c->at<T>(L.phi[c->i_phi]), c->n, cs, cs + 16, rms, a0, c->st);
+  const uint16_t* wf = c->at<uint16_t>(L.cl_wf);
+  const float* bias = c->at<float>(L.cl_bias);
+  closure_conv(a0, wf, bias, c->n, 0, a1, nullptr, nullptr, c->st);
+  closure_conv(a1, wf + 27 * 256, bias + 16, c->n, 0, a2, nullptr, nullptr, c->st);
+  closure_conv(a2, wf + 2 * 27 * 256, bias + 32, c->n, 1, c->at<float>(L.cl_corr), nullptr, scaled ? rms : nullptr,
+               c->st);
+  c->cl_forwarded = true;
+}
+
 template <typename T>
 pm_status do_update(pm_ctx* c, double dtau) {
   const Layout& L = c->L;
@@ -353,6 +396,11 @@ pm_status do_update(pm_ctx* c, double dtau) {
   g.bx = L.b[0] ? c->at<T>(L.b[0]) : nullptr;
   g.by = L.b[1] ? c->at<T>(L.b[1]) : nullptr;
   g.bz = L.b[2] ? c->at<T>(L.b[2]) : nullptr;
+  g.corr = nullptr;
+  if (c->cl_on) {
+    closure_forward_impl<T>(c, true);
+    g.corr = c->at<float>(L.cl_corr);
+  }
   g.mode = c->mode;
   g.dtau = dtau;
   g.a = c->a_of(c->tau);
@@ -675,6 +723,142 @@ pm_status pm_debug_fft(pm_ctx* c, const void* d_in, void* d_out, int direction) 
   }
   c->deposited = false;
   return c->hip_check("debug_fft");
+}
+
+pm_status pm_gather_grad_phi(pm_ctx* c, void* out, int dst_on_device) {
+  if (!c || !out) return PM_EINVAL;
+  if (!c->have_particles) return c->fail(PM_ESTATE, "no particles");
+  const Layout& L = c->L;
+  const long np = c->np;
+  const int other = 1 - c->cur;
+  void* dst = dst_on_device ? out : (void*)(c->ws + L.pos[other]);  // 3 np values fit the FP64 position block
+  if (c->cfg.precision == PM_FP64)
+    gather_grad_phi<double>(c->parts<double>(c->cur), np, c->n, c->at<double>(L.phi[c->i_phi]),
+                            reinterpret_cast<double*>(dst), c->st);
+  else
+    gather_grad_phi<float>(c->parts<float>(c->cur), np, c->n, c->at<float>(L.phi[c->i_phi]),
+                           reinterpret_cast<float*>(dst), c->st);
+  if (!dst_on_device) {
+    (void)hipMemcpyAsync(out, dst, 3 * np * c->rs, hipMemcpyDeviceToHost, c->st);
+    (void)hipStreamSynchronize(c->st);
+  }
+  return c->hip_check("gather_grad_phi");
+}
+
+static pm_status closure_ready(pm_ctx* c, bool params) {
+  if (!c) return PM_EINVAL;
+  if (!c->L.closure) return c->fail(PM_EUNSUPPORTED, "context created without PM_FLAG_CLOSURE");
+  if (params && !c->cl_params) return c->fail(PM_ESTATE, "closure parameters not set");
+  return PM_OK;
+}
+
+pm_status pm_closure_set_params(pm_ctx* c, const float* params, int src_on_device) {
+  pm_status s = closure_ready(c, false);
+  if (s != PM_OK) return s;
+  if (!params) return PM_EINVAL;
+  const Layout& L = c->L;
+  const float* src = params;
+  if (!src_on_device) {
+    // stage through the unused half of the second FP64 position block
+    float* dst = reinterpret_cast<float*>(c->ws + L.pos[1 - c->cur]);
+    (void)hipMemcpyAsync(dst, params, PM_CLOSURE_NPARAM * sizeof(float), hipMemcpyHostToDevice, c->st);
+    src = dst;
+  }
+  closure_pack(src, c->at<uint16_t>(L.cl_wf), c->at<uint16_t>(L.cl_wb), c->at<float>(L.cl_bias), c->st);
+  if (!src_on_device) (void)hipStreamSynchronize(c->st);
+  c->cl_params = true;
+  return c->hip_check("closure_set_params");
+}
+
+pm_status pm_closure_enable(pm_ctx* c, int on) {
+  pm_status s = closure_ready(c, on != 0);
+  if (s != PM_OK) return s;
+  c->cl_on = on != 0;
+  return PM_OK;
+}
+
+pm_status pm_closure_forward(pm_ctx* c, int scaled) {
+  pm_status s = closure_ready(c, true);
+  if (s != PM_OK) return s;
+  if (!c->solved) return c->fail(PM_ESTATE, "closure_forward needs a deposit and a metric solve");
+  if (c->cfg.precision == PM_FP64) closure_forward_impl<double>(c, scaled != 0);
+  else closure_forward_impl<float>(c, scaled != 0);
+  return c->hip_check("closure_forward");
+}
+
+pm_status pm_closure_scale(pm_ctx* c, double* rms) {
+  pm_status s = closure_ready(c, true);
+  if (s != PM_OK) return s;
+  if (!rms) return PM_EINVAL;
+  if (!c->cl_forwarded) return c->fail(PM_ESTATE, "closure_scale needs closure_forward");
+  float v = 0.f;
+  (void)hipStreamSynchronize(c->st);
+  if (hipMemcpy(&v, c->at<double>(c->L.cl_scal) + 1, sizeof(float), hipMemcpyDeviceToHost) != hipSuccess)
+    return c->fail(PM_EHIP, "reading the closure scale failed");
+  *rms = v;
+  return PM_OK;
+}
+
+pm_status pm_closure_gather(pm_ctx* c, float* out, int dst_on_device) {
+  pm_status s = closure_ready(c, true);
+  if (s != PM_OK) return s;
+  if (!out) return PM_EINVAL;
+  if (!c->cl_forwarded) return c->fail(PM_ESTATE, "closure_gather needs closure_forward");
+  const Layout& L = c->L;
+  const long np = c->np;
+  float* dst = dst_on_device ? out : reinterpret_cast<float*>(c->ws + L.pos[1 - c->cur]);
+  if (c->cfg.precision == PM_FP64)
+    closure_gather3<double>(c->parts<double>(c->cur), np, c->n, c->at<float>(L.cl_corr), dst, c->st);
+  else
+    closure_gather3<float>(c->parts<float>(c->cur), np, c->n, c->at<float>(L.cl_corr), dst, c->st);
+  if (!dst_on_device) {
+    (void)hipMemcpyAsync(out, dst, 3 * np * sizeof(float), hipMemcpyDeviceToHost, c->st);
+    (void)hipStreamSynchronize(c->st);
+  }
+  return c->hip_check("closure_gather");
+}
+
+pm_status pm_closure_backward(pm_ctx* c, const float* d_dpred, float* d_grad) {
+  pm_status s = closure_ready(c, true);
+  if (s != PM_OK) return s;
+  if (!d_dpred || !d_grad) return PM_EINVAL;
+  const Layout& L = c->L;
+  if (!L.cl_train) return c->fail(PM_EUNSUPPORTED, "closure training needs n_mesh <= 256");
+  if (!c->cl_forwarded) return c->fail(PM_ESTATE, "closure_backward needs closure_forward");
+  const int n = c->n;
+  float* dcorr = c->at<float>(L.cl_dcorr);
+  c->zero(L.cl_dcorr, 3 * c->n3 * 4);
+  if (c->cfg.precision == PM_FP64)
+    closure_gather3_adjoint<double>(c->parts<double>(c->cur), c->np, n, d_dpred, dcorr, c->st);
+  else
+    closure_gather3_adjoint<float>(c->parts<float>(c->cur), c->np, n, d_dpred, dcorr, c->st);
+  uint16_t* d3 = c->at<uint16_t>(L.cl_dact[2]);
+  uint16_t* d2 = c->at<uint16_t>(L.cl_dact[1]);
+  uint16_t* d1 = c->at<uint16_t>(L.cl_dact[0]);
+  const uint16_t* a0 = c->at<uint16_t>(L.cl_act[0]);
+  const uint16_t* a1 = c->at<uint16_t>(L.cl_act[1]);
+  const uint16_t* a2 = c->at<uint16_t>(L.cl_act[2]);
+  const uint16_t* wb = c->at<uint16_t>(L.cl_wb);
+  float* part = c->at<float>(L.cl_part);
+  closure_soa3_to_bf16(dcorr, c->n3, d3, c->st);
+  const long off2 = 16 * 4 * 27 + 16, off3 = off2 + 16 * 16 * 27 + 16;
+  closure_wgrad(a2, d3, n, part, 16, 3, d_grad, off3, c->st);
+  closure_conv(d3, wb + 2 * 27 * 256, nullptr, n, 2, d2, a2, nullptr, c->st);
+  closure_wgrad(a1, d2, n, part, 16, 16, d_grad, off2, c->st);
+  closure_conv(d2, wb + 27 * 256, nullptr, n, 2, d1, a1, nullptr, c->st);
+  closure_wgrad(a0, d1, n, part, 4, 16, d_grad, 0, c->st);
+  return c->hip_check("closure_backward");
+}
+
+pm_status pm_closure_adam(pm_ctx* c, float* d_params, float* d_m, float* d_v, const float* d_grad, int step,
+                          double lr) {
+  pm_status s = closure_ready(c, false);
+  if (s != PM_OK) return s;
+  if (!d_params || !d_m || !d_v || !d_grad || step < 1 || !(lr > 0)) return PM_EINVAL;
+  closure_adam(d_params, d_m, d_v, d_grad, PM_CLOSURE_NPARAM, lr, step, c->st);
+  closure_pack(d_params, c->at<uint16_t>(c->L.cl_wf), c->at<uint16_t>(c->L.cl_wb), c->at<float>(c->L.cl_bias), c->st);
+  c->cl_params = true;
+  return c->hip_check("closure_adam");
 }
 
 const char* pm_status_string(pm_status s) {

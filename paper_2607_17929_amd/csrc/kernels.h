@@ -86,6 +86,7 @@ void launch_deposit(const Particles<T>& p, const uint32_t* cell_start, int n, in
 template <typename T>
 struct GatherArgs {
   const T* phi; const T* chi; const T* bx; const T* by; const T* bz;
+  const float* corr;  // closure correction to grad phi, FP32 SoA [3][n^3] (null: none)
   int mode;
   double dtau, a, a_half;
 };
@@ -101,5 +102,24 @@ template <typename T>
 void launch_export(const Particles<T>& p, long np, double* pos_aos, T* u_aos, uint32_t* ids, hipStream_t st);
 template <typename T>
 void launch_copy_unpad(const cplx<T>* spec, int n, int nhp, cplx<T>* out, bool to_padded, hipStream_t st);
+
+// ---- closure.hip ----
+void closure_pack(const float* params, uint16_t* wf, uint16_t* wb, float* bias, hipStream_t st);
+void closure_conv(const uint16_t* in, const uint16_t* w, const float* bias, int n, int mode, void* out,
+                  const uint16_t* mask, const float* scale, hipStream_t st);
+long closure_wgrad_blocks(int n);
+void closure_wgrad(const uint16_t* x, const uint16_t* dy, int n, float* part, int ci_n, int co_n, float* grad,
+                   long off, hipStream_t st);
+void closure_adam(float* p, float* m, float* v, const float* g, int np, double lr, int step, hipStream_t st);
+template <typename T>
+void closure_features(const T* n00, const T* phi, int n, const double* n00_sum, double* part, float* rms,
+                      uint16_t* out, hipStream_t st);
+template <typename T>
+void closure_gather3(const Particles<T>& p, long np, int n, const float* f, float* out, hipStream_t st);
+template <typename T>
+void closure_gather3_adjoint(const Particles<T>& p, long np, int n, const float* vals, float* f, hipStream_t st);
+void closure_soa3_to_bf16(const float* f, long n3, uint16_t* out, hipStream_t st);
+template <typename T>
+void gather_grad_phi(const Particles<T>& p, long np, int n, const T* phi, T* out, hipStream_t st);
 
 }  // namespace gpm

@@ -342,6 +342,24 @@ __global__ __launch_bounds__(KD_NT) void kick_drift_kernel(Particles<T> p, const
     const int lx = ix - x0, ly = iy - y0, lz = iz - z0;  // in [0, T*) by construction of the rows
     T phi_p, gphi[3];
     gather_lds(tile[0], lz, ly, lx, wx, wy, wz, hn, phi_p, gphi);
+    if (ga.corr) {
+      // learned closure: CIC-interpolated correction to grad phi
+      const long n3 = nn * n;
+      const int xs[2] = {ix, (ix + 1) & m}, ys[2] = {iy, (iy + 1) & m}, zs[2] = {iz, (iz + 1) & m};
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const float* g = ga.corr + c * n3;
+        T acc = 0;
+#pragma unroll
+        for (int a2 = 0; a2 < 2; ++a2)
+#pragma unroll
+          for (int b2 = 0; b2 < 2; ++b2)
+#pragma unroll
+            for (int d2 = 0; d2 < 2; ++d2)
+              acc += wz[a2] * wy[b2] * wx[d2] * (T)g[zs[a2] * nn + (long)ys[b2] * n + xs[d2]];
+        gphi[c] += acc;
+      }
+    }
     T ux = p.ux[pi], uy = p.uy[pi], uz = p.uz[pi];
     T vx, vy, vz;
     if constexpr (MODE == MODE_NEWTONIAN) {

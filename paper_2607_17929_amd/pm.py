@@ -17,9 +17,10 @@ _PREC = {"fp32": L.PM_FP32, "fp64": L.PM_FP64}
 
 
 def make_config(n_mesh: int, n_particles: int, box_mpch: float, physics: str = "full", precision: str = "fp32",
-                timings: bool = False) -> L.PMConfig:
+                timings: bool = False, closure: bool = False) -> L.PMConfig:
+    flags = (L.PM_FLAG_TIMINGS if timings else 0) | (L.PM_FLAG_CLOSURE if closure else 0)
     return L.PMConfig(n_mesh=n_mesh, precision=_PREC[precision], n_particles=n_particles, box_mpch=box_mpch,
-                      physics=_PHYS[physics], flags=L.PM_FLAG_TIMINGS if timings else 0)
+                      physics=_PHYS[physics], flags=flags)
 
 
 def query_workspace(cfg: L.PMConfig) -> int:
@@ -55,9 +56,9 @@ class PMContext:
 
     def __init__(self, n_mesh: int, n_particles: int, box_mpch: float, physics: str = "full",
                  precision: str = "fp32", timings: bool = False, device: str | torch.device = "cuda:0",
-                 stream: torch.cuda.Stream | None = None):
+                 stream: torch.cuda.Stream | None = None, closure: bool = False):
         self.lib = L.load()
-        self.cfg = make_config(n_mesh, n_particles, box_mpch, physics, precision, timings)
+        self.cfg = make_config(n_mesh, n_particles, box_mpch, physics, precision, timings, closure)
         self.n = n_mesh
         self.np = n_particles
         self.physics = physics
@@ -182,3 +183,46 @@ class PMContext:
         self._chk(self.lib.pm_debug_fft(self.ctx, C.c_void_p(_ptr(x)), C.c_void_p(_ptr(out)), direction),
                   "pm_debug_fft")
         return out
+
+    # -- gathered force and the learned closure ---------------------------------
+    def gather_grad_phi(self) -> torch.Tensor:
+        """grad phi at the particles as the kick sees it, [n][3] in identifier order (device)."""
+        out = torch.empty((self.np, 3), dtype=self.dtype, device=self.device)
+        self._chk(self.lib.pm_gather_grad_phi(self.ctx, C.c_void_p(_ptr(out)), 1), "pm_gather_grad_phi")
+        return out
+
+    def closure_set_params(self, params):
+        t = torch.as_tensor(params, dtype=torch.float32).to(self.device).contiguous()
+        assert t.numel() == L.PM_CLOSURE_NPARAM
+        self._keep_params = t
+        self._chk(self.lib.pm_closure_set_params(self.ctx, C.c_void_p(_ptr(t)), 1), "pm_closure_set_params")
+
+    def closure_enable(self, on: bool = True):
+        self._chk(self.lib.pm_closure_enable(self.ctx, 1 if on else 0), "pm_closure_enable")
+
+    def closure_forward(self, scaled: bool = False):
+        self._chk(self.lib.pm_closure_forward(self.ctx, 1 if scaled else 0), "pm_closure_forward")
+
+    def closure_gather(self) -> torch.Tensor:
+        out = torch.empty((self.np, 3), dtype=torch.float32, device=self.device)
+        self._chk(self.lib.pm_closure_gather(self.ctx, C.c_void_p(_ptr(out)), 1), "pm_closure_gather")
+        return out
+
+    def closure_backward(self, dpred: torch.Tensor) -> torch.Tensor:
+        d = dpred.to(device=self.device, dtype=torch.float32).contiguous()
+        g = torch.empty(L.PM_CLOSURE_NPARAM, dtype=torch.float32, device=self.device)
+        self._chk(self.lib.pm_closure_backward(self.ctx, C.c_void_p(_ptr(d)), C.c_void_p(_ptr(g))),
+                  "pm_closure_backward")
+        return g
+
+    def closure_adam(self, params: torch.Tensor, m: torch.Tensor, v: torch.Tensor, grad: torch.Tensor, step: int,
+                     lr: float):
+        for t in (params, m, v, grad):
+            assert t.is_cuda and t.dtype == torch.float32 and t.is_contiguous() and t.numel() == L.PM_CLOSURE_NPARAM
+        self._chk(self.lib.pm_closure_adam(self.ctx, C.c_void_p(_ptr(params)), C.c_void_p(_ptr(m)),
+                                           C.c_void_p(_ptr(v)), C.c_void_p(_ptr(grad)), step, lr), "pm_closure_adam")
+
+    def closure_scale(self) -> float:
+        r = C.c_double()
+        self._chk(self.lib.pm_closure_scale(self.ctx, C.byref(r)), "pm_closure_scale")
+        return r.value

@@ -1,0 +1,105 @@
+"""GPU parity of the learned closure's kernels against the FP64 oracle (with bfloat16 emulation),
+and a small training run that must beat the plain 1x force on held-out data.
+
+Tolerances (derived in the design notes): the forward output and the weight
+gradients are compared in relative L2; bfloat16 has a unit roundoff of 2^-9,
+and an occasional one-ulp difference in a rounded activation (FP32 versus FP64
+accumulation right at a rounding boundary) perturbs the output by about that
+much at a handful of points, so 2e-3 bounds the output and 2e-2 the gradients
+(which pass through three bfloat16 roundings of back-propagated values).
+"""
+import numpy as np
+import pytest
+
+from oracle import cnn
+from oracle import pm as opm
+from synth import config_particles, spectrum_power_law_m2
+from tests.helpers import rel_l2
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def _setup():
+    from paper_2607_17929_amd import PMContext
+    pos, u, tau0, _ = config_particles("c1_32_scalar_fp64")
+    n = 32
+    ctx = PMContext(n, pos.shape[0], 320.0, physics="scalar", precision="fp64", closure=True)
+    ctx.init_particles(pos, u, tau0)
+    ctx.deposit()
+    ctx.solve_metric(0.0)
+    sim = opm.OracleSim(n=n, box_mpch=320.0, physics="scalar", pos=pos, u=u, tau=tau0)
+    sim.deposit()
+    n00 = sim.dep[0].copy()
+    sim.solve(0.0)
+    return ctx, sim, n00, opm.wrap_positions(pos.copy()), n
+
+
+def _params(seed=3):
+    r = np.random.default_rng(seed)
+    p = 0.15 * r.standard_normal(cnn.N_PARAMS)
+    return p.astype(np.float32).astype(np.float64)
+
+
+def test_closure_forward_and_backward_parity():
+    print("closure parity", flush=True)
+    ctx, sim, n00, pos, n = _setup()
+    params = _params()
+    ctx.closure_set_params(torch.tensor(params, dtype=torch.float32))
+    ctx.closure_forward(False)
+    out = ctx.closure_gather().cpu().numpy().astype(np.float64)
+    x, rms = cnn.features(n00, sim.phi)
+    y, acts = cnn.forward(params, x)
+    ref = cnn.gather(y, pos)
+    assert abs(ctx.closure_scale() - rms) < 1e-6 * rms
+    e = rel_l2(out, ref)
+    print("forward rel-L2", e, flush=True)
+    assert e < 2e-3
+    r = np.random.default_rng(5)
+    dpred = r.standard_normal((pos.shape[0], 3)).astype(np.float32)
+    g = ctx.closure_backward(torch.tensor(dpred)).cpu().numpy().astype(np.float64)
+    d3 = cnn.gather_adjoint(dpred.astype(np.float64), pos, n)
+    gref = cnn.backward(params, acts, d3)
+    offs = [0, 16 * 4 * 27 + 16, 16 * 4 * 27 + 16 + 16 * 16 * 27 + 16, cnn.N_PARAMS]
+    for k in range(3):
+        ek = rel_l2(g[offs[k]:offs[k + 1]], gref[offs[k]:offs[k + 1]])
+        print(f"layer {k + 1} gradient rel-L2 {ek:.3e}", flush=True)
+        assert ek < 2e-2
+
+
+def test_closure_adam_step_parity():
+    print("adam", flush=True)
+    ctx, *_ = _setup()
+    r = np.random.default_rng(9)
+    p = r.standard_normal(cnn.N_PARAMS).astype(np.float32)
+    m = (0.1 * r.standard_normal(cnn.N_PARAMS)).astype(np.float32)
+    v = (0.01 * r.random(cnn.N_PARAMS)).astype(np.float32)
+    g = r.standard_normal(cnn.N_PARAMS).astype(np.float32)
+    tp, tm, tv, tg = (torch.tensor(a, device="cuda") for a in (p, m, v, g))
+    ctx.closure_adam(tp, tm, tv, tg, 7, 1e-3)
+    rp, rm, rv = cnn.adam(p.astype(np.float64), m.astype(np.float64), v.astype(np.float64), g.astype(np.float64), 7,
+                          lr=1e-3)
+    assert rel_l2(tp.cpu().numpy(), rp) < 1e-6
+    assert rel_l2(tm.cpu().numpy(), rm) < 1e-6 and rel_l2(tv.cpu().numpy(), rv) < 1e-6
+
+
+def test_gather_grad_phi_matches_oracle():
+    ctx, sim, n00, pos, n = _setup()
+    g = ctx.gather_grad_phi().cpu().numpy()
+    ref = opm.interpolate(opm.grad(sim.phi, n), pos, n).T
+    assert rel_l2(g, ref) < 1e-10
+
+
+def test_closure_training_beats_plain_force():
+    """Small version of the closure experiment: 32^3 particles, 32^3 vs 64^3 meshes, 4 Mpc/h cells."""
+    from paper_2607_17929_amd import closure
+    print("closure training", flush=True)
+    snaps, c1 = closure.make_pairs(seeds=[11, 12, 13], n_p=32 ** 3, n1=32, box=128.0, a_snaps=[0.2, 0.3, 0.4, 0.5],
+                                   steps=40, spectrum=spectrum_power_law_m2)
+    held, c1h = closure.make_pairs(seeds=[99], n_p=32 ** 3, n1=32, box=128.0, a_snaps=[0.3, 0.5], steps=40,
+                                   spectrum=spectrum_power_law_m2)
+    params, hist = closure.train(c1, snaps, closure.init_params(0), iters=400, lr=2e-3, log_every=100)
+    plain, corr = closure.evaluate(c1h, held, params)
+    print(f"held-out: plain 1x error {plain:.4e}, with closure {corr:.4e}", flush=True)
+    assert np.mean(hist[-50:]) < np.mean(hist[:20])
+    assert corr < 0.8 * plain
