@@ -78,7 +78,8 @@ def make_pairs(seeds, n_p: int, n1: int, box: float, a_snaps, steps: int, spectr
                 rms = c1.closure_scale()
                 out.append(Snapshot(pos=p, u=uu, tau=tau, target=((g[1] - g[0]) / rms).float().contiguous()))
                 k += 1
-        log(f"closure pairs: box seed {seed} done in {time.time() - t0:.1f} s ({len(out)} snapshots)")
+        if log:
+            log(f"closure pairs: box seed {seed} done in {time.time() - t0:.1f} s ({len(out)} snapshots)")
     return out, c1
 
 
@@ -121,3 +122,149 @@ def evaluate(ctx1: PMContext, snaps, params: torch.Tensor):
         plain.append(float((s.target * s.target).mean()))
         corr.append(float(((pred - s.target) ** 2).mean()))
     return float(np.mean(plain)), float(np.mean(corr))
+
+
+# ---------------------------------------------------------------------------
+# power spectrum on the GPU (evaluation only) and the full experiment
+# ---------------------------------------------------------------------------
+
+def power_spectrum(pos: torch.Tensor, m: int, box: float):
+    """CIC density on an m^3 mesh (library deposit), library FFT, CIC window deconvolution,
+    shot-noise subtraction and shells of width 2 pi / box; returns (k, P, modes) as numpy."""
+    n_p = pos.shape[0]
+    ctx = PMContext(m, n_p, box, physics="newtonian", precision="fp32")
+    ctx.init_particles(pos, torch.zeros_like(pos, dtype=torch.float32), 1.0)
+    ctx.deposit()  # n00 = a * (CIC count) with a(tau = 1)
+    rho = ctx.get_field("n00", device=True).double()
+    delta = (rho / rho.mean() - 1.0).float()
+    dk = ctx.debug_fft(delta, 1).to(torch.complex128)
+    del ctx
+    kf = 2.0 * math.pi / box
+    mf = torch.fft.fftfreq(m, d=1.0 / m, device=dk.device, dtype=torch.float64)
+    mh = torch.arange(m // 2 + 1, device=dk.device, dtype=torch.float64)
+    mz, my, mx = mf[:, None, None], mf[None, :, None], mh[None, None, :]
+
+    def sinc(t):
+        return torch.where(t == 0, torch.ones_like(t), torch.sin(t) / torch.where(t == 0, torch.ones_like(t), t))
+
+    w = (sinc(math.pi * mx / m) * sinc(math.pi * my / m) * sinc(math.pi * mz / m)) ** 2
+    p = (dk.abs() / w) ** 2 * (box ** 3 / m ** 6) - box ** 3 / n_p
+    kmag = kf * torch.sqrt(mx * mx + my * my + mz * mz)
+    weight = torch.where((mx > 0) & (mx < m / 2), 2.0, 1.0).to(torch.float64).expand_as(kmag)
+    b = torch.round(kmag / kf).long()
+    nb = m // 2 + 1
+    sel = (b >= 1) & (b < nb)
+    cnt = torch.zeros(nb, dtype=torch.float64, device=dk.device).index_add_(0, b[sel], weight[sel])
+    ps = torch.zeros_like(cnt).index_add_(0, b[sel], (weight * p)[sel])
+    ks = torch.zeros_like(cnt).index_add_(0, b[sel], (weight * kmag)[sel])
+    good = cnt > 0
+    return (ks[good] / cnt[good]).cpu().numpy(), (ps[good] / cnt[good]).cpu().numpy(), cnt[good].cpu().numpy()
+
+
+def run_pm(n_mesh: int, pos, u, tau0: float, tau1: float, steps: int, box: float, params=None, log=print):
+    """Evolve with scalar physics on an n_mesh^3 mesh; returns (final positions [device], wall seconds)."""
+    n_p = pos.shape[0]
+    ctx = PMContext(n_mesh, n_p, box, physics="scalar", precision="fp32", closure=params is not None)
+    ctx.init_particles(pos, u, tau0)
+    if params is not None:
+        ctx.closure_set_params(params)
+        ctx.closure_enable(True)
+    dtau = (tau1 - tau0) / steps
+    torch.cuda.synchronize()
+    t0 = time.time()
+    for i in range(steps):
+        ctx.step(dtau)
+        if log and (i + 1) % 25 == 0:
+            ctx.sync()
+            log(f"  mesh {n_mesh}^3{' + closure' if params is not None else ''}: step {i + 1}/{steps}, "
+                f"a = {ctx.time()[1]:.3f}, {time.time() - t0:.1f} s")
+    ctx.sync()
+    wall = time.time() - t0
+    p, _ = ctx.get_particles(device=True)
+    del ctx
+    torch.cuda.empty_cache()
+    return p, wall
+
+
+def experiment(n_app: int = 512, n_train_p: int = 128, train_box: float = 512.0, n_boxes: int = 64,
+               iters: int = 3000, lr: float = 1e-3, log=print):
+    """Train on seeded boxes (1x and 2x meshes), apply to n_app^3 particles on an n_app^3 mesh and compare
+    P(k) and cost with the plain n_app^3 and 2 n_app^3 meshes at a = 0.5."""
+    from synth import spectrum_power_law_m2, zeldovich_particles
+    from synth.ics import eds_a_of_tau
+
+    res = {}
+    # the training boxes share the application's physical spectrum amplitude: for P ~ k^-2 the variance of
+    # the displacement scales as (1/k_f - 1/k_Nyquist), so the rms in cells is rescaled accordingly
+    app_box = 2048.0 * n_app / 512
+    cell = app_box / n_app
+    var = lambda L, N: (L / (2 * math.pi)) * (1 - 2.0 / N)  # noqa: E731
+    rms_train = 0.2 * cell * math.sqrt(var(train_box, n_train_p) / var(app_box, n_app)) / (train_box / n_train_p)
+    t0 = time.time()
+    snaps, c1 = make_pairs(seeds=range(1000, 1000 + n_boxes), n_p=n_train_p ** 3, n1=n_train_p, box=train_box,
+                           a_snaps=list(np.linspace(0.1, 0.5, 8)), steps=100, spectrum=spectrum_power_law_m2,
+                           rms_cells=rms_train, log=log if n_boxes <= 8 else None)
+    res["pairs_s"] = time.time() - t0
+    log(f"{len(snaps)} training snapshots in {res['pairs_s']:.1f} s (rms displacement {rms_train:.3f} cells)")
+    hold = snaps[-8:]
+    t0 = time.time()
+    params, hist = train(c1, snaps[:-8], init_params(0), iters=iters, lr=lr, log=log, log_every=500)
+    res["train_s"] = time.time() - t0
+    res["heldout_plain"], res["heldout_closure"] = evaluate(c1, hold, params)
+    log(f"trained in {res['train_s']:.1f} s; held-out force error: plain {res['heldout_plain']:.4e}, "
+        f"closure {res['heldout_closure']:.4e}")
+    del c1, snaps
+    torch.cuda.empty_cache()
+    # application
+    tau0, tau1 = tau_of_a(app_box, 0.02), tau_of_a(app_box, 0.5)
+    steps = 100
+    dtau = (tau1 - tau0) / steps
+    pos, u = zeldovich_particles(n_app, 3, spectrum_power_law_m2, app_box, 0.2, 0.02, 0.02,
+                                 eds_a_of_tau(tau0 - 0.5 * dtau, app_box))
+    pos_d = torch.tensor(pos, device="cuda")
+    u_d = torch.tensor(u, device="cuda", dtype=torch.float32)
+    del pos, u
+    out = {}
+    for label, mesh, prm in (("plain_1x", n_app, None), ("closure_1x", n_app, params), ("plain_2x", 2 * n_app, None)):
+        p, wall = run_pm(mesh, pos_d, u_d, tau0, tau1, steps, app_box, prm, log=log)
+        k, pk, cnt = power_spectrum(p, n_app, app_box)
+        out[label] = (k, pk, wall)
+        log(f"{label}: {wall:.1f} s for {steps} steps")
+        del p
+        torch.cuda.empty_cache()
+    k = out["plain_2x"][0]
+    kmax = math.pi / (2.0 * cell)  # half the 1x Nyquist frequency
+    sel = k <= kmax
+    ref = out["plain_2x"][1]
+    for label in ("plain_1x", "closure_1x"):
+        r = out[label][1][sel] / ref[sel] - 1.0
+        res[f"{label}_maxdev"] = float(np.max(np.abs(r)))
+        res[f"{label}_ratio"] = [float(v) for v in r]
+    res["k"] = [float(v) for v in k[sel]]
+    res["kmax_half_nyquist"] = kmax
+    for label in out:
+        res[f"{label}_wall_s"] = out[label][2]
+    res["loss_first"], res["loss_last"] = float(np.mean(hist[:50])), float(np.mean(hist[-50:]))
+    res["pass_2pct"] = res["closure_1x_maxdev"] <= 0.02
+    res["gain"] = res["closure_1x_maxdev"] < res["plain_1x_maxdev"]
+    res["cheaper_than_2x"] = out["closure_1x"][2] < out["plain_2x"][2]
+    return res, params
+
+
+if __name__ == "__main__":
+    import argparse
+    import json
+    import os
+
+    ap = argparse.ArgumentParser(description="learned closure experiment")
+    ap.add_argument("--n-app", type=int, default=512)
+    ap.add_argument("--boxes", type=int, default=64)
+    ap.add_argument("--iters", type=int, default=3000)
+    ap.add_argument("--out", default="gpurun_out/closure_experiment.json")
+    a = ap.parse_args()
+    res, params = experiment(n_app=a.n_app, n_boxes=a.boxes, iters=a.iters, log=lambda s: print(s, flush=True))
+    os.makedirs(os.path.dirname(a.out) or ".", exist_ok=True)
+    with open(a.out, "w") as f:
+        json.dump(res, f, indent=1)
+    np.save(os.path.splitext(a.out)[0] + "_params.npy", params.cpu().numpy())
+    print(json.dumps({k: v for k, v in res.items() if not isinstance(v, list)}), flush=True)
