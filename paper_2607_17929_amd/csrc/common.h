@@ -90,11 +90,35 @@ __host__ __device__ constexpr int stage_ns(int m, int s) {
 
 __device__ __forceinline__ int wrapi(int i, int n) { return i & (n - 1); }
 
+// four values read or written as one aligned LDS access
+template <typename T> struct alignas(4 * sizeof(T)) V4 { T x, y, z, w; };
+
 // Reciprocal and reciprocal square root: the FP32 path uses the hardware
 // instructions (about 1 ulp), the FP64 path the correctly rounded operations.
 template <typename T> __device__ __forceinline__ T rcp(T x) { return (T)1 / x; }
 template <> __device__ __forceinline__ float rcp<float>(float x) { return __builtin_amdgcn_rcpf(x); }
 template <typename T> __device__ __forceinline__ T rsqrt_(T x) { return (T)1 / sqrt(x); }
 template <> __device__ __forceinline__ float rsqrt_<float>(float x) { return __builtin_amdgcn_rsqf(x); }
+
+// Workgroups of a launch go to the 8 XCDs in turn (workgroup b to XCD b mod 8),
+// and each XCD has its own L2.  xcd_remap turns the hardware index into a
+// logical one under which every XCD walks one contiguous range, so that
+// neighbouring workgroups -- which share halo data or output cache lines --
+// meet in the same L2.  A bijection of [0, nb) for any nb.
+__device__ __forceinline__ uint32_t xcd_remap(uint32_t b, uint32_t nb) {
+  constexpr uint32_t NX = 8;
+  const uint32_t q = nb / NX, r = nb % NX, x = b % NX;
+  return x * q + min(x, r) + b / NX;
+}
+
+// the logical 3D workgroup coordinate of a 3D launch (x fastest)
+__device__ __forceinline__ void xcd_block3(int& bx, int& by, int& bz) {
+  const uint32_t gx = gridDim.x, gy = gridDim.y;
+  const uint32_t b = (blockIdx.z * gy + blockIdx.y) * gx + blockIdx.x;
+  const uint32_t l = xcd_remap(b, gx * gy * gridDim.z);
+  bx = (int)(l % gx);
+  by = (int)((l / gx) % gy);
+  bz = (int)(l / (gx * gy));
+}
 
 }  // namespace gpm

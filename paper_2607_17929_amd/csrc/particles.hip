@@ -92,13 +92,16 @@ __global__ __launch_bounds__(DEP_NT) void deposit_kernel(Particles<T> p, const u
                                                          T a, T* __restrict__ dep, double* __restrict__ esum) {
   constexpr int CAP = dep_capacity<T>();
   constexpr int TX = DEP_TX, TY = DEP_TY, TZ = DEP_TZ, CX = DEP_CX, ROWS = DEP_ROWS, GW = TX + 3;
-  __shared__ T sfx[CAP], sfy[CAP], sfz[CAP], sux[CAP], suy[CAP], suz[CAP], se[CAP], sie[CAP];
+  // staged per particle: (cell fractions, 1/e) and (e, u), one 4-vector each
+  __shared__ V4<T> sfr[CAP], smo[NC > 1 ? CAP : 1];
   __shared__ uint32_t cstart[ROWS * CX];  // row-relative staged start of local cell (row, lx); lx = 0 is cell x0 - 1
   __shared__ uint32_t gcs[ROWS * GW];     // halo start/end, then starts of cells x0 .. x0 + TX
   __shared__ uint32_t row_off[ROWS + 1];
   __shared__ double red[DEP_NT];
   const int m = n - 1;
-  const int x0 = blockIdx.x * TX, y0 = blockIdx.y * TY, z0 = blockIdx.z * TZ;
+  int bx, by, bz;
+  xcd_block3(bx, by, bz);
+  const int x0 = bx * TX, y0 = by * TY, z0 = bz * TZ;
   const int tid = threadIdx.x;
   // 1. cell_start values of every touching cell, read in parallel.  Local cell (lx, ly, lz) is
   //    global (x0 - 1 + lx, y0 - 1 + ly, z0 - 1 + lz); on a 16^3 mesh the block spans x and the
@@ -147,16 +150,26 @@ __global__ __launch_bounds__(DEP_NT) void deposit_kernel(Particles<T> p, const u
       const uint32_t gi = (k < halo_n) ? g[0] + k : g[2] + (k - halo_n);
       const double sx = p.px[gi] * (double)n, sy = p.py[gi] * (double)n, sz = p.pz[gi] * (double)n;
       const uint32_t l = i - c0;
-      sfx[l] = (T)(sx - floor(sx));
-      sfy[l] = (T)(sy - floor(sy));
-      sfz[l] = (T)(sz - floor(sz));
+      V4<T> fr;
+      fr.x = (T)(sx - floor(sx));
+      fr.y = (T)(sy - floor(sy));
+      fr.z = (T)(sz - floor(sz));
+      fr.w = (T)0;
       if constexpr (NC > 1) {
         const T ux = p.ux[gi], uy = p.uy[gi], uz = p.uz[gi];
-        sux[l] = ux; suy[l] = uy; suz[l] = uz;
         const T e = REL ? sqrt(a * a + ux * ux + uy * uy + uz * uz) : a;
-        se[l] = e;
-        sie[l] = rcp(e);
+        fr.w = rcp(e);
+        V4<T> mo;
+        mo.x = e; mo.y = ux; mo.z = uy; mo.w = uz;
+        smo[l] = mo;
+        // FP64 energy sum over the particles of the block's own cells (not the halo layers)
+        const int ly = r % (TY + 1), lz = r / (TY + 1);
+        if (ly > 0 && lz > 0 && k >= halo_n) {
+          const double dx = ux, dy = uy, dz = uz;
+          e_own += REL ? sqrt(ad * ad + dx * dx + dy * dy + dz * dz) : ad;
+        }
       }
+      sfr[l] = fr;
     }
     __syncthreads();
 #pragma unroll
@@ -174,27 +187,23 @@ __global__ __launch_bounds__(DEP_NT) void deposit_kernel(Particles<T> p, const u
           const uint32_t s1 = ro + cstart[cb + 1];
           const uint32_t s2 = ro + ((lvx + 2 <= TX) ? cstart[cb + 2] : row_off[rr + 1] - ro);
           const uint32_t b = max(ro + cstart[cb], c0), e = min(s2, c1);
-          const bool own = dy == 1 && dz == 1;
           for (uint32_t i = b; i < e; ++i) {
             const uint32_t l = i - c0;
             const bool upper_x = i < s1;
-            const T fx = sfx[l];
-            const T wx = upper_x ? fx : (T)1 - fx;
-            const T wy = dy == 0 ? sfy[l] : (T)1 - sfy[l];
-            const T wz = dz == 0 ? sfz[l] : (T)1 - sfz[l];
+            const V4<T> fr = sfr[l];
+            const T wx = upper_x ? fr.x : (T)1 - fr.x;
+            const T wy = dy == 0 ? fr.y : (T)1 - fr.y;
+            const T wz = dz == 0 ? fr.z : (T)1 - fr.z;
             const T w = wx * wy * wz;
             if constexpr (NC == 1) {
               acc[k][0] += w * a;
             } else {
-              const T ux = sux[l], uy = suy[l], uz = suz[l], e_p = se[l];
-              const T wi = w * sie[l];
-              acc[k][0] += w * e_p; acc[k][1] += w * ux; acc[k][2] += w * uy; acc[k][3] += w * uz;
-              acc[k][4] += wi * ux * ux; acc[k][5] += wi * ux * uy; acc[k][6] += wi * ux * uz;
-              acc[k][7] += wi * uy * uy; acc[k][8] += wi * uy * uz; acc[k][9] += wi * uz * uz;
-              if (own && !upper_x) {
-                const double dx = ux, dy2 = uy, dz2 = uz;
-                e_own += REL ? sqrt(ad * ad + dx * dx + dy2 * dy2 + dz2 * dz2) : ad;
-              }
+              const V4<T> mo = smo[l];
+              const T wi = w * fr.w;
+              const T wux = wi * mo.y, wuy = wi * mo.z, wuz = wi * mo.w;
+              acc[k][0] += w * mo.x; acc[k][1] += w * mo.y; acc[k][2] += w * mo.z; acc[k][3] += w * mo.w;
+              acc[k][4] += wux * mo.y; acc[k][5] += wux * mo.z; acc[k][6] += wux * mo.w;
+              acc[k][7] += wuy * mo.z; acc[k][8] += wuy * mo.w; acc[k][9] += wuz * mo.w;
             }
           }
         }
@@ -219,7 +228,7 @@ __global__ __launch_bounds__(DEP_NT) void deposit_kernel(Particles<T> p, const u
       if (tid < w) red[tid] += red[tid + w];
       __syncthreads();
     }
-    if (tid == 0) esum[(blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x] = red[0];
+    if (tid == 0) esum[(bz * gridDim.y + by) * gridDim.x + bx] = red[0];
   }
 }
 
@@ -292,7 +301,9 @@ __global__ __launch_bounds__(KD_NT) void kick_drift_kernel(Particles<T> p, const
   __shared__ T tile[NF][KD_G];
   __shared__ uint32_t rbeg[KD_TY * KD_TZ], roff[KD_TY * KD_TZ + 1];
   const int m = n - 1;
-  const int x0 = blockIdx.x * KD_TX, y0 = blockIdx.y * KD_TY, z0 = blockIdx.z * KD_TZ;
+  int bx, by, bz;
+  xcd_block3(bx, by, bz);
+  const int x0 = bx * KD_TX, y0 = by * KD_TY, z0 = bz * KD_TZ;
   const int tid = threadIdx.x;
   const long nn = (long)n * n;
   // particle rows of the block
@@ -549,7 +560,7 @@ template <typename T>
 __global__ __launch_bounds__(256) void scatter_kernel(Particles<T> s, Particles<T> d, long np,
                                                       const uint32_t* __restrict__ key, const uint32_t* __restrict__ rank,
                                                       const uint32_t* __restrict__ cell_start) {
-  const long base = (long)blockIdx.x * (256 * SC_PER) + threadIdx.x;
+  const long base = (long)xcd_remap(blockIdx.x, gridDim.x) * (256 * SC_PER) + threadIdx.x;
   uint32_t k[SC_PER], r[SC_PER];
   long j[SC_PER];
 #pragma unroll
