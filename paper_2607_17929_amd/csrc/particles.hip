@@ -87,32 +87,70 @@ static_assert(DEP_NV % DEP_NT == 0, "whole vertices per thread");
 
 template <typename T> constexpr int dep_capacity() { return sizeof(T) == 4 ? 1024 : 512; }
 
+// largest r in [0, R) with off[r] <= i, for a non-decreasing off with off[0] = 0 <= i (R <= 64)
+template <int R>
+__device__ __forceinline__ int row_of(const uint32_t* off, uint32_t i) {
+  int lo = 0;
+#pragma unroll
+  for (int step = 32; step > 0; step >>= 1)
+    if (step < R && lo + step < R && off[lo + step] <= i) lo += step;
+  return lo;
+}
+
+// exclusive prefix of c over the first wave's lanes (R <= 64 rows): off[0] = 0, off[r + 1] = sum_{q <= r} c_q
+template <int R>
+__device__ __forceinline__ void wave_row_offsets(uint32_t c, uint32_t* off) {
+  const int lane = threadIdx.x;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const uint32_t t = __shfl_up(c, d);
+    if (lane >= d) c += t;
+  }
+  if (lane < R) off[lane + 1] = c;
+  if (lane == 0) off[0] = 0;
+}
+
 template <typename T, int NC, bool REL>
 __global__ __launch_bounds__(DEP_NT) void deposit_kernel(Particles<T> p, const uint32_t* __restrict__ cell_start, int n,
                                                          T a, T* __restrict__ dep, double* __restrict__ esum) {
   constexpr int CAP = dep_capacity<T>();
-  constexpr int TX = DEP_TX, TY = DEP_TY, TZ = DEP_TZ, CX = DEP_CX, ROWS = DEP_ROWS, GW = TX + 3;
+  constexpr int TX = DEP_TX, TY = DEP_TY, CX = DEP_CX, ROWS = DEP_ROWS, GW = TX + 3;
+  constexpr int NQ = (ROWS * GW + DEP_NT - 1) / DEP_NT;  // cell_start reads per thread
+  constexpr int SPT = CAP / DEP_NT;                      // staged particles per thread and chunk
+  static_assert(ROWS <= 64 && CAP % DEP_NT == 0, "row scan in one wave, whole staging rounds");
   // staged per particle: (cell fractions, 1/e) and (e, u), one 4-vector each
   __shared__ V4<T> sfr[CAP], smo[NC > 1 ? CAP : 1];
   __shared__ uint32_t cstart[ROWS * CX];  // row-relative staged start of local cell (row, lx); lx = 0 is cell x0 - 1
   __shared__ uint32_t gcs[ROWS * GW];     // halo start/end, then starts of cells x0 .. x0 + TX
   __shared__ uint32_t row_off[ROWS + 1];
-  __shared__ double red[DEP_NT];
+  __shared__ double red[DEP_NT / 64];
   const int m = n - 1;
   int bx, by, bz;
   xcd_block3(bx, by, bz);
-  const int x0 = bx * TX, y0 = by * TY, z0 = bz * TZ;
+  const int x0 = bx * TX, y0 = by * TY, z0 = bz * DEP_TZ;
   const int tid = threadIdx.x;
-  // 1. cell_start values of every touching cell, read in parallel.  Local cell (lx, ly, lz) is
-  //    global (x0 - 1 + lx, y0 - 1 + ly, z0 - 1 + lz); on a 16^3 mesh the block spans x and the
+  // 1. cell_start values of every touching cell, all reads in flight at once.  Local cell (lx, ly, lz)
+  //    is global (x0 - 1 + lx, y0 - 1 + ly, z0 - 1 + lz); on a 16^3 mesh the block spans x and the
   //    first and last local x-layers are the same cells, but each vertex reads each cell once.
-  for (int q = tid; q < ROWS * GW; q += DEP_NT) {
-    const int r = q / GW, j = q % GW;
-    const int ly = r % (TY + 1), lz = r / (TY + 1);
-    const int cy = (y0 - 1 + ly) & m, cz = (z0 - 1 + lz) & m;
-    const uint32_t rb = ((uint32_t)cz * n + cy) * (uint32_t)n;
-    const uint32_t hc = rb + ((x0 - 1) & m);
-    gcs[q] = cell_start[j == 0 ? hc : (j == 1 ? hc + 1 : rb + x0 + (j - 2))];
+  {
+    uint32_t gv[NQ];
+#pragma unroll
+    for (int k = 0; k < NQ; ++k) {
+      const int q = tid + k * DEP_NT;
+      if (q < ROWS * GW) {
+        const int r = q / GW, j = q % GW;
+        const int ly = r % (TY + 1), lz = r / (TY + 1);
+        const int cy = (y0 - 1 + ly) & m, cz = (z0 - 1 + lz) & m;
+        const uint32_t rb = ((uint32_t)cz * n + cy) * (uint32_t)n;
+        const uint32_t hc = rb + ((x0 - 1) & m);
+        gv[k] = cell_start[j == 0 ? hc : (j == 1 ? hc + 1 : rb + x0 + (j - 2))];
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < NQ; ++k) {
+      const int q = tid + k * DEP_NT;
+      if (q < ROWS * GW) gcs[q] = gv[k];
+    }
   }
   __syncthreads();
   for (int q = tid; q < ROWS * CX; q += DEP_NT) {
@@ -120,14 +158,13 @@ __global__ __launch_bounds__(DEP_NT) void deposit_kernel(Particles<T> p, const u
     const uint32_t* g = gcs + r * GW;
     cstart[q] = (lx == 0) ? 0u : (g[1] - g[0]) + (g[lx + 1] - g[2]);
   }
-  if (tid == 0) {
-    uint32_t acc = 0;
-    row_off[0] = 0;
-    for (int r = 0; r < ROWS; ++r) {
-      const uint32_t* g = gcs + r * GW;
-      acc += (g[1] - g[0]) + (g[TX + 2] - g[2]);
-      row_off[r + 1] = acc;
+  if (tid < 64) {
+    uint32_t c = 0;
+    if (tid < ROWS) {
+      const uint32_t* g = gcs + tid * GW;
+      c = (g[1] - g[0]) + (g[TX + 2] - g[2]);
     }
+    wave_row_offsets<ROWS>(c, row_off);
   }
   __syncthreads();
   const uint32_t total = row_off[ROWS];
@@ -141,35 +178,58 @@ __global__ __launch_bounds__(DEP_NT) void deposit_kernel(Particles<T> p, const u
   double e_own = 0.0;
   for (uint32_t c0 = 0; c0 < total; c0 += CAP) {
     const uint32_t c1 = min(total, c0 + (uint32_t)CAP);
-    int r = 0;
-    for (uint32_t i = c0 + tid; i < c1; i += DEP_NT) {
-      while (row_off[r + 1] <= i) ++r;
-      const uint32_t k = i - row_off[r];
-      const uint32_t* g = gcs + r * GW;
-      const uint32_t halo_n = g[1] - g[0];
-      const uint32_t gi = (k < halo_n) ? g[0] + k : g[2] + (k - halo_n);
-      const double sx = p.px[gi] * (double)n, sy = p.py[gi] * (double)n, sz = p.pz[gi] * (double)n;
-      const uint32_t l = i - c0;
-      V4<T> fr;
-      fr.x = (T)(sx - floor(sx));
-      fr.y = (T)(sy - floor(sy));
-      fr.z = (T)(sz - floor(sz));
-      fr.w = (T)0;
-      if constexpr (NC > 1) {
-        const T ux = p.ux[gi], uy = p.uy[gi], uz = p.uz[gi];
-        const T e = REL ? sqrt(a * a + ux * ux + uy * uy + uz * uz) : a;
-        fr.w = rcp(e);
-        V4<T> mo;
-        mo.x = e; mo.y = ux; mo.z = uy; mo.w = uz;
-        smo[l] = mo;
-        // FP64 energy sum over the particles of the block's own cells (not the halo layers)
-        const int ly = r % (TY + 1), lz = r / (TY + 1);
-        if (ly > 0 && lz > 0 && k >= halo_n) {
-          const double dx = ux, dy = uy, dz = uz;
-          e_own += REL ? sqrt(ad * ad + dx * dx + dy * dy + dz * dz) : ad;
-        }
+    // staging: locate, load (all loads of the thread in flight), then convert and store
+    uint32_t gi[SPT];
+    bool own[SPT];
+#pragma unroll
+    for (int s2 = 0; s2 < SPT; ++s2) {
+      const uint32_t i = c0 + tid + s2 * DEP_NT;
+      gi[s2] = 0;
+      own[s2] = false;
+      if (i < c1) {
+        const int r = row_of<ROWS>(row_off, i);
+        const uint32_t k = i - row_off[r];
+        const uint32_t* g = gcs + r * GW;
+        const uint32_t halo_n = g[1] - g[0];
+        gi[s2] = (k < halo_n) ? g[0] + k : g[2] + (k - halo_n);
+        // the block's own cells: not the halo layers below it in y, z or x
+        own[s2] = (r % (TY + 1)) > 0 && (r / (TY + 1)) > 0 && k >= halo_n;
       }
-      sfr[l] = fr;
+    }
+    double px[SPT], py[SPT], pz[SPT];
+    T ux[SPT], uy[SPT], uz[SPT];
+#pragma unroll
+    for (int s2 = 0; s2 < SPT; ++s2) {
+      if (c0 + tid + s2 * DEP_NT < c1) {
+        px[s2] = p.px[gi[s2]]; py[s2] = p.py[gi[s2]]; pz[s2] = p.pz[gi[s2]];
+        if constexpr (NC > 1) { ux[s2] = p.ux[gi[s2]]; uy[s2] = p.uy[gi[s2]]; uz[s2] = p.uz[gi[s2]]; }
+      }
+    }
+#pragma unroll
+    for (int s2 = 0; s2 < SPT; ++s2) {
+      if (c0 + tid + s2 * DEP_NT < c1) {
+        const uint32_t l = tid + s2 * DEP_NT;
+        const double sx = px[s2] * (double)n, sy = py[s2] * (double)n, sz = pz[s2] * (double)n;
+        V4<T> fr;
+        fr.x = (T)(sx - floor(sx));
+        fr.y = (T)(sy - floor(sy));
+        fr.z = (T)(sz - floor(sz));
+        fr.w = (T)0;
+        if constexpr (NC > 1) {
+          const T vx = ux[s2], vy = uy[s2], vz = uz[s2];
+          const T e = REL ? sqrt(a * a + vx * vx + vy * vy + vz * vz) : a;
+          fr.w = rcp(e);
+          V4<T> mo;
+          mo.x = e; mo.y = vx; mo.z = vy; mo.w = vz;
+          smo[l] = mo;
+          // FP64 energy sum over the particles of the block's own cells
+          if (own[s2]) {
+            const double dx = vx, dy = vy, dz = vz;
+            e_own += REL ? sqrt(ad * ad + dx * dx + dy * dy + dz * dz) : ad;
+          }
+        }
+        sfr[l] = fr;
+      }
     }
     __syncthreads();
 #pragma unroll
@@ -222,13 +282,17 @@ __global__ __launch_bounds__(DEP_NT) void deposit_kernel(Particles<T> p, const u
     for (int c = 0; c < NC; ++c) dep[c * n3 + o] = acc[k][c];
   }
   if (esum) {
-    red[tid] = e_own;
+    // fixed-order reduction: within each wave, then the waves' sums in order
+#pragma unroll
+    for (int d = 32; d > 0; d >>= 1) e_own += __shfl_down(e_own, d);
+    if ((tid & 63) == 0) red[tid >> 6] = e_own;
     __syncthreads();
-    for (int w = DEP_NT / 2; w > 0; w >>= 1) {
-      if (tid < w) red[tid] += red[tid + w];
-      __syncthreads();
+    if (tid == 0) {
+      double t = 0.0;
+#pragma unroll
+      for (int w = 0; w < DEP_NT / 64; ++w) t += red[w];
+      esum[(bz * gridDim.y + by) * gridDim.x + bx] = t;
     }
-    if (tid == 0) esum[(bz * gridDim.y + by) * gridDim.x + bx] = red[0];
   }
 }
 
@@ -293,57 +357,106 @@ __device__ __forceinline__ void gather_lds(const T* __restrict__ f, int zo0, int
   g[2] = gz * half_n;
 }
 
+// Rank of a particle among those that reach the same cell.  The store is
+// sorted by cell and few particles change cell in a step, so equal keys mostly
+// sit in consecutive lanes: each such run of the wave takes its slots with one
+// atomicAdd of its length (one per run instead of one per particle, which
+// serialises on the counter of a crowded cell).  Call with the active lanes in
+// lockstep; every key gets a distinct rank in [0, final count of its cell).
+__device__ __forceinline__ uint32_t rank_in_cell(uint32_t* cnt, uint32_t k) {
+  const int lane = (int)__lane_id();
+  const uint64_t act = __ballot(1);
+  const uint32_t kp = __shfl_up(k, 1);
+  const bool joins_prev = lane > 0 && ((act >> (lane - 1)) & 1ull) && kp == k;
+  const uint64_t heads = __ballot(!joins_prev);
+  const uint64_t upto = (2ull << lane) - 1ull;  // lanes 0 .. lane (all ones for lane 63)
+  const int head = 63 - __clzll((long long)(heads & upto));
+  const uint64_t after = (heads | ~act) & ~upto;  // run boundaries above this lane
+  const int next = after ? __ffsll((long long)after) - 1 : 64;
+  uint32_t base = 0;
+  if (head == lane) base = atomicAdd(&cnt[k], (uint32_t)(next - head));
+  base = __shfl(base, head);
+  return base + (uint32_t)(lane - head);
+}
+
 template <typename T, int MODE>
 __global__ __launch_bounds__(KD_NT) void kick_drift_kernel(Particles<T> p, const uint32_t* __restrict__ cell_start, int n,
                                                            GatherArgs<T> ga, uint32_t* key, uint32_t* rank,
                                                            uint32_t* cnt, int* err) {
   constexpr int NF = MODE == MODE_FULL ? 5 : (MODE == MODE_SCALAR ? 2 : 1);
+  constexpr int NR = KD_TY * KD_TZ;                   // particle rows of the block
+  constexpr int NTL = (KD_G + KD_NT - 1) / KD_NT;     // tile entries per thread and field
+  static_assert(NR <= 64, "row scan in one wave");
   __shared__ T tile[NF][KD_G];
-  __shared__ uint32_t rbeg[KD_TY * KD_TZ], roff[KD_TY * KD_TZ + 1];
+  __shared__ uint32_t rbeg[NR], roff[NR + 1];
   const int m = n - 1;
   int bx, by, bz;
   xcd_block3(bx, by, bz);
   const int x0 = bx * KD_TX, y0 = by * KD_TY, z0 = bz * KD_TZ;
   const int tid = threadIdx.x;
   const long nn = (long)n * n;
-  // particle rows of the block
-  if (tid < KD_TY * KD_TZ) {
-    const int ly = tid % KD_TY, lz = tid / KD_TY;
-    const long rb = ((long)(z0 + lz) * n + (y0 + ly)) * n;
-    const uint32_t b = cell_start[rb + x0], e = cell_start[rb + x0 + KD_TX];
-    rbeg[tid] = b;
-    roff[tid + 1] = e - b;
-  }
-  // field tile with periodic wrap: local (gx, gy, gz) <-> global (x0 - 1 + gx, ...); lanes run along
-  // x in groups of 32 (KD_GX = 19 of them load), one (gy, gz) row per group
+  // field tile with periodic wrap: local (gx, gy, gz) <-> global (x0 - 1 + gx, ...), x fastest;
+  // every read of the thread is issued before the first is used
   const T* src[5] = {ga.phi, ga.chi, ga.bx, ga.by, ga.bz};
-  {
-    const int lane = tid & 31, grp = tid >> 5;
-    const int gxo = (x0 - 1 + lane) & m;
-    for (int row = grp; row < KD_GY * KD_GZ; row += KD_NT / 32) {
-      const int gy = row % KD_GY, gz = row / KD_GY;
-      const long o = (long)((z0 - 1 + gz) & m) * nn + (long)((y0 - 1 + gy) & m) * n + gxo;
-      if (lane < KD_GX) {
+  T tv[NF][NTL];
 #pragma unroll
-        for (int f = 0; f < NF; ++f) tile[f][row * KD_GX + lane] = src[f][o];
-      }
+  for (int k = 0; k < NTL; ++k) {
+    const int q = tid + k * KD_NT;
+    if (q < KD_G) {
+      const int gx = q % KD_GX, row = q / KD_GX;
+      const int gy = row % KD_GY, gz = row / KD_GY;
+      const long o = (long)((z0 - 1 + gz) & m) * nn + (long)((y0 - 1 + gy) & m) * n + ((x0 - 1 + gx) & m);
+#pragma unroll
+      for (int f = 0; f < NF; ++f) tv[f][k] = src[f][o];
+    }
+  }
+  // particle rows of the block: start of each row in the sorted store and the prefix of their lengths
+  if (tid < 64) {
+    uint32_t c = 0;
+    if (tid < NR) {
+      const int ly = tid % KD_TY, lz = tid / KD_TY;
+      const long rb = ((long)(z0 + lz) * n + (y0 + ly)) * n;
+      const uint32_t b = cell_start[rb + x0], e = cell_start[rb + x0 + KD_TX];
+      rbeg[tid] = b;
+      c = e - b;
+    }
+    wave_row_offsets<NR>(c, roff);
+  }
+#pragma unroll
+  for (int k = 0; k < NTL; ++k) {
+    const int q = tid + k * KD_NT;
+    if (q < KD_G) {
+#pragma unroll
+      for (int f = 0; f < NF; ++f) tile[f][q] = tv[f][k];
     }
   }
   __syncthreads();
-  if (tid == 0) {
-    roff[0] = 0;
-    for (int r = 1; r <= KD_TY * KD_TZ; ++r) roff[r] += roff[r - 1];
-  }
-  __syncthreads();
-  const uint32_t total = roff[KD_TY * KD_TZ];
+  const uint32_t total = roff[NR];
   const T hn = (T)(0.5 * n);
   const T dt = (T)ga.dtau;
   const T a = (T)ga.a, ah = (T)ga.a_half;
-  int r = 0;
+  // each thread takes particles tid, tid + KD_NT, ...; the next one's state is read while the
+  // current one is processed
+  uint32_t pin = 0;
+  double xn = 0.0, yn = 0.0, zn = 0.0;
+  T uxn = 0, uyn = 0, uzn = 0;
+  if ((uint32_t)tid < total) {
+    const int r = row_of<NR>(roff, tid);
+    pin = rbeg[r] + (tid - roff[r]);
+    xn = p.px[pin]; yn = p.py[pin]; zn = p.pz[pin];
+    uxn = p.ux[pin]; uyn = p.uy[pin]; uzn = p.uz[pin];
+  }
   for (uint32_t i = tid; i < total; i += KD_NT) {
-    while (roff[r + 1] <= i) ++r;  // i increases, so the row index only moves forward
-    const uint32_t pi = rbeg[r] + (i - roff[r]);
-    double x = p.px[pi], y = p.py[pi], z = p.pz[pi];
+    const uint32_t pi = pin;
+    double x = xn, y = yn, z = zn;
+    T ux = uxn, uy = uyn, uz = uzn;
+    const uint32_t inx = i + KD_NT;
+    if (inx < total) {
+      const int r = row_of<NR>(roff, inx);
+      pin = rbeg[r] + (inx - roff[r]);
+      xn = p.px[pin]; yn = p.py[pin]; zn = p.pz[pin];
+      uxn = p.ux[pin]; uyn = p.uy[pin]; uzn = p.uz[pin];
+    }
     int ix, iy, iz;
     double fxd, fyd, fzd;
     cell_of(x, n, ix, fxd);
@@ -371,7 +484,6 @@ __global__ __launch_bounds__(KD_NT) void kick_drift_kernel(Particles<T> p, const
         gphi[c] += acc;
       }
     }
-    T ux = p.ux[pi], uy = p.uy[pi], uz = p.uz[pi];
     T vx, vy, vz;
     if constexpr (MODE == MODE_NEWTONIAN) {
       ux -= dt * a * gphi[0];
@@ -422,7 +534,7 @@ __global__ __launch_bounds__(KD_NT) void kick_drift_kernel(Particles<T> p, const
     p.ux[pi] = ux; p.uy[pi] = uy; p.uz[pi] = uz;
     const uint32_t k = cell_key(x, y, z, n);
     key[pi] = k;
-    rank[pi] = atomicAdd(&cnt[k], 1u);
+    rank[pi] = rank_in_cell(cnt, k);
   }
 }
 
@@ -561,26 +673,30 @@ __global__ __launch_bounds__(256) void scatter_kernel(Particles<T> s, Particles<
                                                       const uint32_t* __restrict__ key, const uint32_t* __restrict__ rank,
                                                       const uint32_t* __restrict__ cell_start) {
   const long base = (long)xcd_remap(blockIdx.x, gridDim.x) * (256 * SC_PER) + threadIdx.x;
-  uint32_t k[SC_PER], r[SC_PER];
-  long j[SC_PER];
-#pragma unroll
-  for (int q = 0; q < SC_PER; ++q) {
-    const long i = base + q * 256;
-    k[q] = (i < np) ? key[i] : 0u;
-    r[q] = (i < np) ? rank[i] : 0u;
-  }
-#pragma unroll
-  for (int q = 0; q < SC_PER; ++q) j[q] = (long)cell_start[k[q]] + r[q];
+  // every read that does not depend on the destination is issued first
+  uint32_t k[SC_PER], r[SC_PER], id[SC_PER];
+  double x[SC_PER], y[SC_PER], z[SC_PER];
+  T ux[SC_PER], uy[SC_PER], uz[SC_PER];
 #pragma unroll
   for (int q = 0; q < SC_PER; ++q) {
     const long i = base + q * 256;
     if (i < np) {
-      const double x = s.px[i], y = s.py[i], z = s.pz[i];
-      const T ux = s.ux[i], uy = s.uy[i], uz = s.uz[i];
-      const uint32_t id = s.id[i];
-      d.px[j[q]] = x; d.py[j[q]] = y; d.pz[j[q]] = z;
-      d.ux[j[q]] = ux; d.uy[j[q]] = uy; d.uz[j[q]] = uz;
-      d.id[j[q]] = id;
+      k[q] = key[i];
+      r[q] = rank[i];
+      x[q] = s.px[i]; y[q] = s.py[i]; z[q] = s.pz[i];
+      ux[q] = s.ux[i]; uy[q] = s.uy[i]; uz[q] = s.uz[i];
+      id[q] = s.id[i];
+    }
+  }
+  long j[SC_PER];
+#pragma unroll
+  for (int q = 0; q < SC_PER; ++q) j[q] = (base + q * 256 < np) ? (long)cell_start[k[q]] + r[q] : 0;
+#pragma unroll
+  for (int q = 0; q < SC_PER; ++q) {
+    if (base + q * 256 < np) {
+      d.px[j[q]] = x[q]; d.py[j[q]] = y[q]; d.pz[j[q]] = z[q];
+      d.ux[j[q]] = ux[q]; d.uy[j[q]] = uy[q]; d.uz[j[q]] = uz[q];
+      d.id[j[q]] = id[q];
     }
   }
 }
