@@ -29,7 +29,7 @@ namespace gpm {
 // [element][column].  Job j -> column j % C (fastest, so a wave touches
 // consecutive LDS words), butterfly index j / C.
 template <typename T, int N, int C, int NT, int S, bool INV, bool FROM_G, bool TO_G>
-__device__ __forceinline__ void col_stage(cplx<T>* sm, cplx<T>* g, long es, int cvalid, const cplx<T>* __restrict__ tw) {
+__device__ __forceinline__ void col_stage(cplx<T>* sm, cplx<T>* g, uint32_t es, const cplx<T>* stw) {
   constexpr int R = stage_radix(N, S);
   constexpr int NS = stage_ns(N, S);
   constexpr int J = N * C / R;
@@ -45,7 +45,7 @@ __device__ __forceinline__ void col_stage(cplx<T>* sm, cplx<T>* g, long es, int 
       for (int r = 0; r < R; ++r) {
         const int e = i + r * (N / R);
         if (FROM_G) {
-          v[p][r] = (col < cvalid) ? g[(long)e * es + col] : mk<T>(0, 0);
+          v[p][r] = g[(uint32_t)e * es + (uint32_t)col];
         } else {
           v[p][r] = sm[e * C + col];
         }
@@ -62,7 +62,7 @@ __device__ __forceinline__ void col_stage(cplx<T>* sm, cplx<T>* g, long es, int 
       if (NS > 1) {
 #pragma unroll
         for (int r = 1; r < R; ++r) {
-          const cplx<T> w = tw[(r * k) * (N / (NS * R))];
+          const cplx<T> w = stw[(r * k) * (N / (NS * R))];
           v[p][r] = INV ? cmulc(v[p][r], w) : cmul(v[p][r], w);
         }
       }
@@ -72,7 +72,7 @@ __device__ __forceinline__ void col_stage(cplx<T>* sm, cplx<T>* g, long es, int 
       for (int r = 0; r < R; ++r) {
         const int e = j0 + r * NS;
         if (TO_G) {
-          if (col < cvalid) g[(long)e * es + col] = v[p][r];
+          g[(uint32_t)e * es + (uint32_t)col] = v[p][r];
         } else {
           sm[e * C + col] = v[p][r];
         }
@@ -83,23 +83,26 @@ __device__ __forceinline__ void col_stage(cplx<T>* sm, cplx<T>* g, long es, int 
 }
 
 template <typename T, int N, int C, int NT, int S, bool INV>
-__device__ __forceinline__ void col_stages(cplx<T>* sm, cplx<T>* g, long es, int cvalid, const cplx<T>* tw) {
+__device__ __forceinline__ void col_stages(cplx<T>* sm, cplx<T>* g, uint32_t es, const cplx<T>* stw) {
   constexpr int NSTG = nstages(N);
   if constexpr (S < NSTG) {
-    col_stage<T, N, C, NT, S, INV, S == 0, S == NSTG - 1>(sm, g, es, cvalid, tw);
-    col_stages<T, N, C, NT, S + 1, INV>(sm, g, es, cvalid, tw);
+    col_stage<T, N, C, NT, S, INV, S == 0, S == NSTG - 1>(sm, g, es, stw);
+    col_stages<T, N, C, NT, S + 1, INV>(sm, g, es, stw);
   }
 }
 
-// grid: x = column tile, y = outer index, z = component
+// grid: x = column tile, y = outer index, z = component.  Rows are padded to a
+// multiple of C columns, so every tile is whole (the padding columns are
+// transformed too and never read).  es < 2^32 elements for every supported n.
 template <typename T, int N, int C, int NT, bool INV>
-__global__ __launch_bounds__(NT) void fft_cols_kernel(cplx<T>* data, long es, long outer_stride, long comp_stride,
-                                                      int ncols, const cplx<T>* __restrict__ tw) {
+__global__ __launch_bounds__(NT) void fft_cols_kernel(cplx<T>* data, uint32_t es, long outer_stride, long comp_stride,
+                                                      const cplx<T>* __restrict__ tw) {
+  static_assert(nstages(N) >= 2, "the first stage's barrier publishes the twiddle table");
   __shared__ cplx<T> sm[N * C];
-  const int col0 = blockIdx.x * C;
-  cplx<T>* g = data + (long)blockIdx.z * comp_stride + (long)blockIdx.y * outer_stride + col0;
-  const int cvalid = min(C, ncols - col0);
-  col_stages<T, N, C, NT, 0, INV>(sm, g, es, cvalid, tw);
+  __shared__ cplx<T> stw[N];
+  for (int j = threadIdx.x; j < N; j += NT) stw[j] = tw[j];
+  cplx<T>* g = data + (long)blockIdx.z * comp_stride + (long)blockIdx.y * outer_stride + (long)blockIdx.x * C;
+  col_stages<T, N, C, NT, 0, INV>(sm, g, es, stw);
 }
 
 // ---------------------------------------------------------------------------
@@ -258,9 +261,11 @@ __global__ __launch_bounds__(NT) void fft_x_r2c_kernel(SrcArgs<T> a, cplx<T>* sp
   constexpr int NSRC = mode_nsrc(MODE);
   constexpr int L = NSRC * RY;
   __shared__ T sm[NSRC * RY * N];
-  __shared__ double red[NT];
+  __shared__ cplx<T> stw[N];
+  __shared__ double red[RY][NT / 64];
   const int y0 = blockIdx.x * RY, z = blockIdx.y;
   const int tid = threadIdx.x;
+  for (int j = tid; j < N; j += NT) stw[j] = tw[j];
   // 1. assemble the sources of RY rows into LDS rows [c][r][x]
   double acc[RY];
 #pragma unroll
@@ -273,23 +278,26 @@ __global__ __launch_bounds__(NT) void fft_x_r2c_kernel(SrcArgs<T> a, cplx<T>* sp
       if (rr == r) acc[rr] += (double)s0;
   }
   if (a.rowsum) {
+    // fixed-order FP64 row sums: within each wave, then the waves in order
 #pragma unroll
     for (int r = 0; r < RY; ++r) {
-      red[tid] = acc[r];
-      __syncthreads();
-      for (int s = NT / 2; s > 0; s >>= 1) {
-        if (tid < s) red[tid] += red[tid + s];
-        __syncthreads();
-      }
-      if (tid == 0) a.rowsum[(long)z * N + y0 + r] = red[0];
-      __syncthreads();
+#pragma unroll
+      for (int d = 32; d > 0; d >>= 1) acc[r] += __shfl_down(acc[r], d);
+      if ((tid & 63) == 0) red[r][tid >> 6] = acc[r];
+    }
+    __syncthreads();
+    if (tid < RY) {
+      double t = 0.0;
+#pragma unroll
+      for (int w = 0; w < NT / 64; ++w) t += red[tid][w];
+      a.rowsum[(long)z * N + y0 + tid] = t;
     }
   } else {
     __syncthreads();
   }
   // 2. half-length complex FFT of every row (pairs of reals are complex values)
   cplx<T>* cs = reinterpret_cast<cplx<T>*>(sm);
-  row_stages<T, M, L, M, NT, 0, false>(cs, tw, 2);
+  row_stages<T, M, L, M, NT, 0, false>(cs, stw, 2);
   // 3. post-process Z_k -> X_k (k = 0..M) and store the rows
   for (int job = tid; job < L * (M + 1); job += NT) {
     const int line = job / (M + 1), k = job % (M + 1);
@@ -298,7 +306,7 @@ __global__ __launch_bounds__(NT) void fft_x_r2c_kernel(SrcArgs<T> a, cplx<T>* sp
     const cplx<T> ev = scale(zk + zc, (T)0.5);
     const cplx<T> od = scale(zk - zc, (T)0.5);  // = i * O_k
     // X_k = E_k + W^k O_k with O_k = -i * od
-    const cplx<T> w = tw[k == M ? 0 : k];
+    const cplx<T> w = stw[k == M ? 0 : k];
     const cplx<T> wk = (k == M) ? mk<T>(-1, 0) : w;
     const cplx<T> o = mk(od.y, -od.x);
     const cplx<T> xk = ev + cmul(wk, o);
@@ -321,26 +329,44 @@ __global__ __launch_bounds__(NT) void fft_x_c2r_kernel(const cplx<T>* spec, long
   constexpr int M = N / 2;
   constexpr int L = NOUT * RY;
   __shared__ cplx<T> cs[L * M];
+  __shared__ cplx<T> stw[N];
   const int y0 = blockIdx.x * RY, z = blockIdx.y;
   const int tid = threadIdx.x;
-  // 1. pre-process X_k -> Z_k = E_k + i O_k, E_k = X_k + conj X_{M-k}, O_k = (X_k - conj X_{M-k}) W^-k
-  for (int job = tid; job < L * M; job += NT) {
-    const int line = job / M, k = job % M;
-    const int c = line / RY, r = line % RY;
-    const cplx<T>* row = spec + c * comp_stride + ((long)z * N + (y0 + r)) * nhp;
-    cplx<T> xk = row[k];
-    cplx<T> xm = row[M - k];
-    if (k == 0) {
-      xk.y = 0;
-      xm.y = 0;
+  // 1. pre-process X_k -> Z_k = E_k + i O_k, E_k = X_k + conj X_{M-k}, O_k = (X_k - conj X_{M-k}) W^-k;
+  //    the spectrum reads are issued first, the twiddle table is staged while they are in flight
+  constexpr int PJ = (L * M + NT - 1) / NT;
+  cplx<T> xk[PJ], xm[PJ];
+#pragma unroll
+  for (int q = 0; q < PJ; ++q) {
+    const int job = tid + q * NT;
+    if ((L * M) % NT == 0 || job < L * M) {
+      const int line = job / M, k = job % M;
+      const int c = line / RY, r = line % RY;
+      const cplx<T>* row = spec + c * comp_stride + ((long)z * N + (y0 + r)) * nhp;
+      xk[q] = row[k];
+      xm[q] = row[M - k];
     }
-    const cplx<T> xmc = conj(xm);
-    const cplx<T> ev = xk + xmc;
-    const cplx<T> od = cmulc(xk - xmc, tw[k]);
-    cs[line * M + k] = mk(ev.x - od.y, ev.y + od.x);
+  }
+  for (int j = tid; j < N; j += NT) stw[j] = tw[j];
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < PJ; ++q) {
+    const int job = tid + q * NT;
+    if ((L * M) % NT == 0 || job < L * M) {
+      const int line = job / M, k = job % M;
+      cplx<T> a = xk[q], b = xm[q];
+      if (k == 0) {
+        a.y = 0;
+        b.y = 0;
+      }
+      const cplx<T> bc = conj(b);
+      const cplx<T> ev = a + bc;
+      const cplx<T> od = cmulc(a - bc, stw[k]);
+      cs[line * M + k] = mk(ev.x - od.y, ev.y + od.x);
+    }
   }
   __syncthreads();
-  row_stages<T, M, L, M, NT, 0, true>(cs, tw, 2);
+  row_stages<T, M, L, M, NT, 0, true>(cs, stw, 2);
   // 2. z_n = x_{2n} + i x_{2n+1}: the LDS row is the real output row
   const T* rs = reinterpret_cast<const T*>(cs);
   for (int job = tid; job < L * N; job += NT) {
@@ -353,25 +379,31 @@ __global__ __launch_bounds__(NT) void fft_x_c2r_kernel(const cplx<T>* spec, long
 // ---------------------------------------------------------------------------
 // host launchers
 // ---------------------------------------------------------------------------
+#ifndef GPM_XROW_BYTES
+#define GPM_XROW_BYTES 2048  // real row bytes per pass-X workgroup
+#endif
+#ifndef GPM_COL_BYTES
+#define GPM_COL_BYTES 128    // contiguous bytes of one column-tile row
+#endif
 template <typename T, int N> constexpr int rows_per_block() {
-  constexpr int r = 4096 / (N * (int)sizeof(T));
+  constexpr int r = GPM_XROW_BYTES / (N * (int)sizeof(T));
   return r < 1 ? 1 : (r > N ? N : r);
 }
-template <typename T> constexpr int col_tile() { return 128 / (int)sizeof(cplx<T>); }
+template <typename T> constexpr int col_tile() { return GPM_COL_BYTES / (int)sizeof(cplx<T>); }
 
 template <typename T, int N>
 static void launch_cols(cplx<T>* spec, int ncomp, bool inv, bool along_z, int nhp, const cplx<T>* tw, hipStream_t st) {
   constexpr int C = col_tile<T>();
   constexpr int NT = (N * C / 8 < 256) ? (N * C / 8 < 64 ? 64 : N * C / 8) : 256;
+  static_assert(16 % C == 0, "tiles divide the 16-column row padding");
   const long comp_stride = (long)N * N * nhp;
-  const int ncols = N / 2 + 1;
-  dim3 grid((ncols + C - 1) / C, N, ncomp);
-  const long es = along_z ? (long)N * nhp : (long)nhp;
+  dim3 grid(nhp / C, N, ncomp);
+  const uint32_t es = along_z ? (uint32_t)(N * nhp) : (uint32_t)nhp;
   const long os = along_z ? (long)nhp : (long)N * nhp;
   if (inv)
-    hipLaunchKernelGGL((fft_cols_kernel<T, N, C, NT, true>), grid, dim3(NT), 0, st, spec, es, os, comp_stride, ncols, tw);
+    hipLaunchKernelGGL((fft_cols_kernel<T, N, C, NT, true>), grid, dim3(NT), 0, st, spec, es, os, comp_stride, tw);
   else
-    hipLaunchKernelGGL((fft_cols_kernel<T, N, C, NT, false>), grid, dim3(NT), 0, st, spec, es, os, comp_stride, ncols, tw);
+    hipLaunchKernelGGL((fft_cols_kernel<T, N, C, NT, false>), grid, dim3(NT), 0, st, spec, es, os, comp_stride, tw);
 }
 
 template <typename T, int N>
