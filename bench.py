@@ -105,6 +105,17 @@ def run_gpu(args):
         log(f"{label}: {ms:.3f} ms/step, {n_p / ms * 1e3:.3e} particle updates/s")
         return ms, st
 
+    if args.copy_probe_gib > 0:
+        nb = int(args.copy_probe_gib * 2 ** 30) // 4
+        src = torch.ones(nb, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"copy probe: {nb * 4} bytes read, {nb * 4} bytes written")
+        del src, dst
+        torch.cuda.empty_cache()
+
     # FP32 path from the same snapshot
     pos_d, u_d = ctx64.get_particles(device=True)
     ctx32 = PMContext(n, n_p, box, physics="full", precision="fp32", timings=True)
@@ -155,6 +166,9 @@ def main():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-n", type=int, default=128)
+    ap.add_argument("--copy-probe-gib", type=float, default=0.0,
+                    help="run one plain device copy of this many GiB before timing (a known-size dispatch that "
+                         "calibrates hardware byte counters in a profiler run)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:

@@ -25,7 +25,7 @@ bool is_pow2(long v) { return v > 0 && (v & (v - 1)) == 0; }
 
 // byte offsets of every device buffer inside the workspace
 struct Layout {
-  size_t pos[2], mom[2], ids[2], key, rank, cnt, cell_start, bsum;
+  size_t pos[2], mom[2], ids[2], rank, cnt, cell_start, bsum;
   size_t dep, part, phi[3], chi, b[3], spec, hst[4], tw, kt, rowsum, scal, err;
   // learned closure (PM_FLAG_CLOSURE): activations, gradients, packed weights, partials
   size_t cl_act[3], cl_dact[3], cl_corr, cl_dcorr, cl_wf, cl_wb, cl_bias, cl_part, cl_scal;
@@ -57,7 +57,6 @@ Layout make_layout(const pm_config& c) {
     L.mom[b] = take(3 * np * rs + 2 * kSkew);
     L.ids[b] = take(np * 4);
   }
-  L.key = take(np * 4);
   L.rank = take(np * 4);
   L.cnt = take(n3 * 4);
   L.cell_start = take((n3 + 1) * 4);
@@ -324,8 +323,8 @@ template <typename T>
 void sort_particles(pm_ctx* c) {
   const Layout& L = c->L;
   launch_scan(c->at<uint32_t>(L.cnt), c->at<uint32_t>(L.cell_start), c->n3, c->at<uint32_t>(L.bsum), c->st);
-  launch_scatter<T>(c->parts<T>(c->cur), c->parts<T>(1 - c->cur), c->np, c->at<uint32_t>(L.key),
-                    c->at<uint32_t>(L.rank), c->at<uint32_t>(L.cell_start), c->st);
+  launch_scatter<T>(c->parts<T>(c->cur), c->parts<T>(1 - c->cur), c->np, c->n, c->at<uint32_t>(L.rank),
+                    c->at<uint32_t>(L.cell_start), c->st);
   c->cur = 1 - c->cur;
 }
 
@@ -356,8 +355,8 @@ pm_status do_init(pm_ctx* c, const double* pos, const void* u, const uint32_t* i
   for (int i = 0; i < 4; ++i)
     if (L.hst[i]) c->zero(L.hst[i], L.spec_comp * 2 * c->rs);
   Particles<T> p0 = c->parts<T>(0);
-  launch_ingest<T>(dpos, du, dids, np, p0, c->n, c->at<uint32_t>(L.key), c->at<uint32_t>(L.rank),
-                   c->at<uint32_t>(L.cnt), c->at<int>(L.err), c->st);
+  launch_ingest<T>(dpos, du, dids, np, p0, c->n, c->at<uint32_t>(L.rank), c->at<uint32_t>(L.cnt),
+                   c->at<int>(L.err), c->st);
   c->cur = 0;
   sort_particles<T>(c);
   if (!on_device) hipStreamSynchronize(c->st);  // host buffers may be released after return
@@ -406,8 +405,8 @@ pm_status do_update(pm_ctx* c, double dtau) {
   g.a = c->a_of(c->tau);
   g.a_half = c->a_of(c->tau + 0.5 * dtau);
   c->stage_begin(PM_STAGE_KICK_DRIFT);
-  launch_kick_drift<T>(c->parts<T>(c->cur), c->np, c->n, c->at<uint32_t>(L.cell_start), g, c->at<uint32_t>(L.key),
-                       c->at<uint32_t>(L.rank), c->at<uint32_t>(L.cnt), c->at<int>(L.err), c->st);
+  launch_kick_drift<T>(c->parts<T>(c->cur), c->np, c->n, c->at<uint32_t>(L.cell_start), g, c->at<uint32_t>(L.rank),
+                       c->at<uint32_t>(L.cnt), c->at<int>(L.err), c->st);
   c->stage_end(PM_STAGE_KICK_DRIFT);
   c->stage_begin(PM_STAGE_SORT);
   sort_particles<T>(c);

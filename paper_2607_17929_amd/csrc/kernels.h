@@ -79,7 +79,7 @@ struct Particles {
 
 template <typename T>
 void launch_ingest(const double* pos_aos, const T* u_aos, const uint32_t* ids, long n, Particles<T> out, int nmesh,
-                   uint32_t* key, uint32_t* rank, uint32_t* cnt, int* err, hipStream_t st);
+                   uint32_t* rank, uint32_t* cnt, int* err, hipStream_t st);
 template <typename T>
 void launch_deposit(const Particles<T>& p, const uint32_t* cell_start, int n, int ncomp, bool relativistic, double a,
                     T* dep, double* esum_part, double* esum, hipStream_t st);
@@ -92,11 +92,11 @@ struct GatherArgs {
 };
 template <typename T>
 void launch_kick_drift(const Particles<T>& p, long np, int n, const uint32_t* cell_start, const GatherArgs<T>& g,
-                       uint32_t* key, uint32_t* rank, uint32_t* cnt, int* err, hipStream_t st);
+                       uint32_t* rank, uint32_t* cnt, int* err, hipStream_t st);
 void launch_scan(uint32_t* cnt, uint32_t* cell_start, long ncell, uint32_t* block_sums, hipStream_t st);
 size_t scan_block_sums_count(long ncell);
 template <typename T>
-void launch_scatter(const Particles<T>& src, Particles<T> dst, long np, const uint32_t* key, const uint32_t* rank,
+void launch_scatter(const Particles<T>& src, Particles<T> dst, long np, int nmesh, const uint32_t* rank,
                     const uint32_t* cell_start, hipStream_t st);
 template <typename T>
 void launch_export(const Particles<T>& p, long np, double* pos_aos, T* u_aos, uint32_t* ids, hipStream_t st);

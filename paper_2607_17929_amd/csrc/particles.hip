@@ -32,12 +32,12 @@ __device__ __forceinline__ uint32_t cell_key(double x, double y, double z, int n
 }
 
 // ---------------------------------------------------------------------------
-// ingest: [n][3] inputs -> SoA, wrap, validate, key and rank within the cell
+// ingest: [n][3] inputs -> SoA, wrap, validate, rank within the cell
 // ---------------------------------------------------------------------------
 template <typename T>
 __global__ __launch_bounds__(256) void ingest_kernel(const double* pos, const T* u, const uint32_t* ids, long np,
-                                                     Particles<T> out, int nmesh, uint32_t* key, uint32_t* rank,
-                                                     uint32_t* cnt, int* err) {
+                                                     Particles<T> out, int nmesh, uint32_t* rank, uint32_t* cnt,
+                                                     int* err) {
   const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= np) return;
   double x = pos[3 * i], y = pos[3 * i + 1], z = pos[3 * i + 2];
@@ -57,15 +57,14 @@ __global__ __launch_bounds__(256) void ingest_kernel(const double* pos, const T*
   out.ux[i] = ux; out.uy[i] = uy; out.uz[i] = uz;
   out.id[i] = id;
   const uint32_t k = cell_key(x, y, z, nmesh);
-  key[i] = k;
   rank[i] = atomicAdd(&cnt[k], 1u);
 }
 
 template <typename T>
 void launch_ingest(const double* pos_aos, const T* u_aos, const uint32_t* ids, long n, Particles<T> out, int nmesh,
-                   uint32_t* key, uint32_t* rank, uint32_t* cnt, int* err, hipStream_t st) {
+                   uint32_t* rank, uint32_t* cnt, int* err, hipStream_t st) {
   hipLaunchKernelGGL((ingest_kernel<T>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, pos_aos, u_aos, ids, n,
-                     out, nmesh, key, rank, cnt, err);
+                     out, nmesh, rank, cnt, err);
 }
 
 // ---------------------------------------------------------------------------
@@ -78,7 +77,7 @@ void launch_ingest(const double* pos_aos, const T* u_aos, const uint32_t* ids, l
 // particles of the vertex's 8 adjacent cells -- 4 contiguous ranges, one per
 // cell row -- over all chunks, then stores the 10 components once.
 // ---------------------------------------------------------------------------
-constexpr int DEP_TX = 16, DEP_TY = 8, DEP_TZ = 4, DEP_NT = 256;
+constexpr int DEP_TX = 16, DEP_TY = 4, DEP_TZ = 8, DEP_NT = 256;
 constexpr int DEP_ROWS = (DEP_TY + 1) * (DEP_TZ + 1);
 constexpr int DEP_CX = DEP_TX + 1;
 constexpr int DEP_NV = DEP_TX * DEP_TY * DEP_TZ;
@@ -315,16 +314,17 @@ void launch_deposit(const Particles<T>& p, const uint32_t* cell_start, int n, in
 }
 
 // ---------------------------------------------------------------------------
-// gather + kick + drift + new key.  A workgroup takes the particles of a
+// gather + kick + drift + rank in the new cell.  A workgroup takes the particles of a
 // TX x TY x TZ block of cells (TY*TZ contiguous row ranges of the sorted
 // store) and first copies the fields it needs -- the block's vertices plus a
 // margin of one below and two above, enough for the centred differences at
 // the 8 corners of every cell -- into LDS.  Each particle then interpolates
 // phi, chi, B and their centred-difference gradients from LDS (the CIC
 // interpolation of the vertex gradients, written out per corner), kicks, drifts
-// and computes its new cell key and its rank inside that cell.
+// and takes its rank inside its new cell (the sort recomputes the cell from
+// the stored position).
 // ---------------------------------------------------------------------------
-constexpr int KD_TX = 16, KD_TY = 8, KD_TZ = 4, KD_NT = 256;
+constexpr int KD_TX = 16, KD_TY = 4, KD_TZ = 8, KD_NT = 256;
 constexpr int KD_GX = KD_TX + 3, KD_GY = KD_TY + 3, KD_GZ = KD_TZ + 3;
 constexpr int KD_G = KD_GX * KD_GY * KD_GZ;
 
@@ -381,8 +381,8 @@ __device__ __forceinline__ uint32_t rank_in_cell(uint32_t* cnt, uint32_t k) {
 
 template <typename T, int MODE>
 __global__ __launch_bounds__(KD_NT) void kick_drift_kernel(Particles<T> p, const uint32_t* __restrict__ cell_start, int n,
-                                                           GatherArgs<T> ga, uint32_t* key, uint32_t* rank,
-                                                           uint32_t* cnt, int* err) {
+                                                           GatherArgs<T> ga, uint32_t* rank, uint32_t* cnt,
+                                                           int* err) {
   constexpr int NF = MODE == MODE_FULL ? 5 : (MODE == MODE_SCALAR ? 2 : 1);
   constexpr int NR = KD_TY * KD_TZ;                   // particle rows of the block
   constexpr int NTL = (KD_G + KD_NT - 1) / KD_NT;     // tile entries per thread and field
@@ -532,25 +532,23 @@ __global__ __launch_bounds__(KD_NT) void kick_drift_kernel(Particles<T> p, const
     x = wrap01(x); y = wrap01(y); z = wrap01(z);
     p.px[pi] = x; p.py[pi] = y; p.pz[pi] = z;
     p.ux[pi] = ux; p.uy[pi] = uy; p.uz[pi] = uz;
-    const uint32_t k = cell_key(x, y, z, n);
-    key[pi] = k;
-    rank[pi] = rank_in_cell(cnt, k);
+    rank[pi] = rank_in_cell(cnt, cell_key(x, y, z, n));
   }
 }
 
 template <typename T>
 void launch_kick_drift(const Particles<T>& p, long np, int n, const uint32_t* cell_start, const GatherArgs<T>& g,
-                       uint32_t* key, uint32_t* rank, uint32_t* cnt, int* err, hipStream_t st) {
+                       uint32_t* rank, uint32_t* cnt, int* err, hipStream_t st) {
   (void)np;
   dim3 grid(n / KD_TX, n / KD_TY, n / KD_TZ);
   if (g.mode == MODE_NEWTONIAN)
-    hipLaunchKernelGGL((kick_drift_kernel<T, MODE_NEWTONIAN>), grid, dim3(KD_NT), 0, st, p, cell_start, n, g, key, rank,
-                       cnt, err);
+    hipLaunchKernelGGL((kick_drift_kernel<T, MODE_NEWTONIAN>), grid, dim3(KD_NT), 0, st, p, cell_start, n, g, rank, cnt,
+                       err);
   else if (g.mode == MODE_SCALAR)
-    hipLaunchKernelGGL((kick_drift_kernel<T, MODE_SCALAR>), grid, dim3(KD_NT), 0, st, p, cell_start, n, g, key, rank,
-                       cnt, err);
+    hipLaunchKernelGGL((kick_drift_kernel<T, MODE_SCALAR>), grid, dim3(KD_NT), 0, st, p, cell_start, n, g, rank, cnt,
+                       err);
   else
-    hipLaunchKernelGGL((kick_drift_kernel<T, MODE_FULL>), grid, dim3(KD_NT), 0, st, p, cell_start, n, g, key, rank, cnt,
+    hipLaunchKernelGGL((kick_drift_kernel<T, MODE_FULL>), grid, dim3(KD_NT), 0, st, p, cell_start, n, g, rank, cnt,
                        err);
 }
 
@@ -664,24 +662,24 @@ void launch_scan(uint32_t* cnt, uint32_t* cell_start, long ncell, uint32_t* bloc
 }
 
 // ---------------------------------------------------------------------------
-// scatter into the other buffer at cell_start[key] + rank
+// scatter into the other buffer at cell_start[cell] + rank; the cell is
+// recomputed from the stored position exactly as the kick/drift computed it
 // ---------------------------------------------------------------------------
 constexpr int SC_PER = 4;  // particles per thread: independent load chains in flight
 
 template <typename T>
-__global__ __launch_bounds__(256) void scatter_kernel(Particles<T> s, Particles<T> d, long np,
-                                                      const uint32_t* __restrict__ key, const uint32_t* __restrict__ rank,
+__global__ __launch_bounds__(256) void scatter_kernel(Particles<T> s, Particles<T> d, long np, int nmesh,
+                                                      const uint32_t* __restrict__ rank,
                                                       const uint32_t* __restrict__ cell_start) {
   const long base = (long)xcd_remap(blockIdx.x, gridDim.x) * (256 * SC_PER) + threadIdx.x;
   // every read that does not depend on the destination is issued first
-  uint32_t k[SC_PER], r[SC_PER], id[SC_PER];
+  uint32_t r[SC_PER], id[SC_PER];
   double x[SC_PER], y[SC_PER], z[SC_PER];
   T ux[SC_PER], uy[SC_PER], uz[SC_PER];
 #pragma unroll
   for (int q = 0; q < SC_PER; ++q) {
     const long i = base + q * 256;
     if (i < np) {
-      k[q] = key[i];
       r[q] = rank[i];
       x[q] = s.px[i]; y[q] = s.py[i]; z[q] = s.pz[i];
       ux[q] = s.ux[i]; uy[q] = s.uy[i]; uz[q] = s.uz[i];
@@ -690,7 +688,8 @@ __global__ __launch_bounds__(256) void scatter_kernel(Particles<T> s, Particles<
   }
   long j[SC_PER];
 #pragma unroll
-  for (int q = 0; q < SC_PER; ++q) j[q] = (base + q * 256 < np) ? (long)cell_start[k[q]] + r[q] : 0;
+  for (int q = 0; q < SC_PER; ++q)
+    j[q] = (base + q * 256 < np) ? (long)cell_start[cell_key(x[q], y[q], z[q], nmesh)] + r[q] : 0;
 #pragma unroll
   for (int q = 0; q < SC_PER; ++q) {
     if (base + q * 256 < np) {
@@ -702,11 +701,11 @@ __global__ __launch_bounds__(256) void scatter_kernel(Particles<T> s, Particles<
 }
 
 template <typename T>
-void launch_scatter(const Particles<T>& src, Particles<T> dst, long np, const uint32_t* key, const uint32_t* rank,
+void launch_scatter(const Particles<T>& src, Particles<T> dst, long np, int nmesh, const uint32_t* rank,
                     const uint32_t* cell_start, hipStream_t st) {
   const long per_block = 256 * SC_PER;
   hipLaunchKernelGGL((scatter_kernel<T>), dim3((unsigned)((np + per_block - 1) / per_block)), dim3(256), 0, st, src, dst,
-                     np, key, rank, cell_start);
+                     np, nmesh, rank, cell_start);
 }
 
 // ---------------------------------------------------------------------------
@@ -754,13 +753,13 @@ void launch_copy_unpad(const cplx<T>* spec, int n, int nhp, cplx<T>* out, bool t
 
 #define GPM_INST(T)                                                                                                   \
   template void launch_ingest<T>(const double*, const T*, const uint32_t*, long, Particles<T>, int, uint32_t*,         \
-                                 uint32_t*, uint32_t*, int*, hipStream_t);                                             \
+                                 uint32_t*, int*, hipStream_t);                                                        \
   template void launch_deposit<T>(const Particles<T>&, const uint32_t*, int, int, bool, double, T*, double*, double*, \
                                   hipStream_t);                                                                       \
   template void launch_kick_drift<T>(const Particles<T>&, long, int, const uint32_t*, const GatherArgs<T>&, uint32_t*, \
-                                     uint32_t*, uint32_t*, int*, hipStream_t);                                         \
-  template void launch_scatter<T>(const Particles<T>&, Particles<T>, long, const uint32_t*, const uint32_t*,           \
-                                  const uint32_t*, hipStream_t);                                                       \
+                                     uint32_t*, int*, hipStream_t);                                                    \
+  template void launch_scatter<T>(const Particles<T>&, Particles<T>, long, int, const uint32_t*, const uint32_t*,      \
+                                  hipStream_t);                                                                        \
   template void launch_export<T>(const Particles<T>&, long, double*, T*, uint32_t*, hipStream_t);                      \
   template void launch_copy_unpad<T>(const cplx<T>*, int, int, cplx<T>*, bool, hipStream_t);
 GPM_INST(float)
