@@ -44,12 +44,25 @@ def stage_bytes(n: int, n_p: int, rs: int) -> dict:
         "ksolve": 10 * S + 5 * S + 8 * S,
         "fft_zy_inv": 2 * 5 * S,         # per launch (two launches per stage)
         "fft_x_inv": 5 * S + 5 * F,
-        "kick_drift": n_p * (2 * P + 8) + 5 * F,
-        "sort": 16 * n ** 3 + n_p * (12 + 2 * (P + 4)),
+        "kick_drift": n_p * (2 * P + 4) + 5 * F,                  # state in and out, rank out, 5 fields in
+        "sort": 16 * n ** 3 + n_p * (4 + 2 * (P + 4)),           # counts/offsets; rank, state and id in and out
     }
 
 
 LAUNCHES = {"fft_yz_fwd": 2, "fft_zy_inv": 2}
+
+
+def measured_traffic(n: int, stage: str):
+    """HBM bytes per launch of an FP32 stage from the committed counter summary, or None when there is
+    none for this mesh or the stage's kernel sources have changed since it was measured."""
+    from paper_2607_17929_amd import profsum
+    t = profsum.load_traffic(os.path.join(ROOT, "profiles", f"pm_step_{n}_clustered_traffic.md"))
+    if not t or t.get("n") != n:
+        return None
+    e = t["stages"].get(f"fp32:{stage}")
+    if not e or e["source_sha256"] != profsum.source_hash(stage):
+        return None
+    return e["traffic_bytes_per_launch"]
 
 
 def run_gpu(args):
@@ -105,8 +118,8 @@ def run_gpu(args):
         log(f"{label}: {ms:.3f} ms/step, {n_p / ms * 1e3:.3e} particle updates/s")
         return ms, st
 
-    if args.copy_probe_gib > 0:
-        nb = int(args.copy_probe_gib * 2 ** 30) // 4
+    if args.copy_probe_mib > 0:
+        nb = args.copy_probe_mib * 2 ** 20 // 4
         src = torch.ones(nb, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)
         torch.cuda.synchronize()
@@ -166,8 +179,8 @@ def main():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-n", type=int, default=128)
-    ap.add_argument("--copy-probe-gib", type=float, default=0.0,
-                    help="run one plain device copy of this many GiB before timing (a known-size dispatch that "
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="run one plain device copy of this many MiB before timing (a known-size dispatch that "
                          "calibrates hardware byte counters in a profiler run)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -188,7 +201,7 @@ def main():
     nbytes = stage_bytes(n, n_p, 4)
     achieved = nbytes[dom] / (per_launch[dom] * 1e-3) / 1e9
     roof = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(n, dom),
             "algorithmic_bytes_per_launch": nbytes[dom], "ms_per_launch": round(per_launch[dom], 4)}
     stages = {k: {"ms_per_launch": round(per_launch.get(k, 0.0), 4),
                   "GBs": round(nbytes[k] / (per_launch[k] * 1e-3) / 1e9, 1) if k in per_launch else None}
