@@ -83,8 +83,23 @@ def make_pairs(seeds, n_p: int, n1: int, box: float, a_snaps, steps: int, spectr
     return out, c1
 
 
-def train(ctx1: PMContext, snaps, params: torch.Tensor, iters: int, lr: float = 1e-3, log=print, log_every=100):
-    """Adam on the particle MSE; returns (params, loss history)."""
+def cube_symmetry(pos: torch.Tensor, u: torch.Tensor, target: torch.Tensor, perm, signs):
+    """One of the 48 symmetries of the periodic cube applied to a snapshot: axes permuted by perm, axis d
+    reflected (x -> 1 - x) where signs[d] < 0; momenta and force differences transform as vectors.  The
+    mesh, the CIC weights and the centred differences map onto themselves, so the 1x fields the library
+    computes from the transformed particles are the transformed fields."""
+    perm = list(perm)
+    sg = torch.tensor(signs, dtype=torch.float64, device=pos.device)
+    p = pos[:, perm]
+    p = torch.where(sg < 0, 1.0 - p, p)
+    return (p.contiguous(), (u[:, perm] * sg.to(u.dtype)).contiguous(),
+            (target[:, perm] * sg.to(target.dtype)).contiguous())
+
+
+def train(ctx1: PMContext, snaps, params: torch.Tensor, iters: int, lr: float = 1e-3, log=print, log_every=100,
+          augment: bool = False, lr_final: float = 1.0):
+    """Adam on the particle MSE; returns (params, loss history).  With `augment` every iteration applies a
+    random cube symmetry to its snapshot; the learning rate follows a cosine from lr to lr * lr_final."""
     dev = ctx1.device
     p = params.to(dev).float().contiguous().clone()
     m = torch.zeros_like(p)
@@ -94,15 +109,19 @@ def train(ctx1: PMContext, snaps, params: torch.Tensor, iters: int, lr: float = 
     r = np.random.default_rng(1)
     for it in range(1, iters + 1):
         s = snaps[int(r.integers(len(snaps)))]
-        ctx1.init_particles(s.pos, s.u, s.tau)
+        pos, u, target = s.pos, s.u, s.target
+        if augment:
+            pos, u, target = cube_symmetry(pos, u, target, r.permutation(3), r.choice([-1.0, 1.0], 3))
+        ctx1.init_particles(pos, u, s.tau)
         ctx1.deposit()
         ctx1.solve_metric(0.0)
         ctx1.closure_forward(False)
         pred = ctx1.closure_gather()
-        diff = pred - s.target
+        diff = pred - target
         loss = float((diff * diff).mean())
         g = ctx1.closure_backward(diff * (2.0 / diff.numel()))
-        ctx1.closure_adam(p, m, v, g, it, lr)
+        lr_it = lr * (lr_final + (1.0 - lr_final) * 0.5 * (1.0 + math.cos(math.pi * (it - 1) / max(iters - 1, 1))))
+        ctx1.closure_adam(p, m, v, g, it, lr_it)
         hist.append(loss)
         if log and (it % log_every == 0 or it == 1):
             log(f"closure train it {it}: loss {np.mean(hist[-log_every:]):.4e}")
@@ -187,7 +206,7 @@ def run_pm(n_mesh: int, pos, u, tau0: float, tau1: float, steps: int, box: float
 
 
 def experiment(n_app: int = 512, n_train_p: int = 128, train_box: float = 512.0, n_boxes: int = 64,
-               iters: int = 3000, lr: float = 1e-3, log=print):
+               iters: int = 12000, lr: float = 1e-3, augment: bool = True, log=print):
     """Train on seeded boxes (1x and 2x meshes), apply to n_app^3 particles on an n_app^3 mesh and compare
     P(k) and cost with the plain n_app^3 and 2 n_app^3 meshes at a = 0.5."""
     from synth import spectrum_power_law_m2, zeldovich_particles
@@ -208,7 +227,8 @@ def experiment(n_app: int = 512, n_train_p: int = 128, train_box: float = 512.0,
     log(f"{len(snaps)} training snapshots in {res['pairs_s']:.1f} s (rms displacement {rms_train:.3f} cells)")
     hold = snaps[-8:]
     t0 = time.time()
-    params, hist = train(c1, snaps[:-8], init_params(0), iters=iters, lr=lr, log=log, log_every=500)
+    params, hist = train(c1, snaps[:-8], init_params(0), iters=iters, lr=lr, log=log, log_every=1000,
+                         augment=augment, lr_final=0.05)
     res["train_s"] = time.time() - t0
     res["heldout_plain"], res["heldout_closure"] = evaluate(c1, hold, params)
     log(f"trained in {res['train_s']:.1f} s; held-out force error: plain {res['heldout_plain']:.4e}, "
@@ -245,6 +265,7 @@ def experiment(n_app: int = 512, n_train_p: int = 128, train_box: float = 512.0,
     for label in out:
         res[f"{label}_wall_s"] = out[label][2]
     res["loss_first"], res["loss_last"] = float(np.mean(hist[:50])), float(np.mean(hist[-50:]))
+    res["iters"], res["augment"] = iters, augment
     res["pass_2pct"] = res["closure_1x_maxdev"] <= 0.02
     res["gain"] = res["closure_1x_maxdev"] < res["plain_1x_maxdev"]
     res["cheaper_than_2x"] = out["closure_1x"][2] < out["plain_2x"][2]
@@ -259,10 +280,12 @@ if __name__ == "__main__":
     ap = argparse.ArgumentParser(description="learned closure experiment")
     ap.add_argument("--n-app", type=int, default=512)
     ap.add_argument("--boxes", type=int, default=64)
-    ap.add_argument("--iters", type=int, default=3000)
+    ap.add_argument("--iters", type=int, default=12000)
+    ap.add_argument("--no-augment", action="store_true")
     ap.add_argument("--out", default="gpurun_out/closure_experiment.json")
     a = ap.parse_args()
-    res, params = experiment(n_app=a.n_app, n_boxes=a.boxes, iters=a.iters, log=lambda s: print(s, flush=True))
+    res, params = experiment(n_app=a.n_app, n_boxes=a.boxes, iters=a.iters, augment=not a.no_augment,
+                             log=lambda s: print(s, flush=True))
     os.makedirs(os.path.dirname(a.out) or ".", exist_ok=True)
     with open(a.out, "w") as f:
         json.dump(res, f, indent=1)
