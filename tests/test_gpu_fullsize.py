@@ -1,0 +1,193 @@
+"""Parity at the benchmark's full size (512^3 particles on a 512^3 mesh, full physics, the
+precision modes bench.py times), on outputs the oracle's definitions give one by one or through
+properties that hold at any size.
+
+* FFT: sampled Fourier coefficients of a seeded field against the DFT sum written out.
+* Deposit: every vertex of two 16^3 regions (the densest cell's and a random one) against the
+  CIC sums of the particles around them, computed from the oracle's CIC corners; the total n00
+  against the FP64 sum of the particle energies (CIC partition of unity).
+* Translation by whole cells moves the deposit by the same cells (FP64).
+* FP32 against FP64 on the same clustered input: the metric fields of the start-up solve
+  (1e-5 rel-L2 per field; clustered states are compared per field, not as trajectories).
+* A linear plane wave on the 512^3 lattice follows the scalar recursion of the discrete
+  equations (Newtonian and relativistic scalar).
+
+Input: a seeded Zel'dovich set with the benchmark's spectrum and amplitude rule, displaced to
+a = 0.5 (shell-crossed, strongly clustered) -- a synthetic stand-in for the clustered snapshot
+that needs no GPU evolution.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import pm as opm
+from synth import lattice_positions, plane_wave_particles, spectrum_power_law_m2, zeldovich_particles
+from synth.ics import eds_a_of_tau
+from tests.helpers import rel_l2
+from tests.test_oracle_pins import _linear_recursion, _project_wave
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+N = 512
+BOX = 2048.0
+DEP = ["n00", "n0x", "n0y", "n0z", "nxx", "nxy", "nxz", "nyy", "nyz", "nzz"]
+
+
+def _say(msg):
+    print(msg, flush=True)
+
+
+@pytest.fixture(scope="module")
+def clustered():
+    _say("building the 512^3 clustered input")
+    bg = opm.Background(BOX)
+    tau = bg.tau(0.5)
+    dtau = 0.01 * tau
+    pos, u = zeldovich_particles(N, 3, spectrum_power_law_m2, BOX, 0.2, 0.02, 0.5, eds_a_of_tau(tau - 0.5 * dtau, BOX))
+    return pos, u, tau, dtau
+
+
+def _ctx(precision, n_p, physics="full"):
+    from paper_2607_17929_amd import PMContext
+    return PMContext(N, n_p, BOX, physics=physics, precision=precision)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_fft_512_sampled_modes(precision):
+    _say(f"fft 512 {precision}")
+    r = np.random.default_rng(7)
+    f = r.standard_normal((N, N, N))
+    if precision == "fp32":
+        f = f.astype(np.float32).astype(np.float64)
+    ctx = _ctx(precision, 1, "newtonian")
+    spec = ctx.debug_fft(torch.tensor(f), 1).cpu().numpy().astype(np.complex128)
+    modes = [(0, 0, 0), (1, 0, 0), (0, 1, 0), (0, 0, 1), (3, 17, 255), (256, 0, 0), (256, 256, 256), (100, 511, 3),
+             (17, 300, 450), (255, 1, 510), (128, 384, 64), (5, 5, 5)]
+    x = np.arange(N)
+    ex = np.exp(-2j * np.pi * np.outer(x, [m[0] for m in modes]) / N)  # [x][mode]
+    f2 = f.reshape(-1, N)
+    gx = (f2 @ ex.real + 1j * (f2 @ ex.imag)).reshape(N, N, len(modes))  # [z][y][mode]
+    scale = np.sqrt(np.sum(f * f))
+    for j, (kx, ky, kz) in enumerate(modes):
+        ey = np.exp(-2j * np.pi * ky * x / N)
+        ez = np.exp(-2j * np.pi * kz * x / N)
+        ref = ez @ (gx[:, :, j] @ ey)
+        err = abs(spec[kz, ky, kx] - ref) / scale
+        assert err < (1e-12 if precision == "fp64" else 1e-5), ((kx, ky, kz), err)
+
+
+def _region_deposit(pos, u, a, z0, y0, x0, R):
+    """Oracle CIC sums at the vertices [z0, z0+R) x [y0, y0+R) x [x0, x0+R) from the particles of
+    the cells that touch them (cells z0-1 .. z0+R-1 in each axis, periodic)."""
+    base, _ = opm.cic_cells(pos, N)
+    rel = (base - np.array([x0 - 1, y0 - 1, z0 - 1])) % N
+    sel = np.all(rel < R + 1, axis=1)
+    p, q = pos[sel], opm.deposit_quantities(u[sel], a)
+    out = np.zeros((10, R, R, R))
+    for idx, w in opm._corners(p, N):
+        iz, iy, ix = idx // (N * N), (idx // N) % N, idx % N
+        lz, ly, lx = (iz - z0) % N, (iy - y0) % N, (ix - x0) % N
+        ok = (lz < R) & (ly < R) & (lx < R)
+        for c in range(10):
+            np.add.at(out[c], (lz[ok], ly[ok], lx[ok]), w[ok] * q[c, ok])
+    return out
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_deposit_512_clustered_regions(clustered, precision):
+    pos, u, tau, _ = clustered
+    _say(f"deposit 512 clustered {precision}")
+    ctx = _ctx(precision, pos.shape[0])
+    u_in = u.astype(ctx.np_dtype)
+    ctx.init_particles(pos, u_in, tau)
+    ctx.deposit()
+    a = opm.Background(BOX).a(tau)
+    u64 = u_in.astype(np.float64)
+    base, _ = opm.cic_cells(pos, N)
+    key = (base[:, 2] * N + base[:, 1]) * N + base[:, 0]
+    counts = np.bincount(key, minlength=N ** 3)
+    dense = int(np.argmax(counts))
+    assert counts[dense] > 50  # the input is clustered
+    dz, dy, dx = dense // (N * N), (dense // N) % N, dense % N
+    r = np.random.default_rng(11)
+    R = 16
+    regions = [((dz - R // 2) % N, (dy - R // 2) % N, (dx - R // 2) % N), tuple(int(v) for v in r.integers(0, N, 3))]
+    fields = {c: ctx.get_field(c) for c in DEP}
+    tol = 1e-12 if precision == "fp64" else 2e-6
+    for (z0, y0, x0) in regions:
+        ref = _region_deposit(pos, u64, a, z0, y0, x0, R)
+        zi, yi, xi = (np.arange(z0, z0 + R) % N, np.arange(y0, y0 + R) % N, np.arange(x0, x0 + R) % N)
+        for c, name in enumerate(DEP):
+            got = fields[name][np.ix_(zi, yi, xi)].astype(np.float64)
+            err = rel_l2(got, ref[c])
+            assert err < tol, ((z0, y0, x0), name, err)
+    # CIC partition of unity over the whole mesh
+    e = np.sqrt(a * a + np.sum(u64 * u64, axis=1))
+    tot = float(np.sum(fields["n00"], dtype=np.float64))
+    assert abs(tot - e.sum()) < (1e-12 if precision == "fp64" else 1e-6) * e.sum()
+
+
+def test_deposit_512_translation_by_cells(clustered):
+    pos, u, tau, _ = clustered
+    _say("deposit 512 translation")
+    shift = np.array([5, 3, 7])  # cells along x, y, z
+    out = []
+    for p in (pos, (pos + shift / N) % 1.0):
+        ctx = _ctx("fp64", pos.shape[0])
+        ctx.init_particles(p, u, tau)
+        ctx.deposit()
+        out.append([ctx.get_field(c) for c in ("n00", "n0x", "nxy")])
+        del ctx
+        torch.cuda.empty_cache()
+    for f0, f1 in zip(*out):
+        moved = np.roll(f0, shift=(shift[2], shift[1], shift[0]), axis=(0, 1, 2))
+        assert rel_l2(f1, moved) < 1e-13
+
+
+def test_fp32_against_fp64_512_clustered(clustered):
+    pos, u, tau, _ = clustered
+    _say("fp32 vs fp64 at 512 clustered")
+    res = {}
+    for precision in ("fp64", "fp32"):
+        ctx = _ctx(precision, pos.shape[0])
+        ctx.init_particles(pos, u.astype(ctx.np_dtype), tau)
+        ctx.deposit()
+        ctx.solve_metric(0.0)
+        res[precision] = {k: ctx.get_field(k).astype(np.float64) for k in ("phi", "chi", "bx", "by", "bz")}
+        del ctx
+        torch.cuda.empty_cache()
+    errs = {k: rel_l2(res["fp32"][k], res["fp64"][k]) for k in res["fp64"]}
+    _say("  " + ", ".join(f"{k} {v:.2e}" for k, v in errs.items()))
+    for k, err in errs.items():
+        assert err < 1e-5, (k, err)
+
+
+@pytest.mark.parametrize("physics", ["newtonian", "scalar"])
+def test_plane_wave_512_follows_linear_recursion(physics):
+    _say(f"plane wave 512 {physics}")
+    bg = opm.Background(320.0 * N / 32)
+    tau0 = bg.tau(0.02)
+    dtau = (bg.tau(0.05) - tau0) / 10
+    mode = 2
+    eps = 1e-6 / N
+    P0 = 0.3 * eps * bg.a(tau0) * bg.hconf(tau0)
+    pos, u = plane_wave_particles(N, N, eps, P0, mode=mode)
+    from paper_2607_17929_amd import PMContext
+    ctx = PMContext(N, N ** 3, 320.0 * N / 32, physics=physics, precision="fp64")
+    ctx.init_particles(pos, u, tau0)
+    steps = 3
+    for _ in range(steps):
+        ctx.step(dtau)
+    ref = _linear_recursion(bg, N, mode, eps, P0, tau0, dtau, steps, opm.NEWTONIAN if physics == "newtonian"
+                            else opm.SCALAR)
+    p, uu = ctx.get_particles()
+
+    class _S:
+        def particles_by_id(self):
+            return p, uu
+
+    U, P = _project_wave(_S(), lattice_positions(N), 2 * math.pi * mode)
+    assert abs(U - ref[-1][0]) < 1e-5 * abs(ref[-1][0]), (U, ref[-1][0])
+    assert abs(P - ref[-1][1]) < 1e-5 * abs(ref[-1][1]), (P, ref[-1][1])
