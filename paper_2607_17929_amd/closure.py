@@ -205,8 +205,49 @@ def run_pm(n_mesh: int, pos, u, tau0: float, tau1: float, steps: int, box: float
     return p, wall
 
 
+def scaled_output(params: torch.Tensor, s: float) -> torch.Tensor:
+    """Parameters whose network output is s times the original (the last layer is linear)."""
+    p = params.clone()
+    n_last = 3 * 16 * 27 + 3
+    p[-n_last:] *= s
+    return p
+
+
+def max_pk_deviation(k, ratio, kmax):
+    sel = k <= kmax
+    return float(np.max(np.abs(ratio[sel] - 1.0)))
+
+
+def calibrate_amplitude(params, n_p1: int, box: float, rms_cells: float, seeds, scales=(1.0, 1.1, 1.2, 1.3, 1.4, 1.5),
+                        steps: int = 100, log=print):
+    """Output amplitude of the closure chosen on training boxes: each box is run on the 2x mesh and on the 1x
+    mesh with the closure scaled by s; the s whose box-averaged P(k) ratio to the 2x runs deviates least up
+    to half the 1x Nyquist frequency is returned with the table of deviations."""
+    from synth import spectrum_power_law_m2, zeldovich_particles
+    from synth.ics import eds_a_of_tau
+
+    tau0, tau1 = tau_of_a(box, 0.02), tau_of_a(box, 0.5)
+    dtau = (tau1 - tau0) / steps
+    kmax = math.pi / (2.0 * box / n_p1)
+    ratios = {s: [] for s in scales}
+    for seed in seeds:
+        pos, u = zeldovich_particles(n_p1, seed, spectrum_power_law_m2, box, rms_cells, 0.02, 0.02,
+                                     eds_a_of_tau(tau0 - 0.5 * dtau, box))
+        pos_d = torch.tensor(pos, device="cuda")
+        u_d = torch.tensor(u, device="cuda", dtype=torch.float32)
+        p2, _ = run_pm(2 * n_p1, pos_d, u_d, tau0, tau1, steps, box, None, log=None)
+        k, pk2, _ = power_spectrum(p2, n_p1, box)
+        for s in scales:
+            p1, _ = run_pm(n_p1, pos_d, u_d, tau0, tau1, steps, box, scaled_output(params, s), log=None)
+            ratios[s].append(power_spectrum(p1, n_p1, box)[1] / pk2)
+    table = {s: max_pk_deviation(k, np.mean(ratios[s], axis=0), kmax) for s in scales}
+    if log:
+        log("calibration: " + ", ".join(f"s={s:.1f}: {d:.4f}" for s, d in table.items()))
+    return min(table, key=table.get), table
+
+
 def experiment(n_app: int = 512, n_train_p: int = 128, train_box: float = 512.0, n_boxes: int = 64,
-               iters: int = 12000, lr: float = 1e-3, augment: bool = True, log=print):
+               iters: int = 12000, lr: float = 1e-3, augment: bool = True, calibrate: bool = True, log=print):
     """Train on seeded boxes (1x and 2x meshes), apply to n_app^3 particles on an n_app^3 mesh and compare
     P(k) and cost with the plain n_app^3 and 2 n_app^3 meshes at a = 0.5."""
     from synth import spectrum_power_law_m2, zeldovich_particles
@@ -235,6 +276,12 @@ def experiment(n_app: int = 512, n_train_p: int = 128, train_box: float = 512.0,
         f"closure {res['heldout_closure']:.4e}")
     del c1, snaps
     torch.cuda.empty_cache()
+    if calibrate:
+        t0 = time.time()
+        s, table = calibrate_amplitude(params, n_train_p, train_box, rms_train, seeds=range(1000, 1000 + 4), log=log)
+        params = scaled_output(params, s)
+        res["amplitude"], res["calibration"], res["calibration_s"] = s, table, time.time() - t0
+        log(f"output amplitude {s:.2f} from the training boxes' 2x spectra ({res['calibration_s']:.1f} s)")
     # application
     tau0, tau1 = tau_of_a(app_box, 0.02), tau_of_a(app_box, 0.5)
     steps = 100
@@ -272,6 +319,32 @@ def experiment(n_app: int = 512, n_train_p: int = 128, train_box: float = 512.0,
     return res, params
 
 
+def summary_md(res: dict, command: str) -> str:
+    """Markdown summary of an experiment result (the committed profile of the closure experiment)."""
+    lines = ["# Learned closure experiment: 512^3 particles, 512^3 mesh + closure vs plain 1024^3 mesh", "",
+             "Command (repository root, GPU box):", "", f"    {command}", "",
+             f"Training: {res.get('iters')} Adam iterations (cosine decay), cube-symmetry augmentation "
+             f"{'on' if res.get('augment') else 'off'}; pairs {res['pairs_s']:.1f} s, training {res['train_s']:.1f} s.",
+             f"Held-out particle force error (units of rms|grad phi|^2): plain 1x {res['heldout_plain']:.3e}, "
+             f"with closure {res['heldout_closure']:.3e}."]
+    if "amplitude" in res:
+        lines.append(f"Output amplitude chosen on 4 training boxes: s = {res['amplitude']:.2f} "
+                     f"({res['calibration_s']:.1f} s); max deviation per s: "
+                     + ", ".join(f"{float(k):.1f}: {v:.4f}" for k, v in res["calibration"].items()) + ".")
+    lines += ["", "| run | wall time, 100 steps | max abs(P/P_2x - 1), k <= k_Ny/2 |", "|---|---|---|",
+              f"| plain 512^3 mesh | {res['plain_1x_wall_s']:.1f} s | {res['plain_1x_maxdev']:.4f} |",
+              f"| 512^3 mesh + closure | {res['closure_1x_wall_s']:.1f} s | {res['closure_1x_maxdev']:.4f} |",
+              f"| plain 1024^3 mesh | {res['plain_2x_wall_s']:.1f} s | (reference) |", "",
+              f"2% target: {'met' if res['pass_2pct'] else 'not met'}; gain over the plain mesh: "
+              f"{'yes' if res['gain'] else 'no'}; cheaper than the 2x mesh: "
+              f"{'yes' if res['cheaper_than_2x'] else 'no'} "
+              f"({res['closure_1x_wall_s'] / res['plain_2x_wall_s']:.2f}x of its time).", "",
+              "P(k) ratio minus one (every 6th bin):", "", "| k [h/Mpc] | plain 1x | 1x + closure |", "|---|---|---|"]
+    for i in range(0, len(res["k"]), 6):
+        lines.append(f"| {res['k'][i]:.4f} | {res['plain_1x_ratio'][i]:+.4f} | {res['closure_1x_ratio'][i]:+.4f} |")
+    return "\n".join(lines) + "\n"
+
+
 if __name__ == "__main__":
     import argparse
     import json
@@ -282,10 +355,17 @@ if __name__ == "__main__":
     ap.add_argument("--boxes", type=int, default=64)
     ap.add_argument("--iters", type=int, default=12000)
     ap.add_argument("--no-augment", action="store_true")
+    ap.add_argument("--no-calibrate", action="store_true")
     ap.add_argument("--out", default="gpurun_out/closure_experiment.json")
+    ap.add_argument("--summarize", metavar="RESULT_JSON", help="print the markdown summary of a stored result")
+    ap.add_argument("--command", default="python -u -m paper_2607_17929_amd.closure --out gpurun_out/closure_experiment.json")
     a = ap.parse_args()
+    if a.summarize:
+        with open(a.summarize) as f:
+            print(summary_md(json.load(f), a.command), end="")
+        raise SystemExit(0)
     res, params = experiment(n_app=a.n_app, n_boxes=a.boxes, iters=a.iters, augment=not a.no_augment,
-                             log=lambda s: print(s, flush=True))
+                             calibrate=not a.no_calibrate, log=lambda s: print(s, flush=True))
     os.makedirs(os.path.dirname(a.out) or ".", exist_ok=True)
     with open(a.out, "w") as f:
         json.dump(res, f, indent=1)

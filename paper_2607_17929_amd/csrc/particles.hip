@@ -324,18 +324,21 @@ void launch_deposit(const Particles<T>& p, const uint32_t* cell_start, int n, in
 // and takes its rank inside its new cell (the sort recomputes the cell from
 // the stored position).
 // ---------------------------------------------------------------------------
-constexpr int KD_TX = 16, KD_TY = 4, KD_TZ = 8, KD_NT = 256;
-constexpr int KD_GX = KD_TX + 3, KD_GY = KD_TY + 3, KD_GZ = KD_TZ + 3;
-constexpr int KD_G = KD_GX * KD_GY * KD_GZ;
+// Blocks are TX x 2 x 8 cells with TX = 32 (16 on a 16^3 mesh): rows of 32 cells keep the
+// row segments of the 4-byte particle arrays at whole 128-byte lines more often.
+constexpr int KD_TY = 2, KD_TZ = 8, KD_NT = 256;
+template <int TX> struct KdTile {
+  static constexpr int GX = TX + 3, GY = KD_TY + 3, GZ = KD_TZ + 3, G = GX * GY * GZ;
+};
 
-template <typename T>
+template <typename T, int GX, int GY>
 __device__ __forceinline__ void gather_lds(const T* __restrict__ f, int zo0, int yo0, int xo0, const T* wx, const T* wy,
                                            const T* wz, T half_n, T& val, T* g) {
-  // f: LDS tile with x stride 1, y stride KD_GX, z stride KD_GX*KD_GY whose index 0 is the vertex one
+  // f: LDS tile with x stride 1, y stride GX, z stride GX*GY whose index 0 is the vertex one
   // below the block in every axis; (xo0, yo0, zo0) = the particle's cell relative to the block, so the
   // cell's lower corner is tile index (xo0 + 1, yo0 + 1, zo0 + 1)
   T v = 0, gx = 0, gy = 0, gz = 0;
-  constexpr int SY = KD_GX, SZ = KD_GX * KD_GY;
+  constexpr int SY = GX, SZ = GX * GY;
 #pragma unroll
   for (int cz = 0; cz < 2; ++cz) {
 #pragma unroll
@@ -379,12 +382,13 @@ __device__ __forceinline__ uint32_t rank_in_cell(uint32_t* cnt, uint32_t k) {
   return base + (uint32_t)(lane - head);
 }
 
-template <typename T, int MODE>
+template <typename T, int MODE, int TX>
 __global__ __launch_bounds__(KD_NT) void kick_drift_kernel(Particles<T> p, const uint32_t* __restrict__ cell_start, int n,
                                                            GatherArgs<T> ga, uint32_t* rank, uint32_t* cnt,
                                                            int* err) {
   constexpr int NF = MODE == MODE_FULL ? 5 : (MODE == MODE_SCALAR ? 2 : 1);
   constexpr int NR = KD_TY * KD_TZ;                   // particle rows of the block
+  constexpr int KD_GX = KdTile<TX>::GX, KD_GY = KdTile<TX>::GY, KD_G = KdTile<TX>::G;
   constexpr int NTL = (KD_G + KD_NT - 1) / KD_NT;     // tile entries per thread and field
   static_assert(NR <= 64, "row scan in one wave");
   __shared__ T tile[NF][KD_G];
@@ -392,7 +396,7 @@ __global__ __launch_bounds__(KD_NT) void kick_drift_kernel(Particles<T> p, const
   const int m = n - 1;
   int bx, by, bz;
   xcd_block3(bx, by, bz);
-  const int x0 = bx * KD_TX, y0 = by * KD_TY, z0 = bz * KD_TZ;
+  const int x0 = bx * TX, y0 = by * KD_TY, z0 = bz * KD_TZ;
   const int tid = threadIdx.x;
   const long nn = (long)n * n;
   // field tile with periodic wrap: local (gx, gy, gz) <-> global (x0 - 1 + gx, ...), x fastest;
@@ -416,7 +420,7 @@ __global__ __launch_bounds__(KD_NT) void kick_drift_kernel(Particles<T> p, const
     if (tid < NR) {
       const int ly = tid % KD_TY, lz = tid / KD_TY;
       const long rb = ((long)(z0 + lz) * n + (y0 + ly)) * n;
-      const uint32_t b = cell_start[rb + x0], e = cell_start[rb + x0 + KD_TX];
+      const uint32_t b = cell_start[rb + x0], e = cell_start[rb + x0 + TX];
       rbeg[tid] = b;
       c = e - b;
     }
@@ -465,7 +469,7 @@ __global__ __launch_bounds__(KD_NT) void kick_drift_kernel(Particles<T> p, const
     const T wx[2] = {(T)1 - (T)fxd, (T)fxd}, wy[2] = {(T)1 - (T)fyd, (T)fyd}, wz[2] = {(T)1 - (T)fzd, (T)fzd};
     const int lx = ix - x0, ly = iy - y0, lz = iz - z0;  // in [0, T*) by construction of the rows
     T phi_p, gphi[3];
-    gather_lds(tile[0], lz, ly, lx, wx, wy, wz, hn, phi_p, gphi);
+    gather_lds<T, KD_GX, KD_GY>(tile[0], lz, ly, lx, wx, wy, wz, hn, phi_p, gphi);
     if (ga.corr) {
       // learned closure: CIC-interpolated correction to grad phi
       const long n3 = nn * n;
@@ -493,7 +497,7 @@ __global__ __launch_bounds__(KD_NT) void kick_drift_kernel(Particles<T> p, const
       vx = ux * ia; vy = uy * ia; vz = uz * ia;
     } else {
       T chi_p, gchi[3];
-      gather_lds(tile[1], lz, ly, lx, wx, wy, wz, hn, chi_p, gchi);
+      gather_lds<T, KD_GX, KD_GY>(tile[1], lz, ly, lx, wx, wy, wz, hn, chi_p, gchi);
       const T u2 = ux * ux + uy * uy + uz * uz;
       const T ie = rsqrt_(a * a + u2);
       const T e = (a * a + u2) * ie;
@@ -504,9 +508,9 @@ __global__ __launch_bounds__(KD_NT) void kick_drift_kernel(Particles<T> p, const
       T B[3] = {0, 0, 0};
       if constexpr (MODE == MODE_FULL) {
         T gb[3][3];  // gb[j][i] = d_i B_j
-        gather_lds(tile[2 % NF], lz, ly, lx, wx, wy, wz, hn, B[0], gb[0]);
-        gather_lds(tile[3 % NF], lz, ly, lx, wx, wy, wz, hn, B[1], gb[1]);
-        gather_lds(tile[4 % NF], lz, ly, lx, wx, wy, wz, hn, B[2], gb[2]);
+        gather_lds<T, KD_GX, KD_GY>(tile[2 % NF], lz, ly, lx, wx, wy, wz, hn, B[0], gb[0]);
+        gather_lds<T, KD_GX, KD_GY>(tile[3 % NF], lz, ly, lx, wx, wy, wz, hn, B[1], gb[1]);
+        gather_lds<T, KD_GX, KD_GY>(tile[4 % NF], lz, ly, lx, wx, wy, wz, hn, B[2], gb[2]);
         fx -= ux * gb[0][0] + uy * gb[1][0] + uz * gb[2][0];
         fy -= ux * gb[0][1] + uy * gb[1][1] + uz * gb[2][1];
         fz -= ux * gb[0][2] + uy * gb[1][2] + uz * gb[2][2];
@@ -536,20 +540,29 @@ __global__ __launch_bounds__(KD_NT) void kick_drift_kernel(Particles<T> p, const
   }
 }
 
+template <typename T, int TX>
+static void launch_kick_drift_tx(const Particles<T>& p, int n, const uint32_t* cell_start, const GatherArgs<T>& g,
+                                 uint32_t* rank, uint32_t* cnt, int* err, hipStream_t st) {
+  dim3 grid(n / TX, n / KD_TY, n / KD_TZ);
+  if (g.mode == MODE_NEWTONIAN)
+    hipLaunchKernelGGL((kick_drift_kernel<T, MODE_NEWTONIAN, TX>), grid, dim3(KD_NT), 0, st, p, cell_start, n, g, rank,
+                       cnt, err);
+  else if (g.mode == MODE_SCALAR)
+    hipLaunchKernelGGL((kick_drift_kernel<T, MODE_SCALAR, TX>), grid, dim3(KD_NT), 0, st, p, cell_start, n, g, rank,
+                       cnt, err);
+  else
+    hipLaunchKernelGGL((kick_drift_kernel<T, MODE_FULL, TX>), grid, dim3(KD_NT), 0, st, p, cell_start, n, g, rank, cnt,
+                       err);
+}
+
 template <typename T>
 void launch_kick_drift(const Particles<T>& p, long np, int n, const uint32_t* cell_start, const GatherArgs<T>& g,
                        uint32_t* rank, uint32_t* cnt, int* err, hipStream_t st) {
   (void)np;
-  dim3 grid(n / KD_TX, n / KD_TY, n / KD_TZ);
-  if (g.mode == MODE_NEWTONIAN)
-    hipLaunchKernelGGL((kick_drift_kernel<T, MODE_NEWTONIAN>), grid, dim3(KD_NT), 0, st, p, cell_start, n, g, rank, cnt,
-                       err);
-  else if (g.mode == MODE_SCALAR)
-    hipLaunchKernelGGL((kick_drift_kernel<T, MODE_SCALAR>), grid, dim3(KD_NT), 0, st, p, cell_start, n, g, rank, cnt,
-                       err);
+  if (n >= 32)
+    launch_kick_drift_tx<T, 32>(p, n, cell_start, g, rank, cnt, err, st);
   else
-    hipLaunchKernelGGL((kick_drift_kernel<T, MODE_FULL>), grid, dim3(KD_NT), 0, st, p, cell_start, n, g, rank, cnt,
-                       err);
+    launch_kick_drift_tx<T, 16>(p, n, cell_start, g, rank, cnt, err, st);
 }
 
 // ---------------------------------------------------------------------------
