@@ -287,6 +287,31 @@ def b_from_momentum(s_k, kt):
     return [np.where(k2 > 0, 4.0 / safe * (s_k[i] - k[i] * kdots), 0.0) for i in range(3)]
 
 
+def vector_source(sig_k, kt):
+    """Vector part of the trace-free source: w_j = P_jl khat_m Sigma_lm with P = delta - khat khat.
+
+    The spin-1 part of Sigma is khat_i w_j + khat_j w_i, and w = 0 at k = 0.
+    """
+    k = kt
+    k2 = k[0] ** 2 + k[1] ** 2 + k[2] ** 2
+    kn = np.sqrt(np.where(k2 > 0, k2, 1.0))
+    kh = [k[i] / kn for i in range(3)]
+    v = [sum(sig_k[SYM_INDEX[(l, m)]] * kh[m] for m in range(3)) for l in range(3)]
+    kv = kh[0] * v[0] + kh[1] * v[1] + kh[2] * v[2]
+    return [np.where(k2 > 0, v[j] - kh[j] * kv, 0.0) for j in range(3)]
+
+
+def b_parabolic_step(a2b_k, w, kt, dtau, a_mid):
+    """Vector part of Eq. 5: (d_tau + 2 H)(i kt_i B_j + i kt_j B_i) = khat_i w_j + khat_j w_i.
+
+    With B transverse this is d_tau (a^2 B_j) = -i a^2 w_j / |kt|; one step from
+    tau - dtau to tau with a^2 at the midpoint.  State and result: a^2 B(k).
+    """
+    k2 = kt[0] ** 2 + kt[1] ** 2 + kt[2] ** 2
+    kn = np.sqrt(np.where(k2 > 0, k2, 1.0))
+    return [np.where(k2 > 0, a2b_k[j] + dtau * a_mid * a_mid * (-1j) * w[j] / kn, 0.0) for j in range(3)]
+
+
 def tt_project(sig_k, kt):
     """Lambda^TT_{ij,kl} Sigma_kl = P_ik P_jl Sigma_kl - P_ij P_kl Sigma_kl / 2, P = delta - kt kt / kt^2."""
     k = kt
@@ -344,6 +369,7 @@ class OracleSim:
     u: np.ndarray
     tau: float
     ids: np.ndarray = None
+    b_route: str = "elliptic"  # full physics: B from Eq. 6 ("elliptic") or from the vector part of Eq. 5
     bg: Background = field(init=False)
 
     def __post_init__(self):
@@ -364,7 +390,10 @@ class OracleSim:
         hk0 = np.zeros((n, n, n // 2 + 1), dtype=np.complex128)
         self.h_k = [hk0.copy() for _ in range(6)]   # 6-component tensor spectrum and its time derivative
         self.pi_k = [hk0.copy() for _ in range(6)]
+        self.a2B_k = [hk0.copy() for _ in range(3)]  # a^2 B(k), the state of the parabolic B route
         self.last_sigma_k = None
+        if self.b_route not in ("elliptic", "parabolic"):
+            raise ValueError("b_route must be 'elliptic' or 'parabolic'")
 
     @property
     def n_p(self) -> int:
@@ -390,7 +419,7 @@ class OracleSim:
         gchi = grad(chi1, n)
         return E, J, K, gphi, gchi
 
-    def _solve_once(self, phi1, chi1, phidot, inv_dtau):
+    def _solve_once(self, phi1, chi1, phidot, inv_dtau, elliptic_b=True):
         n = self.n
         a = self.bg.a(self.tau)
         hc = self.bg.hconf(self.tau)
@@ -407,9 +436,11 @@ class OracleSim:
         sig_k = [fft3(s) * nyq for s in sig]
         chi = ifft3(chi_from_sigma(sig_k, kt, n), n)
         B = None
-        if self.physics == FULL:
+        self._B_k = None
+        if self.physics == FULL and elliptic_b:
             S = momentum_source(J, phi1, chi1, phidot, gphi, gchi)
-            B = [ifft3(bk, n) for bk in b_from_momentum([fft3(s) * nyq for s in S], kt)]
+            self._B_k = b_from_momentum([fft3(s) * nyq for s in S], kt)
+            B = [ifft3(bk, n) for bk in self._B_k]
         return phi, chi, B, sig_k
 
     def solve(self, dtau_prev: float):
@@ -450,21 +481,31 @@ class OracleSim:
             self.phi_prev = phi
             self.phi = phi
             self.chi = chi
-            if B is not None:
-                self.B = B
             self.dtau_last = 0.0
             if self.physics == FULL:
+                # the start takes B from the momentum constraint with either route; the parabolic
+                # route then integrates a^2 B from there
+                self.B = B
+                a = self.bg.a(self.tau)
+                self.a2B_k = [a * a * bk for bk in self._B_k]
                 self.h_k = [np.zeros_like(sig_k[0]) for _ in range(6)]
                 self.pi_k = [np.zeros_like(sig_k[0]) for _ in range(6)]
         else:
             phidot = (self.phi - self.phi_prev) / self.dtau_last if self.dtau_last > 0 else 0.0
-            phi, chi, B, sig_k = self._solve_once(self.phi, self.chi, phidot, 1.0 / dtau_prev)
+            parabolic = self.b_route == "parabolic"
+            phi, chi, B, sig_k = self._solve_once(self.phi, self.chi, phidot, 1.0 / dtau_prev,
+                                                  elliptic_b=not parabolic)
             if self.physics == FULL:
                 src = tt_project(sig_k, kt)
                 hc_half = self.bg.hconf(self.tau - 0.5 * dtau_prev)
                 for s in range(6):
                     self.h_k[s], self.pi_k[s] = crank_nicolson_tensor(
                         self.h_k[s], self.pi_k[s], src[s], k2, dtau_prev, hc_half)
+                if parabolic:
+                    a_mid = self.bg.a(self.tau - 0.5 * dtau_prev)
+                    self.a2B_k = b_parabolic_step(self.a2B_k, vector_source(sig_k, kt), kt, dtau_prev, a_mid)
+                    a = self.bg.a(self.tau)
+                    B = [ifft3(x / (a * a), n) for x in self.a2B_k]
                 self.B = B
             self.phi_prev = self.phi
             self.phi = phi

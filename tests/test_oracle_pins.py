@@ -531,3 +531,66 @@ def test_p15_translation_by_whole_cells():
     d = s2.pos - pm.wrap_positions(s1.pos + shift / n)
     d -= np.round(d)
     assert np.max(np.abs(d)) < 1e-13
+
+
+# --------------------------------------------------------------------------
+# P18: B from the vector part of the trace-free space-space equation (parabolic route)
+# --------------------------------------------------------------------------
+
+def _sym_from(T):
+    return [T[i, j] for i, j in pm.SYM]
+
+
+def test_p18_vector_source_projects_the_spin1_part():
+    kt = [np.array(v) for v in (0.7, -1.3, 0.4)]
+    kv = np.array([float(v) for v in kt])
+    kh = kv / np.linalg.norm(kv)
+    e = np.cross(kh, [0.2, 0.9, -0.4])
+    vec = np.outer(kh, e) + np.outer(e, kh)                      # spin-1
+    t1 = np.cross(kh, [1.0, 0.0, 0.0]); t1 /= np.linalg.norm(t1)
+    t2 = np.cross(kh, t1)
+    tt = np.outer(t1, t1) - np.outer(t2, t2)                      # spin-2
+    sc = np.outer(kh, kh) - np.eye(3) / 3                         # spin-0, trace-free
+    w = pm.vector_source(_sym_from(vec + 3.0 * tt - 2.0 * sc), kt)
+    assert np.allclose([float(x) for x in w], e, atol=1e-14)
+
+
+def test_p18_parabolic_step_integrates_a2_exactly_to_second_order():
+    """Constant vector source: a^2 B(tau) = -i w / |kt| * int a^2 dtau; EdS a^2 = (H0 tau / 2)^4."""
+    bg = pm.Background(320.0)
+    kt = [np.array(v) for v in (1.5, 0.0, 0.0)]
+    w = [np.array(0.0), np.array(2.0e-6), np.array(0.0)]
+    tau0, tau1 = bg.tau(0.02), bg.tau(0.1)
+    h0 = bg.h0
+    exact = -1j * 2.0e-6 / 1.5 * (h0 / 2) ** 4 * (tau1 ** 5 - tau0 ** 5) / 5
+    errs = []
+    for steps in (10, 20, 40):
+        d = (tau1 - tau0) / steps
+        state = [np.array(0j)] * 3
+        for i in range(steps):
+            t = tau0 + (i + 1) * d
+            state = pm.b_parabolic_step(state, w, kt, d, bg.a(t - 0.5 * d))
+        errs.append(abs(complex(state[1]) - exact) / abs(exact))
+        assert abs(complex(state[0])) == 0.0 and abs(complex(state[2])) == 0.0
+    assert errs[0] < 1e-2
+    assert 3.5 < errs[0] / errs[1] < 4.5 and 3.5 < errs[1] / errs[2] < 4.5
+
+
+def test_p18_parabolic_and_elliptic_routes_agree():
+    """The two B equations are equivalent through stress-energy conservation (Sec. 3.1, below Eq. 6):
+    on a smooth Zel'dovich flow they agree to the deposit's discretisation (measured ~5 %)."""
+    from synth import spectrum_power_law_m2, zeldovich_particles
+    from synth.ics import eds_a_of_tau
+    n, box, steps = 32, 320.0, 10
+    bg = pm.Background(box)
+    tau0 = bg.tau(0.02)
+    dtau = (bg.tau(0.05) - tau0) / steps
+    pos, u = zeldovich_particles(n, 1, spectrum_power_law_m2, box, 0.2, 0.02, 0.02, eds_a_of_tau(tau0 - 0.5 * dtau, box))
+    sims = [pm.OracleSim(n=n, box_mpch=box, physics=pm.FULL, pos=pos, u=u, tau=tau0, b_route=r)
+            for r in ("elliptic", "parabolic")]
+    for _ in range(steps):
+        for s in sims:
+            s.step(dtau)
+    num = math.sqrt(sum(np.sum((sims[1].B[j] - sims[0].B[j]) ** 2) for j in range(3)))
+    den = math.sqrt(sum(np.sum(sims[0].B[j] ** 2) for j in range(3)))
+    assert den > 0 and num / den < 0.1, num / den
