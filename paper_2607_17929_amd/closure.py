@@ -247,7 +247,7 @@ def calibrate_amplitude(params, n_p1: int, box: float, rms_cells: float, seeds, 
 
 
 def experiment(n_app: int = 512, n_train_p: int = 128, train_box: float = 512.0, n_boxes: int = 64,
-               iters: int = 12000, lr: float = 1e-3, augment: bool = True, calibrate: bool = True, log=print):
+               iters: int = 12000, lr: float = 1e-3, augment: bool = True, calibrate: bool = False, log=print):
     """Train on seeded boxes (1x and 2x meshes), apply to n_app^3 particles on an n_app^3 mesh and compare
     P(k) and cost with the plain n_app^3 and 2 n_app^3 meshes at a = 0.5."""
     from synth import spectrum_power_law_m2, zeldovich_particles
@@ -355,7 +355,8 @@ if __name__ == "__main__":
     ap.add_argument("--boxes", type=int, default=64)
     ap.add_argument("--iters", type=int, default=12000)
     ap.add_argument("--no-augment", action="store_true")
-    ap.add_argument("--no-calibrate", action="store_true")
+    ap.add_argument("--calibrate", action="store_true",
+                    help="scale the output by the amplitude that best matches the training boxes' 2x spectra")
     ap.add_argument("--out", default="gpurun_out/closure_experiment.json")
     ap.add_argument("--summarize", metavar="RESULT_JSON", help="print the markdown summary of a stored result")
     ap.add_argument("--command", default="python -u -m paper_2607_17929_amd.closure --out gpurun_out/closure_experiment.json")
@@ -365,7 +366,7 @@ if __name__ == "__main__":
             print(summary_md(json.load(f), a.command), end="")
         raise SystemExit(0)
     res, params = experiment(n_app=a.n_app, n_boxes=a.boxes, iters=a.iters, augment=not a.no_augment,
-                             calibrate=not a.no_calibrate, log=lambda s: print(s, flush=True))
+                             calibrate=a.calibrate, log=lambda s: print(s, flush=True))
     os.makedirs(os.path.dirname(a.out) or ".", exist_ok=True)
     with open(a.out, "w") as f:
         json.dump(res, f, indent=1)
