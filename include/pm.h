@@ -61,12 +61,19 @@ enum { PM_FP32 = 0, PM_FP64 = 1 };
 enum {
   PM_NEWTONIAN = 0, /* Newtonian limit (Sec. 3.2): lap psi = 4 pi G a^2 delta rho, phi = psi */
   PM_SCALAR = 1,    /* phi and chi (psi = phi - chi) */
-  PM_FULL = 2       /* phi, chi, B_i (elliptic, Eq. 6) and h_ij (Eq. 5, not fed back) */
+  PM_FULL = 2       /* phi, chi, B_i (elliptic, Eq. 6, or parabolic, see PM_FLAG_B_PARABOLIC) and h_ij
+                       (Eq. 5, not fed back) */
 };
 
 enum {
-  PM_FLAG_TIMINGS = 1u, /* record per-stage device times (pm_get_timings) */
-  PM_FLAG_CLOSURE = 2u  /* reserve workspace for the learned closure (pm_closure_*) */
+  PM_FLAG_TIMINGS = 1u,    /* record per-stage device times (pm_get_timings) */
+  PM_FLAG_CLOSURE = 2u,    /* reserve workspace for the learned closure (pm_closure_*) */
+  /* With PM_FULL: B_i from the vector part of the trace-free space-space equation (Sec. 3.1,
+   * Eq. 5), d_tau(a^2 B_j) = -i a^2 w_j / |kt| with w the spin-1 part of its source, integrated
+   * with a^2 at the midpoint of each step and started from the momentum constraint (Eq. 6) at the
+   * quasi-static start.  Later steps need 7 forward and 5 inverse transforms instead of 10 and 5
+   * (the paper's benchmark configuration, Sec. 4.1).  Ignored for other physics. */
+  PM_FLAG_B_PARABOLIC = 4u
 };
 
 /* field identifiers for pm_get_field / pm_set_field (real space, [z][y][x]) */

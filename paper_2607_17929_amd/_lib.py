@@ -12,6 +12,7 @@ PM_FP32, PM_FP64 = 0, 1
 PM_NEWTONIAN, PM_SCALAR, PM_FULL = 0, 1, 2
 PM_FLAG_TIMINGS = 1
 PM_FLAG_CLOSURE = 2
+PM_FLAG_B_PARABOLIC = 4
 PM_CLOSURE_NPARAM = 9971
 
 FIELDS = {

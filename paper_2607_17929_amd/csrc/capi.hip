@@ -26,7 +26,7 @@ bool is_pow2(long v) { return v > 0 && (v & (v - 1)) == 0; }
 // byte offsets of every device buffer inside the workspace
 struct Layout {
   size_t pos[2], mom[2], ids[2], rank, cnt, cell_start, bsum;
-  size_t dep, part, phi[3], chi, b[3], spec, hst[4], tw, kt, rowsum, scal, err;
+  size_t dep, part, phi[3], chi, b[3], spec, hst[4], a2b[3], tw, kt, rowsum, scal, err;
   // learned closure (PM_FLAG_CLOSURE): activations, gradients, packed weights, partials
   size_t cl_act[3], cl_dact[3], cl_corr, cl_dcorr, cl_wf, cl_wb, cl_bias, cl_part, cl_scal;
   bool closure, cl_train;
@@ -68,6 +68,8 @@ Layout make_layout(const pm_config& c) {
   for (int i = 0; i < 3; ++i) L.b[i] = mode == MODE_FULL ? take(n3 * rs) : 0;
   L.spec = take((size_t)nspec * L.spec_comp * 2 * rs);
   for (int i = 0; i < 4; ++i) L.hst[i] = mode == MODE_FULL ? take(L.spec_comp * 2 * rs) : 0;
+  const bool parabolic = mode == MODE_FULL && (c.flags & PM_FLAG_B_PARABOLIC) != 0;
+  for (int i = 0; i < 3; ++i) L.a2b[i] = parabolic ? take(L.spec_comp * 2 * rs) : 0;
   L.tw = take(n * 2 * rs);
   L.kt = take(n * rs);
   L.rowsum = take(n * n * 8);
@@ -235,10 +237,12 @@ void upload_tables(pm_ctx* c) {
 }
 
 // one forward transform + solve + inverse transform
+// smode: the solve's mode (c->mode, or MODE_FULLP for a parabolic-B step); b_op as in SolveArgs
 template <typename T>
 void solve_pass(pm_ctx* c, const T* phi1, const T* phi2, const T* chi1, double inv_dt, double inv_dtl, T* phi_out,
-                int tensor_op, double dtau, double hc_half) {
+                int tensor_op, double dtau, double hc_half, int smode, int b_op) {
   const Layout& L = c->L;
+  const int nsrc = mode_nsrc(smode);
   const double a = c->a_of(c->tau), hc = c->hc_of(c->tau), eb = c->ebar(a);
   SrcArgsH<T> s;
   s.dep = c->at<T>(L.dep);
@@ -249,17 +253,17 @@ void solve_pass(pm_ctx* c, const T* phi1, const T* phi2, const T* chi1, double i
   cplx<T>* spec = c->at<cplx<T>>(L.spec);
   const cplx<T>* tw = c->at<cplx<T>>(L.tw);
   c->stage_begin(PM_STAGE_FFT_X_FWD);
-  fft_r2c_x<T>(s, c->mode, c->n, L.nhp, spec, tw, c->st);
+  fft_r2c_x<T>(s, smode == MODE_FULLP ? MODE_SCALAR : smode, c->n, L.nhp, spec, tw, c->st);
   c->stage_end(PM_STAGE_FFT_X_FWD);
   c->stage_begin(PM_STAGE_FFT_YZ_FWD);
-  fft_cols<T>(c->n, L.nhp, spec, L.nsrc, false, false, tw, c->st);
-  fft_cols<T>(c->n, L.nhp, spec, L.nsrc, false, true, tw, c->st);
+  fft_cols<T>(c->n, L.nhp, spec, nsrc, false, false, tw, c->st);
+  fft_cols<T>(c->n, L.nhp, spec, nsrc, false, true, tw, c->st);
   c->stage_end(PM_STAGE_FFT_YZ_FWD);
   double* dc = c->at<double>(L.scal);
   c->stage_begin(PM_STAGE_KSOLVE);
   if (c->mode != MODE_NEWTONIAN) launch_sum_f64(s.rowsum, (long)c->n * c->n, dc, c->st);
   SolveArgs<T> sa;
-  sa.spec = spec; sa.comp_stride = L.spec_comp; sa.n = c->n; sa.nhp = L.nhp; sa.mode = c->mode;
+  sa.spec = spec; sa.comp_stride = L.spec_comp; sa.n = c->n; sa.nhp = L.nhp; sa.mode = smode;
   sa.kt = c->at<T>(L.kt);
   sa.hc = hc; sa.inv_dt = inv_dt; sa.ebar = eb; sa.inv_n3 = 1.0 / (double)c->n3;
   sa.dc = c->mode == MODE_NEWTONIAN ? nullptr : dc;
@@ -272,6 +276,11 @@ void solve_pass(pm_ctx* c, const T* phi1, const T* phi2, const T* chi1, double i
   sa.px = L.hst[3] ? c->at<cplx<T>>(L.hst[3]) : nullptr;
   sa.tensor_op = c->mode == MODE_FULL ? tensor_op : 0;
   sa.dtau = dtau; sa.hc_half = hc_half;
+  for (int i = 0; i < 3; ++i) sa.a2b[i] = L.a2b[i] ? c->at<cplx<T>>(L.a2b[i]) : nullptr;
+  sa.b_op = L.a2b[0] ? b_op : 0;
+  sa.a2_now = a * a;
+  const double am = c->a_of(c->tau - 0.5 * dtau);
+  sa.a2_mid = am * am;
   launch_solve<T>(sa, c->st);
   c->stage_end(PM_STAGE_KSOLVE);
   T* outs[8] = {phi_out, c->mode != MODE_NEWTONIAN ? c->at<T>(L.chi) : nullptr, nullptr, nullptr, nullptr,
@@ -294,14 +303,15 @@ pm_status do_solve(pm_ctx* c, double dtau_prev) {
   const T* chi = c->mode != MODE_NEWTONIAN ? c->at<T>(L.chi) : nullptr;
   if (c->mode == MODE_NEWTONIAN) {
     const int i_new = 3 - c->i_phi - c->i_prev;
-    solve_pass<T>(c, nullptr, nullptr, nullptr, 0, 0, slot(i_new), 0, 0, 0);
+    solve_pass<T>(c, nullptr, nullptr, nullptr, 0, 0, slot(i_new), 0, 0, 0, c->mode, 0);
     c->i_prev = c->i_phi;
     c->i_phi = i_new;
   } else if (dtau_prev <= 0) {
     // quasi-static start: two passes from phi = chi = 0, no time derivatives
     const int sa = 0, sb = 1, sc = 2;
-    solve_pass<T>(c, nullptr, nullptr, nullptr, 0, 0, slot(sa), 1, 0, 0);
-    solve_pass<T>(c, slot(sa), slot(sa), chi, 0, 0, slot(sb), 1, 0, 0);
+    // (the parabolic B route starts from the momentum constraint's B of the second pass)
+    solve_pass<T>(c, nullptr, nullptr, nullptr, 0, 0, slot(sa), 1, 0, 0, c->mode, 0);
+    solve_pass<T>(c, slot(sa), slot(sa), chi, 0, 0, slot(sb), 1, 0, 0, c->mode, 1);
     hipMemcpyAsync(slot(sc), slot(sb), c->n3 * sizeof(T), hipMemcpyDeviceToDevice, c->st);
     c->i_phi = sb;
     c->i_prev = sc;
@@ -310,8 +320,9 @@ pm_status do_solve(pm_ctx* c, double dtau_prev) {
     const int i_new = 3 - c->i_phi - c->i_prev;
     const double inv_dtl = c->dtau_last > 0 ? 1.0 / c->dtau_last : 0.0;
     const double hc_half = c->hc_of(c->tau - 0.5 * dtau_prev);
+    const int smode = (c->mode == MODE_FULL && c->L.a2b[0]) ? MODE_FULLP : c->mode;
     solve_pass<T>(c, slot(c->i_phi), slot(c->i_prev), chi, 1.0 / dtau_prev, inv_dtl, slot(i_new), 2, dtau_prev,
-                  hc_half);
+                  hc_half, smode, 2);
     c->i_prev = c->i_phi;
     c->i_phi = i_new;
     c->dtau_last = dtau_prev;
@@ -354,6 +365,8 @@ pm_status do_init(pm_ctx* c, const double* pos, const void* u, const uint32_t* i
     if (L.b[i]) c->zero(L.b[i], c->n3 * c->rs);
   for (int i = 0; i < 4; ++i)
     if (L.hst[i]) c->zero(L.hst[i], L.spec_comp * 2 * c->rs);
+  for (int i = 0; i < 3; ++i)
+    if (L.a2b[i]) c->zero(L.a2b[i], L.spec_comp * 2 * c->rs);
   Particles<T> p0 = c->parts<T>(0);
   launch_ingest<T>(dpos, du, dids, np, p0, c->n, c->at<uint32_t>(L.rank), c->at<uint32_t>(L.cnt),
                    c->at<int>(L.err), c->st);

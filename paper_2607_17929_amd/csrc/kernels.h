@@ -8,10 +8,11 @@
 
 namespace gpm {
 
-// source assembly modes of the forward pass X
-enum { MODE_RAW = 0, MODE_NEWTONIAN = 1, MODE_SCALAR = 2, MODE_FULL = 3 };
+// source assembly modes of the forward pass X (MODE_FULLP: full physics with B from the vector part
+// of the space-space equation -- the sources are those of MODE_SCALAR, the solve adds B and h)
+enum { MODE_RAW = 0, MODE_NEWTONIAN = 1, MODE_SCALAR = 2, MODE_FULL = 3, MODE_FULLP = 4 };
 __host__ __device__ constexpr int mode_nsrc(int mode) {
-  return mode == MODE_FULL ? 10 : (mode == MODE_SCALAR ? 7 : 1);
+  return mode == MODE_FULL ? 10 : ((mode == MODE_SCALAR || mode == MODE_FULLP) ? 7 : 1);
 }
 
 // host-side (FP64) arguments of the forward transform with source assembly
@@ -59,6 +60,10 @@ struct SolveArgs {
   cplx<T>* hp; cplx<T>* hx; cplx<T>* pp; cplx<T>* px;
   int tensor_op;      // 0: none, 1: reset to zero, 2: Crank-Nicolson step
   double dtau, hc_half;
+  // parabolic B state a^2 B(k) (3 half spectra, unnormalised like the sources)
+  cplx<T>* a2b[3];
+  int b_op;           // MODE_FULL: 1 = also store a^2 B of the elliptic solution; MODE_FULLP: step
+  double a2_now, a2_mid;
 };
 template <typename T> void launch_solve(const SolveArgs<T>& a, hipStream_t st);
 // rebuild the six h_ij half spectra from the polarisation state (diagnostic)

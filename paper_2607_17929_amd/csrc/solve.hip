@@ -99,17 +99,53 @@ __global__ __launch_bounds__(256) void solve_kernel(SolveArgs<T> a) {
     }
     sp[idx] = phi;
     sp[cs + idx] = chi;
-    if constexpr (MODE == MODE_FULL) {
-      // B: transverse projection of the momentum source
-      const cplx<T>* S = src + 7;
+    if constexpr (MODE == MODE_FULL || MODE == MODE_FULLP) {
       cplx<T> B[3] = {mk<T>(0, 0), mk<T>(0, 0), mk<T>(0, 0)};
-      if (!zero && !nyq) {
-        const T ik2 = (T)1 / k2;
-        const cplx<T> kd = mk((k[0] * S[0].x + k[1] * S[1].x + k[2] * S[2].x) * ik2,
-                              (k[0] * S[0].y + k[1] * S[1].y + k[2] * S[2].y) * ik2);
-        const T f = (T)4 * ik2 * s;
+      if constexpr (MODE == MODE_FULL) {
+        // B: transverse projection of the momentum source (Eq. 6)
+        const cplx<T>* S = src + 7;
+        cplx<T> Bu[3] = {mk<T>(0, 0), mk<T>(0, 0), mk<T>(0, 0)};
+        if (!zero && !nyq) {
+          const T ik2 = (T)1 / k2;
+          const cplx<T> kd = mk((k[0] * S[0].x + k[1] * S[1].x + k[2] * S[2].x) * ik2,
+                                (k[0] * S[0].y + k[1] * S[1].y + k[2] * S[2].y) * ik2);
+          const T f = (T)4 * ik2;
 #pragma unroll
-        for (int i = 0; i < 3; ++i) B[i] = mk(f * (S[i].x - k[i] * kd.x), f * (S[i].y - k[i] * kd.y));
+          for (int i = 0; i < 3; ++i) Bu[i] = mk(f * (S[i].x - k[i] * kd.x), f * (S[i].y - k[i] * kd.y));
+        }
+#pragma unroll
+        for (int i = 0; i < 3; ++i) B[i] = scale(Bu[i], s);
+        if (a.b_op == 1) {
+          // start of the parabolic route: a^2 B from the momentum constraint
+          const T a2 = (T)a.a2_now;
+#pragma unroll
+          for (int i = 0; i < 3; ++i) a.a2b[i][idx] = scale(Bu[i], a2);
+        }
+      } else {
+        // B from the vector part of Eq. 5: d_tau (a^2 B_j) = -i a^2 w_j / |kt|,
+        // w = P (Sigma khat) the spin-1 part of the trace-free source
+        cplx<T> st[3] = {mk<T>(0, 0), mk<T>(0, 0), mk<T>(0, 0)};
+        if (!zero && !nyq) {
+          const T kn = sqrt(k2), ikn = (T)1 / kn;
+          const T kh[3] = {k[0] * ikn, k[1] * ikn, k[2] * ikn};
+          const cplx<T> v[3] = {
+              mk(sg[0].x * kh[0] + sg[1].x * kh[1] + sg[2].x * kh[2], sg[0].y * kh[0] + sg[1].y * kh[1] + sg[2].y * kh[2]),
+              mk(sg[1].x * kh[0] + sg[3].x * kh[1] + sg[4].x * kh[2], sg[1].y * kh[0] + sg[3].y * kh[1] + sg[4].y * kh[2]),
+              mk(sg[2].x * kh[0] + sg[4].x * kh[1] + sg[5].x * kh[2], sg[2].y * kh[0] + sg[4].y * kh[1] + sg[5].y * kh[2])};
+          const cplx<T> kv = mk(kh[0] * v[0].x + kh[1] * v[1].x + kh[2] * v[2].x,
+                                kh[0] * v[0].y + kh[1] * v[1].y + kh[2] * v[2].y);
+          const T f = (T)a.dtau * (T)a.a2_mid * ikn;
+          const T out_scale = s / (T)a.a2_now;
+#pragma unroll
+          for (int j = 0; j < 3; ++j) {
+            const cplx<T> w = mk(v[j].x - kh[j] * kv.x, v[j].y - kh[j] * kv.y);
+            const cplx<T> old = a.a2b[j][idx];
+            st[j] = mk(old.x + f * w.y, old.y - f * w.x);  // -i w = (w.y, -w.x)
+            B[j] = scale(st[j], out_scale);
+          }
+        }
+#pragma unroll
+        for (int j = 0; j < 3; ++j) a.a2b[j][idx] = st[j];
       }
 #pragma unroll
       for (int i = 0; i < 3; ++i) sp[(2 + i) * cs + idx] = B[i];
@@ -148,6 +184,8 @@ void launch_solve(const SolveArgs<T>& a, hipStream_t st) {
     hipLaunchKernelGGL((solve_kernel<T, MODE_NEWTONIAN>), grid, dim3(256), 0, st, a);
   else if (a.mode == MODE_SCALAR)
     hipLaunchKernelGGL((solve_kernel<T, MODE_SCALAR>), grid, dim3(256), 0, st, a);
+  else if (a.mode == MODE_FULLP)
+    hipLaunchKernelGGL((solve_kernel<T, MODE_FULLP>), grid, dim3(256), 0, st, a);
   else
     hipLaunchKernelGGL((solve_kernel<T, MODE_FULL>), grid, dim3(256), 0, st, a);
 }

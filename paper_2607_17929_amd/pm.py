@@ -17,8 +17,11 @@ _PREC = {"fp32": L.PM_FP32, "fp64": L.PM_FP64}
 
 
 def make_config(n_mesh: int, n_particles: int, box_mpch: float, physics: str = "full", precision: str = "fp32",
-                timings: bool = False, closure: bool = False) -> L.PMConfig:
-    flags = (L.PM_FLAG_TIMINGS if timings else 0) | (L.PM_FLAG_CLOSURE if closure else 0)
+                timings: bool = False, closure: bool = False, b_route: str = "elliptic") -> L.PMConfig:
+    if b_route not in ("elliptic", "parabolic"):
+        raise ValueError("b_route must be 'elliptic' or 'parabolic'")
+    flags = ((L.PM_FLAG_TIMINGS if timings else 0) | (L.PM_FLAG_CLOSURE if closure else 0)
+             | (L.PM_FLAG_B_PARABOLIC if b_route == "parabolic" else 0))
     return L.PMConfig(n_mesh=n_mesh, precision=_PREC[precision], n_particles=n_particles, box_mpch=box_mpch,
                       physics=_PHYS[physics], flags=flags)
 
@@ -56,9 +59,9 @@ class PMContext:
 
     def __init__(self, n_mesh: int, n_particles: int, box_mpch: float, physics: str = "full",
                  precision: str = "fp32", timings: bool = False, device: str | torch.device = "cuda:0",
-                 stream: torch.cuda.Stream | None = None, closure: bool = False):
+                 stream: torch.cuda.Stream | None = None, closure: bool = False, b_route: str = "elliptic"):
         self.lib = L.load()
-        self.cfg = make_config(n_mesh, n_particles, box_mpch, physics, precision, timings, closure)
+        self.cfg = make_config(n_mesh, n_particles, box_mpch, physics, precision, timings, closure, b_route)
         self.n = n_mesh
         self.np = n_particles
         self.physics = physics

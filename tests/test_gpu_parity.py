@@ -19,9 +19,9 @@ pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 
 
-def _ctx(n, n_p, box, physics, precision, timings=False):
+def _ctx(n, n_p, box, physics, precision, timings=False, b_route="elliptic"):
     from paper_2607_17929_amd import PMContext
-    return PMContext(n, n_p, box, physics=physics, precision=precision, timings=timings)
+    return PMContext(n, n_p, box, physics=physics, precision=precision, timings=timings, b_route=b_route)
 
 
 def _say(*a):
@@ -106,11 +106,12 @@ def test_deposit_parity(case, precision):
 # whole steps
 # ---------------------------------------------------------------------------
 
-def _run_both(n, box, physics, precision, pos, u, tau0, dtaus, check_every=False):
-    ctx = _ctx(n, pos.shape[0], box, physics, precision)
+def _run_both(n, box, physics, precision, pos, u, tau0, dtaus, check_every=False, b_route="elliptic"):
+    ctx = _ctx(n, pos.shape[0], box, physics, precision, b_route=b_route)
     u_in = u.astype(ctx.np_dtype)
     ctx.init_particles(pos, u_in, tau0)
-    sim = opm.OracleSim(n=n, box_mpch=box, physics=physics, pos=pos, u=u_in.astype(np.float64), tau=tau0)
+    sim = opm.OracleSim(n=n, box_mpch=box, physics=physics, pos=pos, u=u_in.astype(np.float64), tau=tau0,
+                        b_route=b_route)
     worst = {}
     for i, dt in enumerate(dtaus):
         ctx.step(dt)
@@ -216,3 +217,29 @@ def test_nan_particles_are_reported():
     ctx.init_particles(pos, np.zeros((64, 3), np.float32), 10.0)
     with pytest.raises(PMError):
         ctx.sync()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_full_parabolic_b_route(precision):
+    """Full physics with B integrated from the vector part of the space-space equation (12 FFTs per step)."""
+    _say(f"{precision} full, parabolic B")
+    pos, u, tau0, dtau = config_particles("c1_32_scalar_fp64")
+    steps = 4 if precision == "fp64" else 10
+    worst, dxmax, urel, *_ = _run_both(32, 320.0, "full", precision, pos, u, tau0, [dtau] * steps,
+                                       check_every=precision == "fp64", b_route="parabolic")
+    _say(worst, dxmax, urel)
+    for k, v in worst.items():
+        assert v < FIELD_TOL[precision], (k, v)
+    assert dxmax < POS_TOL[precision]
+
+
+def test_full_parabolic_b_route_c2_shape_small():
+    """The parabolic route on C2's spectrum at 64^3 (several tiles), FP32, 10 steps."""
+    _say("fp32 c2-like 64^3 parabolic B")
+    pos, u, tau0, dtau = config_particles("c2_256_full", n=64)
+    box = 1024.0 * 64 / 256
+    worst, dxmax, urel, *_ = _run_both(64, box, "full", "fp32", pos, u, tau0, [dtau] * 10, b_route="parabolic")
+    _say(worst, dxmax, urel)
+    for k, v in worst.items():
+        assert v < FIELD_TOL["fp32"], (k, v)
+    assert dxmax < POS_TOL["fp32"]
