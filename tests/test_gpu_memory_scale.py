@@ -1,0 +1,76 @@
+"""Memory-scale run: 1024^3 particles on a 1024^3 mesh, box 4096 Mpc/h, the benchmark's spectrum, Zel'dovich
+start at a = 0.1, FP32 fields with FP64 positions, full physics (about 234 GB of the 288 GB of HBM).
+
+The oracle cannot run at this size (its FP64 state alone exceeds the host), and the FP64 GPU path needs
+about 395 GB, so the checks are invariants that hold at any size: CIC partition of unity of the deposit
+(sum of n00 = sum of the particle energies, sum of n0i = sum of the momenta), finite fields and positions
+after the start-up solve and three steps.  The per-stage times of the last step are printed.
+"""
+import numpy as np
+import pytest
+
+from oracle import pm as opm
+from synth import spectrum_power_law_m2, zeldovich_particles
+from synth.ics import eds_a_of_tau
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+N = 1024
+BOX = 4096.0
+
+
+def _say(msg):
+    print(msg, flush=True)
+
+
+def test_memory_scale_1024():
+    from paper_2607_17929_amd import PMContext
+    props = torch.cuda.get_device_properties(0)
+    _say(f"device memory {props.total_memory / 1e9:.0f} GB")
+    bg = opm.Background(BOX)
+    tau = bg.tau(0.1)
+    dtau = 0.01 * tau
+    _say("building the 1024^3 input")
+    pos, u = zeldovich_particles(N, 4, spectrum_power_law_m2, BOX, 0.2, 0.02, 0.1, eds_a_of_tau(tau - 0.5 * dtau, BOX))
+    u32 = u.astype(np.float32)
+    del u
+    ctx = PMContext(N, N ** 3, BOX, physics="full", precision="fp32", timings=True)
+    _say(f"workspace {ctx.ws_bytes / 1e9:.1f} GB")
+    ctx.init_particles(pos, u32, tau)
+    del pos
+    ctx.deposit()
+    a = bg.a(tau)
+    u64 = u32.astype(np.float64)
+    e_sum = float(np.sum(np.sqrt(a * a + np.sum(u64 * u64, axis=1))))
+    u_sum = u64.sum(axis=0)
+    del u64, u32
+    n00 = ctx.get_field("n00", device=True)
+    tot = float(torch.sum(n00, dtype=torch.float64))
+    del n00
+    _say(f"sum n00 {tot:.9e} vs sum e {e_sum:.9e}")
+    assert abs(tot - e_sum) < 1e-6 * e_sum
+    for i, c in enumerate(("n0x", "n0y", "n0z")):
+        f = ctx.get_field(c, device=True)
+        s = float(torch.sum(f, dtype=torch.float64))
+        del f
+        assert abs(s - u_sum[i]) < 1e-5 * (abs(u_sum[i]) + 1e-6 * e_sum), (c, s, u_sum[i])
+    ctx.solve_metric(0.0)
+    ctx.update_particles(dtau)
+    for _ in range(2):
+        ctx.step(dtau)
+    ctx.sync()
+    ctx.timings()  # time the next step alone
+    ctx.step(dtau)
+    ctx.sync()
+    st = ctx.timings()
+    launches = {"fft_yz_fwd": 2, "fft_zy_inv": 2}
+    per = {k: v[0] / v[1] / launches.get(k, 1) for k, v in st.items() if v[1]}
+    total = sum(v[0] for v in st.values())
+    _say("stage ms per launch: " + ", ".join(f"{k} {v:.2f}" for k, v in per.items()) + f"; step {total:.1f} ms")
+    for c in ("phi", "chi", "bx"):
+        f = ctx.get_field(c, device=True)
+        assert bool(torch.isfinite(f).all()), c
+        del f
+    p, _ = ctx.get_particles(device=True)
+    assert bool(torch.isfinite(p).all()) and float(p.min()) >= 0.0 and float(p.max()) < 1.0
