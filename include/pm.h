@@ -184,6 +184,18 @@ pm_status pm_sync(pm_ctx* ctx);
  * precision; uses the context's spectrum buffer as scratch. */
 pm_status pm_debug_fft(pm_ctx* ctx, const void* d_in, void* d_out, int direction);
 
+/* Shell-averaged matter power spectrum of the current particles on the context's
+ * mesh (evaluation of results, not part of a step; Sec. 4.1 computes spectra on the
+ * fly, Sec. 4.4 compares them): CIC count field, forward FFT, division by the CIC
+ * window prod_d sinc^2(pi m_d / n), |delta_k|^2 L^3 / n^6 minus the Poisson shot
+ * noise L^3 / N_p when subtract_shot_noise != 0, averaged over shells of width
+ * k_f = 2 pi / L, shell b = round(|m|) for b = 1 .. n/2.  Writes n/2 + 1 host
+ * values to each of k_out (mean |k| of the shell, h/Mpc), p_out ((Mpc/h)^3) and
+ * modes_out (modes in the shell; entry 0 and empty shells are 0).  Uses the
+ * deposit and spectrum buffers as scratch (call it between steps; the next
+ * pm_solve_metric needs a new pm_deposit) and synchronises the stream. */
+pm_status pm_power_spectrum(pm_ctx* ctx, int subtract_shot_noise, double* k_out, double* p_out, double* modes_out);
+
 /* Gradient of phi (centred differences, CIC-interpolated, as used by the kick)
  * at every particle, [n][3] in identifier order, context precision. */
 pm_status pm_gather_grad_phi(pm_ctx* ctx, void* out, int dst_on_device);

@@ -27,7 +27,7 @@ EXPORTS = (
     "pm_query_workspace", "pm_create", "pm_destroy", "pm_init_particles", "pm_deposit", "pm_solve_metric",
     "pm_update_particles", "pm_step", "pm_get_field", "pm_set_field", "pm_get_particles", "pm_get_time",
     "pm_background", "pm_tau_of_a", "pm_get_timings", "pm_sync", "pm_debug_fft", "pm_status_string",
-    "pm_last_error", "pm_gather_grad_phi", "pm_closure_set_params", "pm_closure_enable", "pm_closure_forward",
+    "pm_last_error", "pm_gather_grad_phi", "pm_power_spectrum", "pm_closure_set_params", "pm_closure_enable", "pm_closure_forward",
     "pm_closure_gather", "pm_closure_backward", "pm_closure_adam", "pm_closure_scale",
 )
 
@@ -80,6 +80,7 @@ def load():
         "pm_sync": [vp],
         "pm_debug_fft": [vp, vp, vp, C.c_int],
         "pm_gather_grad_phi": [vp, vp, C.c_int],
+        "pm_power_spectrum": [vp, C.c_int, vp, vp, vp],
         "pm_closure_set_params": [vp, vp, C.c_int],
         "pm_closure_enable": [vp, C.c_int],
         "pm_closure_forward": [vp, C.c_int],

@@ -148,36 +148,15 @@ def evaluate(ctx1: PMContext, snaps, params: torch.Tensor):
 # ---------------------------------------------------------------------------
 
 def power_spectrum(pos: torch.Tensor, m: int, box: float):
-    """CIC density on an m^3 mesh (library deposit), library FFT, CIC window deconvolution,
-    shot-noise subtraction and shells of width 2 pi / box; returns (k, P, modes) as numpy."""
+    """P(k) of particle positions on an m^3 measurement mesh with the library's estimator
+    (pm_power_spectrum: CIC counts, FFT, CIC window deconvolution, shot noise subtracted, shells of
+    width 2 pi / box); returns (k, P, modes) as numpy arrays."""
     n_p = pos.shape[0]
     ctx = PMContext(m, n_p, box, physics="newtonian", precision="fp32")
     ctx.init_particles(pos, torch.zeros_like(pos, dtype=torch.float32), 1.0)
-    ctx.deposit()  # n00 = a * (CIC count) with a(tau = 1)
-    rho = ctx.get_field("n00", device=True).double()
-    delta = (rho / rho.mean() - 1.0).float()
-    dk = ctx.debug_fft(delta, 1).to(torch.complex128)
+    out = ctx.power_spectrum(subtract_shot_noise=True)
     del ctx
-    kf = 2.0 * math.pi / box
-    mf = torch.fft.fftfreq(m, d=1.0 / m, device=dk.device, dtype=torch.float64)
-    mh = torch.arange(m // 2 + 1, device=dk.device, dtype=torch.float64)
-    mz, my, mx = mf[:, None, None], mf[None, :, None], mh[None, None, :]
-
-    def sinc(t):
-        return torch.where(t == 0, torch.ones_like(t), torch.sin(t) / torch.where(t == 0, torch.ones_like(t), t))
-
-    w = (sinc(math.pi * mx / m) * sinc(math.pi * my / m) * sinc(math.pi * mz / m)) ** 2
-    p = (dk.abs() / w) ** 2 * (box ** 3 / m ** 6) - box ** 3 / n_p
-    kmag = kf * torch.sqrt(mx * mx + my * my + mz * mz)
-    weight = torch.where((mx > 0) & (mx < m / 2), 2.0, 1.0).to(torch.float64).expand_as(kmag)
-    b = torch.round(kmag / kf).long()
-    nb = m // 2 + 1
-    sel = (b >= 1) & (b < nb)
-    cnt = torch.zeros(nb, dtype=torch.float64, device=dk.device).index_add_(0, b[sel], weight[sel])
-    ps = torch.zeros_like(cnt).index_add_(0, b[sel], (weight * p)[sel])
-    ks = torch.zeros_like(cnt).index_add_(0, b[sel], (weight * kmag)[sel])
-    good = cnt > 0
-    return (ks[good] / cnt[good]).cpu().numpy(), (ps[good] / cnt[good]).cpu().numpy(), cnt[good].cpu().numpy()
+    return out
 
 
 def run_pm(n_mesh: int, pos, u, tau0: float, tau1: float, steps: int, box: float, params=None, log=print):

@@ -737,6 +737,52 @@ pm_status pm_debug_fft(pm_ctx* c, const void* d_in, void* d_out, int direction) 
   return c->hip_check("debug_fft");
 }
 
+}  // extern "C"
+
+namespace {
+template <typename T>
+pm_status do_power_spectrum(pm_ctx* c, int subtract, double* k_out, double* p_out, double* modes_out) {
+  const Layout& L = c->L;
+  T* dep = c->at<T>(L.dep);
+  launch_deposit<T>(c->parts<T>(c->cur), c->at<uint32_t>(L.cell_start), c->n, 1, false, 1.0, dep, nullptr, nullptr,
+                    c->st);
+  SrcArgsH<T> s;
+  s.raw = dep;
+  cplx<T>* spec = c->at<cplx<T>>(L.spec);
+  fft_forward<T>(s, MODE_RAW, c->n, L.nhp, spec, 1, c->at<cplx<T>>(L.tw), c->st);
+  // the count field has been transformed: its buffer holds the partials and the result
+  const size_t scratch = (size_t)L.ndep * c->n3 * c->rs;
+  const int nblocks = pk_blocks(c->n, scratch);
+  const int nb = c->n / 2 + 1;
+  double* part = reinterpret_cast<double*>(dep);
+  const double box3 = 1.0;  // box units: P in units of L^3, converted below
+  launch_power_spectrum<T>(spec, c->n, L.nhp, box3 / ((double)c->np * (double)c->np), subtract ? box3 / (double)c->np : 0.0,
+                           nblocks, part, c->st);
+  std::vector<double> h(3 * nb);
+  (void)hipMemcpyAsync(h.data(), part + (long)nblocks * 3 * nb, 3 * nb * sizeof(double), hipMemcpyDeviceToHost, c->st);
+  (void)hipStreamSynchronize(c->st);
+  const double Lb = c->cfg.box_mpch, kf = 2.0 * M_PI / Lb;
+  for (int b = 0; b < nb; ++b) {
+    const double m = h[b];
+    modes_out[b] = m;
+    p_out[b] = m > 0 ? h[nb + b] / m * Lb * Lb * Lb : 0.0;
+    k_out[b] = m > 0 ? h[2 * nb + b] / m * kf : 0.0;
+  }
+  c->deposited = false;
+  return c->hip_check("power_spectrum");
+}
+}  // namespace
+
+extern "C" {
+
+pm_status pm_power_spectrum(pm_ctx* c, int subtract_shot_noise, double* k_out, double* p_out, double* modes_out) {
+  if (!c || !k_out || !p_out || !modes_out) return PM_EINVAL;
+  if (!c->have_particles) return c->fail(PM_ESTATE, "no particles");
+  pm_status s = DISPATCH(c, do_power_spectrum, c, subtract_shot_noise, k_out, p_out, modes_out);
+  if (s != PM_OK) return s;
+  return read_sticky(c);
+}
+
 pm_status pm_gather_grad_phi(pm_ctx* c, void* out, int dst_on_device) {
   if (!c || !out) return PM_EINVAL;
   if (!c->have_particles) return c->fail(PM_ESTATE, "no particles");

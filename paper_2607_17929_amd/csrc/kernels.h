@@ -74,6 +74,15 @@ void launch_tensor_components(cplx<T>* spec, long comp_stride, int n, int nhp, c
 void launch_sum_f64(const double* in, long count, double* out, hipStream_t st);
 void launch_sum_as_f64(const float* in, long count, double* out, hipStream_t st);
 
+// ---- pk.hip ----
+// blocks of the binning pass whose partials ((blocks + 1) rows of 3 (n/2 + 1) doubles) fit in scratch_bytes
+int pk_blocks(int n, size_t scratch_bytes);
+// shell sums [modes | P | |m|] of the power spectrum of a count field's half spectrum, written to
+// scratch + nblocks * 3 (n/2 + 1); amp2 = L^3 / N_p^2, shot = L^3 / N_p (or 0)
+template <typename T>
+void launch_power_spectrum(const cplx<T>* spec, int n, int nhp, double amp2, double shot, int nblocks, double* scratch,
+                           hipStream_t st);
+
 // ---- particles.hip ----
 template <typename T>
 struct Particles {

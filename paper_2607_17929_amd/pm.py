@@ -173,6 +173,18 @@ class PMContext:
     def sync(self):
         self._chk(self.lib.pm_sync(self.ctx), "pm_sync")
 
+    def power_spectrum(self, subtract_shot_noise: bool = True):
+        """Shell-averaged P(k) of the current particles on this mesh (pm_power_spectrum):
+        (k [h/Mpc], P [(Mpc/h)^3], modes) for the non-empty shells b = 1 .. n/2."""
+        nb = self.n // 2 + 1
+        k = np.zeros(nb)
+        p = np.zeros(nb)
+        m = np.zeros(nb)
+        self._chk(self.lib.pm_power_spectrum(self.ctx, int(bool(subtract_shot_noise)), k.ctypes.data, p.ctypes.data,
+                                             m.ctypes.data), "pm_power_spectrum")
+        good = m > 0
+        return k[good], p[good], m[good]
+
     def debug_fft(self, x: torch.Tensor, direction: int) -> torch.Tensor:
         n = self.n
         if direction == 1:

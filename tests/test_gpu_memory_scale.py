@@ -25,7 +25,11 @@ def _say(msg):
 
 
 def test_memory_scale_1024():
+    import gc
     from paper_2607_17929_amd import PMContext
+    # release what earlier tests left in the caching allocator: the workspace needs 234 GB
+    gc.collect()
+    torch.cuda.empty_cache()
     props = torch.cuda.get_device_properties(0)
     _say(f"device memory {props.total_memory / 1e9:.0f} GB")
     bg = opm.Background(BOX)
@@ -72,5 +76,8 @@ def test_memory_scale_1024():
         f = ctx.get_field(c, device=True)
         assert bool(torch.isfinite(f).all()), c
         del f
-    p, _ = ctx.get_particles(device=True)
-    assert bool(torch.isfinite(p).all()) and float(p.min()) >= 0.0 and float(p.max()) < 1.0
+    p, _ = ctx.get_particles()
+    assert bool(np.isfinite(p).all()) and float(p.min()) >= 0.0 and float(p.max()) < 1.0
+    del ctx
+    gc.collect()
+    torch.cuda.empty_cache()
