@@ -324,9 +324,10 @@ void launch_deposit(const Particles<T>& p, const uint32_t* cell_start, int n, in
 // and takes its rank inside its new cell (the sort recomputes the cell from
 // the stored position).
 // ---------------------------------------------------------------------------
-// Blocks are TX x 2 x 8 cells with TX = 32 (16 on a 16^3 mesh): rows of 32 cells keep the
-// row segments of the 4-byte particle arrays at whole 128-byte lines more often.
-constexpr int KD_TY = 2, KD_TZ = 8, KD_NT = 256;
+// Blocks are TX x 4 x 8 cells with TX = 32 (16 on a 16^3 mesh): rows of 32 cells keep the
+// row segments of the 4-byte particle arrays at whole 128-byte lines more often, and the field
+// tile is 2.6 values per cell of the block.
+constexpr int KD_TY = 4, KD_TZ = 8, KD_NT = 512;
 template <int TX> struct KdTile {
   static constexpr int GX = TX + 3, GY = KD_TY + 3, GZ = KD_TZ + 3, G = GX * GY * GZ;
 };
