@@ -30,8 +30,8 @@
  * synchronise the stream.  Functions return pm_status (0 = success, negative =
  * error) and never throw.  A failed HIP call or a non-finite particle
  * coordinate found on the device is reported as PM_EHIP / PM_ENAN by the next
- * synchronising call and is sticky until pm_init_particles().  One context
- * must not be used from two threads at once.
+ * synchronising call and is sticky until pm_init_particles() or
+ * pm_set_state().  One context must not be used from two threads at once.
  */
 #ifndef PM_H
 #define PM_H
@@ -195,6 +195,31 @@ pm_status pm_debug_fft(pm_ctx* ctx, const void* d_in, void* d_out, int direction
  * deposit and spectrum buffers as scratch (call it between steps; the next
  * pm_solve_metric needs a new pm_deposit) and synchronises the stream. */
 pm_status pm_power_spectrum(pm_ctx* ctx, int subtract_shot_noise, double* k_out, double* p_out, double* modes_out);
+
+/* Checkpoint and restart.  The paper writes particle and metric snapshots
+ * (Sec. 4.1) but does not describe a restart; this pair saves and restores
+ * everything the next steps depend on: the particles in their sorted order,
+ * the cell offsets of the sort, phi of the latest and the previous solve, chi,
+ * B_i, the tensor state (h and its time derivative, two polarisations, Sec. 3.1),
+ * the parabolic a^2 B state, the FP64 homogeneous-mode scalars, tau, the step
+ * counter, the last two time steps, the call-order state and, between
+ * pm_deposit and pm_solve_metric, the deposit.  Not included: the closure's
+ * parameters and its enable switch (bind them again after a restore).
+ * pm_get_state: blob NULL -> *bytes = the size the current state needs (it
+ * grows by the deposit between pm_deposit and pm_solve_metric).  Otherwise
+ * *bytes is the capacity of blob (PM_EINVAL, with *bytes set to the size, if it
+ * is too small); on success *bytes is the size written.  The blob is an opaque
+ * byte image for a context of the same n_mesh, precision, physics, B route and
+ * n_particles.  dst_on_device / src_on_device: the blob is device (1) or host (0)
+ * memory; either way both calls synchronise the stream before they return.
+ * pm_set_state validates the header (PM_EINVAL for a blob of another
+ * configuration, truncated or corrupt), clears a sticky device error and leaves
+ * the context as it was when the blob was taken.  The run after a restore agrees
+ * with the uninterrupted run to rounding: particles inside a cell are ordered by
+ * the sort's atomic counters, so sums over a cell's particles may round
+ * differently from run to run. */
+pm_status pm_get_state(pm_ctx* ctx, void* blob, size_t* bytes, int dst_on_device);
+pm_status pm_set_state(pm_ctx* ctx, const void* blob, size_t bytes, int src_on_device);
 
 /* Gradient of phi (centred differences, CIC-interpolated, as used by the kick)
  * at every particle, [n][3] in identifier order, context precision. */

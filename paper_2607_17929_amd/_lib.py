@@ -28,7 +28,7 @@ EXPORTS = (
     "pm_update_particles", "pm_step", "pm_get_field", "pm_set_field", "pm_get_particles", "pm_get_time",
     "pm_background", "pm_tau_of_a", "pm_get_timings", "pm_sync", "pm_debug_fft", "pm_status_string",
     "pm_last_error", "pm_gather_grad_phi", "pm_power_spectrum", "pm_closure_set_params", "pm_closure_enable", "pm_closure_forward",
-    "pm_closure_gather", "pm_closure_backward", "pm_closure_adam", "pm_closure_scale",
+    "pm_closure_gather", "pm_closure_backward", "pm_closure_adam", "pm_closure_scale", "pm_get_state", "pm_set_state",
 )
 
 
@@ -78,6 +78,8 @@ def load():
         "pm_tau_of_a": [cfgp, C.c_double, C.POINTER(C.c_double)],
         "pm_get_timings": [vp, C.POINTER(C.c_double), C.POINTER(C.c_int64), C.c_int],
         "pm_sync": [vp],
+        "pm_get_state": [vp, vp, C.POINTER(C.c_size_t), C.c_int],
+        "pm_set_state": [vp, vp, C.c_size_t, C.c_int],
         "pm_debug_fft": [vp, vp, vp, C.c_int],
         "pm_gather_grad_phi": [vp, vp, C.c_int],
         "pm_power_spectrum": [vp, C.c_int, vp, vp, vp],

@@ -105,6 +105,12 @@ pm_status check_config(const pm_config* c) {
   return PM_OK;
 }
 
+__global__ void zero_bytes_kernel(unsigned char* p, size_t bytes) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < bytes) p[i] = 0;
+}
+
+// p must be 16-byte aligned
 __global__ void zero_kernel(unsigned char* p, size_t bytes) {
   const size_t i = ((size_t)blockIdx.x * blockDim.x + threadIdx.x) * 16;
   if (i + 16 <= bytes) {
@@ -162,6 +168,10 @@ struct pm_ctx {
   void zero(size_t off, size_t bytes) {
     const size_t nthr = (bytes + 15) / 16;
     hipLaunchKernelGGL(zero_kernel, dim3((unsigned)((nthr + 255) / 256)), dim3(256), 0, st, ws + off, bytes);
+  }
+  // any alignment, small sizes
+  void zero_bytes(unsigned char* p, size_t bytes) {
+    hipLaunchKernelGGL(zero_bytes_kernel, dim3((unsigned)((bytes + 255) / 256)), dim3(256), 0, st, p, bytes);
   }
   void drain_events() {
     (void)hipStreamSynchronize(st);
@@ -781,6 +791,179 @@ pm_status pm_power_spectrum(pm_ctx* c, int subtract_shot_noise, double* k_out, d
   pm_status s = DISPATCH(c, do_power_spectrum, c, subtract_shot_noise, k_out, p_out, modes_out);
   if (s != PM_OK) return s;
   return read_sticky(c);
+}
+
+}  // extern "C"
+
+// ---- checkpoint of the time-stepping state ---------------------------------------------------
+namespace {
+
+constexpr uint64_t kStateMagic = 0x31455441545347ULL;  // "GSTATE1" (little-endian bytes)
+constexpr uint32_t kStateVersion = 1;
+constexpr size_t kStateHeader = 1024;
+constexpr int kStateMaxSec = 32;
+
+struct StateHeader {
+  uint64_t magic;
+  uint32_t version, nsec;
+  int32_t n_mesh, precision, physics, parabolic;
+  int64_t n_particles;
+  double tau, last_step, dtau_last;
+  int64_t steps;
+  int32_t deposited, solved, solved_once, pad;
+  uint64_t total;
+  uint64_t off[kStateMaxSec], bytes[kStateMaxSec];
+};
+static_assert(sizeof(StateHeader) <= kStateHeader, "state header too large");
+
+// workspace regions that make up the state: the sorted particles (buffer `cur`), the cell offsets
+// of the sort, phi of the latest and the previous solve, chi, B, the tensor and parabolic-B
+// spectra, the FP64 scalars and, between a deposit and its solve, the deposit
+int state_sections(const pm_ctx* c, int cur, int i_phi, int i_prev, bool with_dep, size_t* ws_off,
+                   size_t* bytes) {
+  const Layout& L = c->L;
+  const long np = c->np, n3 = c->n3;
+  const size_t rs = c->rs;
+  int k = 0;
+  auto add = [&](size_t off, size_t b) { ws_off[k] = off; bytes[k] = b; ++k; };
+  add(L.pos[cur], 3 * np * 8 + 2 * kSkew);
+  add(L.mom[cur], 3 * np * rs + 2 * kSkew);
+  add(L.ids[cur], np * 4);
+  add(L.cell_start, (n3 + 1) * 4);
+  add(L.phi[i_phi], n3 * rs);
+  add(L.phi[i_prev], n3 * rs);
+  if (L.chi) add(L.chi, n3 * rs);
+  for (int i = 0; i < 3; ++i)
+    if (L.b[i]) add(L.b[i], n3 * rs);
+  for (int i = 0; i < 4; ++i)
+    if (L.hst[i]) add(L.hst[i], L.spec_comp * 2 * rs);
+  for (int i = 0; i < 3; ++i)
+    if (L.a2b[i]) add(L.a2b[i], L.spec_comp * 2 * rs);
+  add(L.scal, 8 * 8);
+  if (with_dep) add(L.dep, (size_t)L.ndep * n3 * rs);
+  return k;
+}
+
+size_t state_blob_offsets(int nsec, const size_t* bytes, uint64_t* off) {
+  size_t o = kStateHeader;
+  for (int i = 0; i < nsec; ++i) {
+    off[i] = o;
+    o = align_up(o + bytes[i]);
+  }
+  return o;
+}
+
+}  // namespace
+
+extern "C" {
+
+pm_status pm_get_state(pm_ctx* c, void* blob, size_t* bytes, int dst_on_device) {
+  if (!c || !bytes) return PM_EINVAL;
+  if (!c->have_particles) return c->fail(PM_ESTATE, "no particles");
+  if (c->sticky) return (pm_status)c->sticky;
+  size_t ws_off[kStateMaxSec], sb[kStateMaxSec];
+  const int nsec = state_sections(c, c->cur, c->i_phi, c->i_prev, c->deposited, ws_off, sb);
+  StateHeader h;
+  memset(&h, 0, sizeof(h));
+  const size_t total = state_blob_offsets(nsec, sb, h.off);
+  if (!blob) {
+    *bytes = total;
+    return PM_OK;
+  }
+  if (*bytes < total) {
+    *bytes = total;
+    return c->fail(PM_EINVAL, "state buffer too small");
+  }
+  h.magic = kStateMagic;
+  h.version = kStateVersion;
+  h.nsec = (uint32_t)nsec;
+  h.n_mesh = c->n;
+  h.precision = c->cfg.precision;
+  h.physics = c->cfg.physics;
+  h.parabolic = c->L.a2b[0] ? 1 : 0;
+  h.n_particles = c->np;
+  h.tau = c->tau;
+  h.last_step = c->last_step;
+  h.dtau_last = c->dtau_last;
+  h.steps = c->steps;
+  h.deposited = c->deposited;
+  h.solved = c->solved;
+  h.solved_once = c->solved_once;
+  h.total = total;
+  for (int i = 0; i < nsec; ++i) h.bytes[i] = sb[i];
+  unsigned char* dst = reinterpret_cast<unsigned char*>(blob);
+  const hipMemcpyKind kind = dst_on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+  // the whole header block, zero beyond the struct
+  std::vector<unsigned char> head(kStateHeader, 0);
+  memcpy(head.data(), &h, sizeof(h));
+  if (dst_on_device)
+    (void)hipMemcpyAsync(dst, head.data(), kStateHeader, hipMemcpyHostToDevice, c->st);
+  else
+    memcpy(dst, head.data(), kStateHeader);
+  for (int i = 0; i < nsec; ++i) {
+    (void)hipMemcpyAsync(dst + h.off[i], c->ws + ws_off[i], sb[i], kind, c->st);
+    // zero the alignment gap after the section, so that equal states give equal blobs
+    const size_t end = h.off[i] + sb[i], next = i + 1 < nsec ? h.off[i + 1] : total;
+    if (next > end) {
+      if (dst_on_device) c->zero_bytes(dst + end, next - end);
+      else memset(dst + end, 0, next - end);
+    }
+  }
+  // the header copy reads host memory of this frame: wait for it (and for host destinations)
+  (void)hipStreamSynchronize(c->st);
+  *bytes = total;
+  pm_status s = c->hip_check("get_state");
+  if (s != PM_OK) return s;
+  return read_sticky(c);
+}
+
+pm_status pm_set_state(pm_ctx* c, const void* blob, size_t bytes, int src_on_device) {
+  if (!c || !blob) return PM_EINVAL;
+  if (bytes < kStateHeader) return c->fail(PM_EINVAL, "state blob too small");
+  StateHeader h;
+  if (src_on_device) {
+    if (hipMemcpyAsync(&h, blob, sizeof(h), hipMemcpyDeviceToHost, c->st) != hipSuccess ||
+        hipStreamSynchronize(c->st) != hipSuccess)
+      return c->fail(PM_EHIP, "reading the state header failed");
+  } else {
+    memcpy(&h, blob, sizeof(h));
+  }
+  if (h.magic != kStateMagic || h.version != kStateVersion) return c->fail(PM_EINVAL, "not a state blob");
+  if (h.n_mesh != c->n || h.precision != c->cfg.precision || h.physics != c->cfg.physics ||
+      h.parabolic != (c->L.a2b[0] ? 1 : 0) || h.n_particles != c->np)
+    return c->fail(PM_EINVAL, "state blob of another configuration");
+  if (!(h.tau > 0) || !isfinite(h.tau) || h.steps < 0 || h.total > bytes)
+    return c->fail(PM_EINVAL, "corrupt state header");
+  // restore into particle buffer 0 and phi slots 0 (latest) and 1 (previous)
+  size_t ws_off[kStateMaxSec], sb[kStateMaxSec];
+  uint64_t off[kStateMaxSec];
+  const int nsec = state_sections(c, 0, 0, 1, h.deposited != 0, ws_off, sb);
+  const size_t total = state_blob_offsets(nsec, sb, off);
+  if ((int)h.nsec != nsec || h.total != total) return c->fail(PM_EINVAL, "corrupt state header");
+  for (int i = 0; i < nsec; ++i)
+    if (h.off[i] != off[i] || h.bytes[i] != sb[i]) return c->fail(PM_EINVAL, "corrupt state header");
+  const unsigned char* src = reinterpret_cast<const unsigned char*>(blob);
+  const hipMemcpyKind kind = src_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+  for (int i = 0; i < nsec; ++i) (void)hipMemcpyAsync(c->ws + ws_off[i], src + off[i], sb[i], kind, c->st);
+  // the per-cell counters are zero between sorts; the device error flag starts clear
+  c->zero(c->L.cnt, c->n3 * 4);
+  c->zero(c->L.err, 64);
+  if (!src_on_device) (void)hipStreamSynchronize(c->st);
+  c->cur = 0;
+  c->i_phi = 0;
+  c->i_prev = 1;
+  c->tau = h.tau;
+  c->last_step = h.last_step;
+  c->dtau_last = h.dtau_last;
+  c->steps = h.steps;
+  c->deposited = h.deposited != 0;
+  c->solved = h.solved != 0;
+  c->solved_once = h.solved_once != 0;
+  c->have_particles = true;
+  c->cl_forwarded = false;
+  c->sticky = 0;
+  c->last_error.clear();
+  return c->hip_check("set_state");
 }
 
 pm_status pm_gather_grad_phi(pm_ctx* c, void* out, int dst_on_device) {

@@ -173,6 +173,28 @@ class PMContext:
     def sync(self):
         self._chk(self.lib.pm_sync(self.ctx), "pm_sync")
 
+    def get_state(self, device: bool = False):
+        """Checkpoint of the time-stepping state (pm_get_state): a uint8 numpy array, or a uint8
+        device tensor when `device`."""
+        nb = C.c_size_t(0)
+        self._chk(self.lib.pm_get_state(self.ctx, None, C.byref(nb), 0), "pm_get_state")
+        if device:
+            blob = torch.empty(nb.value, dtype=torch.uint8, device=self.device)
+            self._chk(self.lib.pm_get_state(self.ctx, C.c_void_p(_ptr(blob)), C.byref(nb), 1), "pm_get_state")
+            return blob
+        blob = np.empty(nb.value, dtype=np.uint8)
+        self._chk(self.lib.pm_get_state(self.ctx, blob.ctypes.data, C.byref(nb), 0), "pm_get_state")
+        return blob
+
+    def set_state(self, blob):
+        """Restore a checkpoint taken by get_state on a context of the same configuration."""
+        if isinstance(blob, torch.Tensor) and blob.device.type != "cpu":
+            b = blob.contiguous()
+            self._chk(self.lib.pm_set_state(self.ctx, C.c_void_p(_ptr(b)), b.numel(), 1), "pm_set_state")
+            return
+        a = np.ascontiguousarray(blob.cpu().numpy() if isinstance(blob, torch.Tensor) else blob, dtype=np.uint8)
+        self._chk(self.lib.pm_set_state(self.ctx, a.ctypes.data, a.size, 0), "pm_set_state")
+
     def power_spectrum(self, subtract_shot_noise: bool = True):
         """Shell-averaged P(k) of the current particles on this mesh (pm_power_spectrum):
         (k [h/Mpc], P [(Mpc/h)^3], modes) for the non-empty shells b = 1 .. n/2."""

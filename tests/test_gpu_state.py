@@ -1,0 +1,189 @@
+"""Checkpoint and restart through the C ABI (pm_get_state / pm_set_state).
+
+* A run restarted in a fresh context from a checkpoint continues like the uninterrupted run
+  (and, in FP64, like the oracle run over all steps): every part of the state (particles, phi of
+  the two latest solves, chi, B, the tensor state and the parabolic a^2 B state) feeds the later
+  steps, so a part left out shows up in the fields after the restart.
+* The blob survives a restore byte for byte (host and device blobs are the same bytes).
+* A checkpoint taken between pm_deposit and pm_solve_metric carries the deposit.
+* Blobs of another configuration, truncated or with a damaged header are rejected.
+* A sticky device error (non-finite phi set from the host, detected by the kick) is cleared by a
+  restore, after which the run goes on as before.
+
+Runs after a restore agree with the uninterrupted run to rounding, not bit for bit: particles
+inside a cell are ordered by the sort's atomic counters.
+"""
+import numpy as np
+import pytest
+
+from oracle import pm as opm
+from synth import config_particles
+from tests.helpers import gpu_fields, oracle_fields, periodic_max_dx, rel_l2
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+TOL = {"fp64": (1e-11, 1e-10), "fp32": (1e-5, 1e-4)}  # (fields rel-L2, positions in mesh spacings)
+
+
+def _say(msg):
+    print(msg, flush=True)
+
+
+def _ctx(n, n_p, box, physics, precision, b_route="elliptic"):
+    from paper_2607_17929_amd import PMContext
+    return PMContext(n, n_p, box, physics=physics, precision=precision, b_route=b_route)
+
+
+def _state_of(ctx, physics):
+    f = gpu_fields(ctx, physics)
+    f["phi_prev"] = ctx.get_field("phi_prev").astype(np.float64)
+    p, u = ctx.get_particles()
+    return f, p, u.astype(np.float64), ctx.time()
+
+
+CASES = [("fp64", "full", "parabolic"), ("fp64", "full", "elliptic"), ("fp64", "scalar", "elliptic"),
+         ("fp32", "full", "parabolic"), ("fp64", "newtonian", "elliptic")]
+
+
+@pytest.mark.parametrize("precision,physics,b_route", CASES)
+def test_restart_continues_the_run(precision, physics, b_route):
+    _say(f"restart {precision} {physics} {b_route}")
+    pos, u, tau0, dtau = config_particles("c1_32_scalar_fp64")
+    n, box = 32, 320.0
+    a = _ctx(n, pos.shape[0], box, physics, precision, b_route)
+    u_in = u.astype(a.np_dtype)
+    a.init_particles(pos, u_in, tau0)
+    for _ in range(3):
+        a.step(dtau)
+    blob = a.get_state()
+    for _ in range(4):
+        a.step(dtau)
+    ref = _state_of(a, physics)
+    del a
+    b = _ctx(n, pos.shape[0], box, physics, precision, b_route)
+    b.set_state(blob)
+    assert b.time()[2] == 3
+    for _ in range(4):
+        b.step(dtau)
+    got = _state_of(b, physics)
+    ftol, ptol = TOL[precision]
+    assert got[3] == ref[3]  # tau, a and the step count
+    for k in ref[0]:
+        assert rel_l2(got[0][k], ref[0][k]) < ftol, (k, rel_l2(got[0][k], ref[0][k]))
+    assert periodic_max_dx(got[1], ref[1], n) < ptol
+    assert rel_l2(got[2], ref[2]) < ftol
+    if precision == "fp64":
+        # the restarted run against the oracle over all seven steps
+        sim = opm.OracleSim(n=n, box_mpch=box, physics=physics, pos=pos, u=u, tau=tau0, b_route=b_route)
+        for _ in range(7):
+            sim.step(dtau)
+        of = oracle_fields(sim, physics)
+        for k in of:
+            assert rel_l2(got[0][k], of[k]) < 1e-10, (k, rel_l2(got[0][k], of[k]))
+        op, _ = sim.particles_by_id()
+        assert periodic_max_dx(got[1], op, n) < 1e-9
+
+
+def test_blob_round_trip_is_exact():
+    _say("state blob round trip")
+    pos, u, tau0, dtau = config_particles("c1_32_scalar_fp64")
+    a = _ctx(32, pos.shape[0], 320.0, "full", "fp32", "parabolic")
+    a.init_particles(pos, u.astype(np.float32), tau0)
+    for _ in range(2):
+        a.step(dtau)
+    host = a.get_state()
+    dev = a.get_state(device=True)
+    assert dev.numel() == host.size
+    assert np.array_equal(dev.cpu().numpy(), host)
+    b = _ctx(32, pos.shape[0], 320.0, "full", "fp32", "parabolic")
+    b.set_state(dev)
+    again = b.get_state()
+    assert np.array_equal(again, host)
+    # the restored context hands back the same fields and particles bit for bit
+    for k in ("phi", "phi_prev", "chi", "bx", "hxy"):
+        assert np.array_equal(a.get_field(k), b.get_field(k)), k
+    pa, ua = a.get_particles()
+    pb, ub = b.get_particles()
+    assert np.array_equal(pa, pb) and np.array_equal(ua, ub)
+
+
+def test_checkpoint_between_deposit_and_solve():
+    _say("state between deposit and solve")
+    pos, u, tau0, dtau = config_particles("c1_32_scalar_fp64")
+    a = _ctx(32, pos.shape[0], 320.0, "full", "fp64")
+    a.init_particles(pos, u, tau0)
+    a.step(dtau)
+    after_step = a.get_state().size
+    a.deposit()
+    blob = a.get_state()
+    assert blob.size >= after_step + 10 * 32 ** 3 * 8  # the ten deposit components travel with it
+    b = _ctx(32, pos.shape[0], 320.0, "full", "fp64")
+    b.set_state(blob)
+    for c in (a, b):
+        c.solve_metric(dtau)
+        c.update_particles(dtau)
+    fa, fb = gpu_fields(a, "full"), gpu_fields(b, "full")
+    for k in fa:
+        assert rel_l2(fb[k], fa[k]) < 1e-12, k
+    from paper_2607_17929_amd import PMError
+    with pytest.raises(PMError):
+        _ctx(32, pos.shape[0], 320.0, "full", "fp64").solve_metric(dtau)  # no state, no deposit
+
+
+def test_foreign_or_damaged_blobs_are_rejected():
+    from paper_2607_17929_amd import PMError
+    _say("state blob validation")
+    pos, u, tau0, dtau = config_particles("c1_32_scalar_fp64")
+    a = _ctx(32, pos.shape[0], 320.0, "scalar", "fp64")
+    a.init_particles(pos, u, tau0)
+    a.step(dtau)
+    blob = a.get_state()
+    for other in (_ctx(32, pos.shape[0], 320.0, "scalar", "fp32"), _ctx(32, pos.shape[0], 320.0, "full", "fp64"),
+                  _ctx(16, pos.shape[0], 320.0, "scalar", "fp64"), _ctx(32, pos.shape[0] - 1, 320.0, "scalar", "fp64")):
+        with pytest.raises(PMError) as e:
+            other.set_state(blob)
+        assert e.value.status == -1
+    with pytest.raises(PMError):
+        a.set_state(blob[: blob.size // 2])
+    bad = blob.copy()
+    bad[0] ^= 0xFF
+    with pytest.raises(PMError):
+        a.set_state(bad)
+    bad = blob.copy()
+    bad[96:104] = 0xFF  # the first section's offset
+    with pytest.raises(PMError):
+        a.set_state(bad)
+    # the context still holds its own state and steps on
+    a.step(dtau)
+    assert a.time()[2] == 2
+
+
+def test_restore_clears_a_sticky_device_error():
+    from paper_2607_17929_amd import PMError
+    _say("state restore after a device error")
+    pos, u, tau0, dtau = config_particles("c1_32_scalar_fp64")
+    a = _ctx(32, pos.shape[0], 320.0, "scalar", "fp64")
+    a.init_particles(pos, u, tau0)
+    for _ in range(2):
+        a.step(dtau)
+    blob = a.get_state()
+    ref = _ctx(32, pos.shape[0], 320.0, "scalar", "fp64")
+    ref.set_state(blob)
+    ref.step(dtau)
+    bad = np.full((32, 32, 32), np.nan)
+    a.set_field("phi", bad)
+    a.update_particles(dtau)  # non-finite kick: the kernel flags it and parks the particles
+    with pytest.raises(PMError) as e:
+        a.sync()
+    assert e.value.status == -4
+    with pytest.raises(PMError):
+        a.step(dtau)  # sticky
+    a.set_state(blob)
+    a.step(dtau)
+    fa, fr = gpu_fields(a, "scalar"), gpu_fields(ref, "scalar")
+    for k in fa:
+        assert rel_l2(fa[k], fr[k]) < 1e-12, k
+    pa, _ = a.get_particles()
+    pr, _ = ref.get_particles()
+    assert periodic_max_dx(pa, pr, 32) < 1e-10
