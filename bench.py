@@ -43,16 +43,16 @@ def stage_bytes(n: int, n_p: int, rs: int) -> dict:
     return {
         "deposit": n_p * P + 10 * F,
         "fft_x_fwd": 13 * F + 10 * S,
-        "fft_yz_fwd": 2 * 10 * S,        # per launch (two launches per stage)
-        "ksolve": 10 * S + 5 * S + 8 * S,
-        "fft_zy_inv": 2 * 5 * S,         # per launch (two launches per stage)
+        "fft_y_fwd": 2 * 10 * S,
+        "kspace": 10 * S + 5 * S + 8 * S,  # sources in, solutions out, tensor state in and out
+        "fft_y_inv": 2 * 5 * S,
         "fft_x_inv": 5 * S + 5 * F,
         "kick_drift": n_p * (2 * P + 4) + 5 * F,                  # state in and out, rank out, 5 fields in
         "sort": 16 * n ** 3 + n_p * (4 + 2 * (P + 4)),           # counts/offsets; rank, state and id in and out
     }
 
 
-LAUNCHES = {"fft_yz_fwd": 2, "fft_zy_inv": 2}
+LAUNCHES: dict = {}  # stages that run as several launches of one kernel (none)
 
 
 def measured_traffic(n: int, stage: str):

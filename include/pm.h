@@ -95,9 +95,9 @@ enum {
 enum {
   PM_STAGE_DEPOSIT = 0,    /* CIC deposit (+ FP64 energy sum) */
   PM_STAGE_FFT_X_FWD = 1,  /* source assembly + R2C along x */
-  PM_STAGE_FFT_YZ_FWD = 2, /* complex FFTs along y, then z */
-  PM_STAGE_KSOLVE = 3,     /* Fourier-space solves */
-  PM_STAGE_FFT_ZY_INV = 4, /* inverse complex FFTs along z, then y */
+  PM_STAGE_FFT_Y_FWD = 2,  /* complex FFTs along y */
+  PM_STAGE_KSPACE = 3,     /* complex FFTs along z, Fourier-space solves, inverse FFTs along z (one kernel) */
+  PM_STAGE_FFT_Y_INV = 4,  /* inverse complex FFTs along y */
   PM_STAGE_FFT_X_INV = 5,  /* C2R along x */
   PM_STAGE_KICK_DRIFT = 6, /* gather + kick + drift + cell key */
   PM_STAGE_SORT = 7,       /* counting sort: scan + scatter */

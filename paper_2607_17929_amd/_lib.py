@@ -20,7 +20,7 @@ FIELDS = {
     "phi": 10, "chi": 11, "bx": 12, "by": 13, "bz": 14, "phi_prev": 15,
     "hxx": 16, "hxy": 17, "hxz": 18, "hyy": 19, "hyz": 20, "hzz": 21,
 }
-STAGES = ("deposit", "fft_x_fwd", "fft_yz_fwd", "ksolve", "fft_zy_inv", "fft_x_inv", "kick_drift", "sort")
+STAGES = ("deposit", "fft_x_fwd", "fft_y_fwd", "kspace", "fft_y_inv", "fft_x_inv", "kick_drift", "sort")
 
 # names of every function include/pm.h declares
 EXPORTS = (

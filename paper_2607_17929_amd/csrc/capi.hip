@@ -26,7 +26,7 @@ bool is_pow2(long v) { return v > 0 && (v & (v - 1)) == 0; }
 // byte offsets of every device buffer inside the workspace
 struct Layout {
   size_t pos[2], mom[2], ids[2], rank, cnt, cell_start, bsum;
-  size_t dep, part, phi[3], chi, b[3], spec, hst[4], a2b[3], tw, kt, rowsum, scal, err;
+  size_t dep, part, phi[3], chi, b[3], spec, spec_out, hst, a2b, tw, kt, rowsum, scal, err;
   // learned closure (PM_FLAG_CLOSURE): activations, gradients, packed weights, partials
   size_t cl_act[3], cl_dact[3], cl_corr, cl_dcorr, cl_wf, cl_wb, cl_bias, cl_part, cl_scal;
   bool closure, cl_train;
@@ -66,10 +66,13 @@ Layout make_layout(const pm_config& c) {
   for (int i = 0; i < 3; ++i) L.phi[i] = take(n3 * rs);
   L.chi = mode != MODE_NEWTONIAN ? take(n3 * rs) : 0;
   for (int i = 0; i < 3; ++i) L.b[i] = mode == MODE_FULL ? take(n3 * rs) : 0;
+  // sources (component-interleaved half spectra) and the solutions of the Fourier-space kernel
   L.spec = take((size_t)nspec * L.spec_comp * 2 * rs);
-  for (int i = 0; i < 4; ++i) L.hst[i] = mode == MODE_FULL ? take(L.spec_comp * 2 * rs) : 0;
+  L.spec_out = take((size_t)L.nout * L.spec_comp * 2 * rs);
+  // per-mode state: tensor records of 4 and parabolic-B records of 3 complex values
+  L.hst = mode == MODE_FULL ? take(4 * L.spec_comp * 2 * rs) : 0;
   const bool parabolic = mode == MODE_FULL && (c.flags & PM_FLAG_B_PARABOLIC) != 0;
-  for (int i = 0; i < 3; ++i) L.a2b[i] = parabolic ? take(L.spec_comp * 2 * rs) : 0;
+  L.a2b = parabolic ? take(3 * L.spec_comp * 2 * rs) : 0;
   L.tw = take(n * 2 * rs);
   L.kt = take(n * rs);
   L.rowsum = take(n * n * 8);
@@ -261,48 +264,45 @@ void solve_pass(pm_ctx* c, const T* phi1, const T* phi2, const T* chi1, double i
   s.kap = c->kappa() / (a * a);
   s.ebar = eb; s.hc = hc; s.inv_dt = inv_dt; s.inv_dtl = inv_dtl;
   cplx<T>* spec = c->at<cplx<T>>(L.spec);
+  cplx<T>* spec_out = c->at<cplx<T>>(L.spec_out);
   const cplx<T>* tw = c->at<cplx<T>>(L.tw);
   c->stage_begin(PM_STAGE_FFT_X_FWD);
   fft_r2c_x<T>(s, smode == MODE_FULLP ? MODE_SCALAR : smode, c->n, L.nhp, spec, tw, c->st);
   c->stage_end(PM_STAGE_FFT_X_FWD);
-  c->stage_begin(PM_STAGE_FFT_YZ_FWD);
-  fft_cols<T>(c->n, L.nhp, spec, nsrc, false, false, tw, c->st);
-  fft_cols<T>(c->n, L.nhp, spec, nsrc, false, true, tw, c->st);
-  c->stage_end(PM_STAGE_FFT_YZ_FWD);
+  c->stage_begin(PM_STAGE_FFT_Y_FWD);
+  fft_cols<T>(c->n, L.nhp * nsrc, spec, 1, false, false, tw, c->st);
+  c->stage_end(PM_STAGE_FFT_Y_FWD);
   double* dc = c->at<double>(L.scal);
-  c->stage_begin(PM_STAGE_KSOLVE);
+  c->stage_begin(PM_STAGE_KSPACE);
   if (c->mode != MODE_NEWTONIAN) launch_sum_f64(s.rowsum, (long)c->n * c->n, dc, c->st);
   SolveArgs<T> sa;
-  sa.spec = spec; sa.comp_stride = L.spec_comp; sa.n = c->n; sa.nhp = L.nhp; sa.mode = smode;
+  sa.spec = spec; sa.out = spec_out; sa.n = c->n; sa.nhp = L.nhp; sa.mode = smode;
   sa.kt = c->at<T>(L.kt);
+  sa.tw = tw;
   sa.hc = hc; sa.inv_dt = inv_dt; sa.ebar = eb; sa.inv_n3 = 1.0 / (double)c->n3;
   sa.dc = c->mode == MODE_NEWTONIAN ? nullptr : dc;
   sa.kap_a2 = c->kappa() / (a * a);
   sa.n3_ebar = (double)c->n3 * eb;
   sa.phibar_out = dc + 1;
-  sa.hp = L.hst[0] ? c->at<cplx<T>>(L.hst[0]) : nullptr;
-  sa.hx = L.hst[1] ? c->at<cplx<T>>(L.hst[1]) : nullptr;
-  sa.pp = L.hst[2] ? c->at<cplx<T>>(L.hst[2]) : nullptr;
-  sa.px = L.hst[3] ? c->at<cplx<T>>(L.hst[3]) : nullptr;
+  sa.hst = L.hst ? c->at<cplx<T>>(L.hst) : nullptr;
   sa.tensor_op = c->mode == MODE_FULL ? tensor_op : 0;
   sa.dtau = dtau; sa.hc_half = hc_half;
-  for (int i = 0; i < 3; ++i) sa.a2b[i] = L.a2b[i] ? c->at<cplx<T>>(L.a2b[i]) : nullptr;
-  sa.b_op = L.a2b[0] ? b_op : 0;
+  sa.a2b = L.a2b ? c->at<cplx<T>>(L.a2b) : nullptr;
+  sa.b_op = L.a2b ? b_op : 0;
   sa.a2_now = a * a;
   const double am = c->a_of(c->tau - 0.5 * dtau);
   sa.a2_mid = am * am;
   launch_solve<T>(sa, c->st);
-  c->stage_end(PM_STAGE_KSOLVE);
+  c->stage_end(PM_STAGE_KSPACE);
   T* outs[8] = {phi_out, c->mode != MODE_NEWTONIAN ? c->at<T>(L.chi) : nullptr, nullptr, nullptr, nullptr,
                 nullptr, nullptr, nullptr};
   if (c->mode == MODE_FULL)
     for (int i = 0; i < 3; ++i) outs[2 + i] = c->at<T>(L.b[i]);
-  c->stage_begin(PM_STAGE_FFT_ZY_INV);
-  fft_cols<T>(c->n, L.nhp, spec, L.nout, true, true, tw, c->st);
-  fft_cols<T>(c->n, L.nhp, spec, L.nout, true, false, tw, c->st);
-  c->stage_end(PM_STAGE_FFT_ZY_INV);
+  c->stage_begin(PM_STAGE_FFT_Y_INV);
+  fft_cols<T>(c->n, L.nhp * L.nout, spec_out, 1, true, false, tw, c->st);
+  c->stage_end(PM_STAGE_FFT_Y_INV);
   c->stage_begin(PM_STAGE_FFT_X_INV);
-  fft_c2r_x<T>(c->n, L.nhp, spec, L.nout, outs, 1.0, tw, c->st);
+  fft_c2r_x<T>(c->n, L.nhp, spec_out, L.nout, outs, 1.0, tw, c->st);
   c->stage_end(PM_STAGE_FFT_X_INV);
 }
 
@@ -330,7 +330,7 @@ pm_status do_solve(pm_ctx* c, double dtau_prev) {
     const int i_new = 3 - c->i_phi - c->i_prev;
     const double inv_dtl = c->dtau_last > 0 ? 1.0 / c->dtau_last : 0.0;
     const double hc_half = c->hc_of(c->tau - 0.5 * dtau_prev);
-    const int smode = (c->mode == MODE_FULL && c->L.a2b[0]) ? MODE_FULLP : c->mode;
+    const int smode = (c->mode == MODE_FULL && c->L.a2b) ? MODE_FULLP : c->mode;
     solve_pass<T>(c, slot(c->i_phi), slot(c->i_prev), chi, 1.0 / dtau_prev, inv_dtl, slot(i_new), 2, dtau_prev,
                   hc_half, smode, 2);
     c->i_prev = c->i_phi;
@@ -373,10 +373,8 @@ pm_status do_init(pm_ctx* c, const double* pos, const void* u, const uint32_t* i
   if (L.chi) c->zero(L.chi, c->n3 * c->rs);
   for (int i = 0; i < 3; ++i)
     if (L.b[i]) c->zero(L.b[i], c->n3 * c->rs);
-  for (int i = 0; i < 4; ++i)
-    if (L.hst[i]) c->zero(L.hst[i], L.spec_comp * 2 * c->rs);
-  for (int i = 0; i < 3; ++i)
-    if (L.a2b[i]) c->zero(L.a2b[i], L.spec_comp * 2 * c->rs);
+  if (L.hst) c->zero(L.hst, 4 * L.spec_comp * 2 * c->rs);
+  if (L.a2b) c->zero(L.a2b, 3 * L.spec_comp * 2 * c->rs);
   Particles<T> p0 = c->parts<T>(0);
   launch_ingest<T>(dpos, du, dids, np, p0, c->n, c->at<uint32_t>(L.rank), c->at<uint32_t>(L.cnt),
                    c->at<int>(L.err), c->st);
@@ -592,13 +590,13 @@ pm_status pm_get_field(pm_ctx* c, int id, void* dst, int dst_on_device) {
     if (c->cfg.precision == PM_FP64) {
       cplx<double>* spec = c->at<cplx<double>>(L.spec);
       launch_tensor_components<double>(spec, L.spec_comp, c->n, L.nhp, c->at<double>(L.kt),
-                                       c->at<cplx<double>>(L.hst[0]), c->at<cplx<double>>(L.hst[1]), 0, c->st);
+                                       c->at<cplx<double>>(L.hst), c->st);
       double* out[1] = {c->at<double>(L.dep)};
       fft_inverse<double>(c->n, L.nhp, spec + comp * L.spec_comp, 1, out, 1.0 / c->n3, c->at<cplx<double>>(L.tw), c->st);
     } else {
       cplx<float>* spec = c->at<cplx<float>>(L.spec);
-      launch_tensor_components<float>(spec, L.spec_comp, c->n, L.nhp, c->at<float>(L.kt), c->at<cplx<float>>(L.hst[0]),
-                                      c->at<cplx<float>>(L.hst[1]), 0, c->st);
+      launch_tensor_components<float>(spec, L.spec_comp, c->n, L.nhp, c->at<float>(L.kt), c->at<cplx<float>>(L.hst),
+                                      c->st);
       float* out[1] = {c->at<float>(L.dep)};
       fft_inverse<float>(c->n, L.nhp, spec + comp * L.spec_comp, 1, out, 1.0 / c->n3, c->at<cplx<float>>(L.tw), c->st);
     }
@@ -835,10 +833,8 @@ int state_sections(const pm_ctx* c, int cur, int i_phi, int i_prev, bool with_de
   if (L.chi) add(L.chi, n3 * rs);
   for (int i = 0; i < 3; ++i)
     if (L.b[i]) add(L.b[i], n3 * rs);
-  for (int i = 0; i < 4; ++i)
-    if (L.hst[i]) add(L.hst[i], L.spec_comp * 2 * rs);
-  for (int i = 0; i < 3; ++i)
-    if (L.a2b[i]) add(L.a2b[i], L.spec_comp * 2 * rs);
+  if (L.hst) add(L.hst, 4 * L.spec_comp * 2 * rs);
+  if (L.a2b) add(L.a2b, 3 * L.spec_comp * 2 * rs);
   add(L.scal, 8 * 8);
   if (with_dep) add(L.dep, (size_t)L.ndep * n3 * rs);
   return k;
@@ -880,7 +876,7 @@ pm_status pm_get_state(pm_ctx* c, void* blob, size_t* bytes, int dst_on_device) 
   h.n_mesh = c->n;
   h.precision = c->cfg.precision;
   h.physics = c->cfg.physics;
-  h.parabolic = c->L.a2b[0] ? 1 : 0;
+  h.parabolic = c->L.a2b ? 1 : 0;
   h.n_particles = c->np;
   h.tau = c->tau;
   h.last_step = c->last_step;
@@ -930,7 +926,7 @@ pm_status pm_set_state(pm_ctx* c, const void* blob, size_t bytes, int src_on_dev
   }
   if (h.magic != kStateMagic || h.version != kStateVersion) return c->fail(PM_EINVAL, "not a state blob");
   if (h.n_mesh != c->n || h.precision != c->cfg.precision || h.physics != c->cfg.physics ||
-      h.parabolic != (c->L.a2b[0] ? 1 : 0) || h.n_particles != c->np)
+      h.parabolic != (c->L.a2b ? 1 : 0) || h.n_particles != c->np)
     return c->fail(PM_EINVAL, "state blob of another configuration");
   if (!(h.tau > 0) || !isfinite(h.tau) || h.steps < 0 || h.total > bytes)
     return c->fail(PM_EINVAL, "corrupt state header");

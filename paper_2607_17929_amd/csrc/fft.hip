@@ -1,16 +1,19 @@
 // 3D real-to-complex FFT passes for an n^3 periodic mesh on gfx950.
 //
 // Layouts (x fastest, as in the paper's rod decomposition, Sec. 2):
-//   real field      [z][y][x]                  n^3 values
-//   half spectrum   [z][y][kx], kx = 0 .. n/2  rows padded to NHP complex values
+//   real field      [z][y][x]                     n^3 values
+//   half spectrum   [z][y][kx][c], kx = 0 .. n/2  rows padded to NHP kx values;
+//                   the c components of a mode are adjacent (interleaved)
 // A forward 3D transform is three passes, each reading and writing the whole
 // half spectrum once:
 //   pass X  (rows along x, contiguous): source assembly fused in, R2C by the
 //           half-length complex FFT with the usual even/odd post-processing;
 //   pass Y  (columns along y) and pass Z (columns along z): batched complex
-//           FFTs on LDS tiles of n elements x C contiguous kx columns, so that
-//           every global access is a C*sizeof(complex) = 128-byte segment.
-// The inverse runs pass Z, pass Y and the C2R pass X.  Each 1D FFT is a
+//           FFTs on LDS tiles of n elements x C contiguous (kx, c) columns, so
+//           that every global access is a C*sizeof(complex) = 128-byte segment.
+// The inverse runs pass Z, pass Y and the C2R pass X.  In the PM solve, pass Z,
+// the Fourier-space solves and the inverse pass Z are one fused kernel
+// (solve.hip).  Each 1D FFT is a
 // Stockham auto-sort radix-8/4/2 transform done in place in LDS: every thread
 // loads its butterflies' inputs into registers, the workgroup synchronises,
 // and the results are written back, so one tile buffer suffices.  The first
@@ -18,78 +21,10 @@
 // writes straight to global memory.  Twiddles come from a table of
 // exp(-2 pi i j / n) computed in FP64 on the host.
 #include "common.h"
+#include "fft_lds.h"
 #include "kernels.h"
 
 namespace gpm {
-
-// ---------------------------------------------------------------------------
-// Column passes (Y and Z)
-// ---------------------------------------------------------------------------
-// One Stockham stage over a tile of C columns x N elements held in LDS as
-// [element][column].  Job j -> column j % C (fastest, so a wave touches
-// consecutive LDS words), butterfly index j / C.
-template <typename T, int N, int C, int NT, int S, bool INV, bool FROM_G, bool TO_G>
-__device__ __forceinline__ void col_stage(cplx<T>* sm, cplx<T>* g, uint32_t es, const cplx<T>* stw) {
-  constexpr int R = stage_radix(N, S);
-  constexpr int NS = stage_ns(N, S);
-  constexpr int J = N * C / R;
-  constexpr int PER = (J + NT - 1) / NT;
-  const int tid = threadIdx.x;
-  cplx<T> v[PER][R];
-#pragma unroll
-  for (int p = 0; p < PER; ++p) {
-    const int job = tid + p * NT;
-    if (J % NT == 0 || job < J) {
-      const int col = job % C, i = job / C;
-#pragma unroll
-      for (int r = 0; r < R; ++r) {
-        const int e = i + r * (N / R);
-        if (FROM_G) {
-          v[p][r] = g[(uint32_t)e * es + (uint32_t)col];
-        } else {
-          v[p][r] = sm[e * C + col];
-        }
-      }
-    }
-  }
-  if (!FROM_G) __syncthreads();
-#pragma unroll
-  for (int p = 0; p < PER; ++p) {
-    const int job = tid + p * NT;
-    if (J % NT == 0 || job < J) {
-      const int col = job % C, i = job / C;
-      const int k = i % NS;
-      if (NS > 1) {
-#pragma unroll
-        for (int r = 1; r < R; ++r) {
-          const cplx<T> w = stw[(r * k) * (N / (NS * R))];
-          v[p][r] = INV ? cmulc(v[p][r], w) : cmul(v[p][r], w);
-        }
-      }
-      dftR<T, R, INV>(v[p]);
-      const int j0 = (i / NS) * NS * R + k;
-#pragma unroll
-      for (int r = 0; r < R; ++r) {
-        const int e = j0 + r * NS;
-        if (TO_G) {
-          g[(uint32_t)e * es + (uint32_t)col] = v[p][r];
-        } else {
-          sm[e * C + col] = v[p][r];
-        }
-      }
-    }
-  }
-  if (!TO_G) __syncthreads();
-}
-
-template <typename T, int N, int C, int NT, int S, bool INV>
-__device__ __forceinline__ void col_stages(cplx<T>* sm, cplx<T>* g, uint32_t es, const cplx<T>* stw) {
-  constexpr int NSTG = nstages(N);
-  if constexpr (S < NSTG) {
-    col_stage<T, N, C, NT, S, INV, S == 0, S == NSTG - 1>(sm, g, es, stw);
-    col_stages<T, N, C, NT, S + 1, INV>(sm, g, es, stw);
-  }
-}
 
 // grid: x = column tile, y = outer index, z = component.  Rows are padded to a
 // multiple of C columns, so every tile is whole (the padding columns are
@@ -102,8 +37,13 @@ __global__ __launch_bounds__(NT) void fft_cols_kernel(cplx<T>* data, uint32_t es
   __shared__ cplx<T> stw[N];
   for (int j = threadIdx.x; j < N; j += NT) stw[j] = tw[j];
   cplx<T>* g = data + (long)blockIdx.z * comp_stride + (long)blockIdx.y * outer_stride + (long)blockIdx.x * C;
-  col_stages<T, N, C, NT, 0, INV>(sm, g, es, stw);
+  col_stages<T, N, C, NT, 0, INV, true, true, uint32_t>(sm, g, es, g, es, stw);
 }
+
+// LDS line stride (complex values) of pass X: M + 7 makes the line stride 14 words modulo the 64
+// banks (FP32; 28 for FP64), so that a wave reading one k of up to ten component lines, and the
+// next k's, spreads over the banks
+__host__ __device__ constexpr int x_line_stride(int m) { return m + 7; }
 
 // ---------------------------------------------------------------------------
 // Row FFTs in LDS (pass X): L lines of M complex values, line stride LS.
@@ -255,24 +195,25 @@ __device__ __forceinline__ T assemble_point(const SrcArgs<T>& a, int n, int x, i
 // Pass X forward: assembly + R2C.  grid: x = y-chunk (RY rows), y = z plane.
 // ---------------------------------------------------------------------------
 template <typename T, int N, int MODE, int RY, int NT>
-__global__ __launch_bounds__(NT) void fft_x_r2c_kernel(SrcArgs<T> a, cplx<T>* spec, long comp_stride, int nhp,
+__global__ __launch_bounds__(NT) void fft_x_r2c_kernel(SrcArgs<T> a, cplx<T>* spec, int nhp,
                                                        const cplx<T>* __restrict__ tw) {
   constexpr int M = N / 2;
+  constexpr int LS = x_line_stride(M);
   constexpr int NSRC = mode_nsrc(MODE);
   constexpr int L = NSRC * RY;
-  __shared__ T sm[NSRC * RY * N];
+  __shared__ T sm[L * 2 * LS];
   __shared__ cplx<T> stw[N];
   __shared__ double red[RY][NT / 64];
   const int y0 = blockIdx.x * RY, z = blockIdx.y;
   const int tid = threadIdx.x;
   for (int j = tid; j < N; j += NT) stw[j] = tw[j];
-  // 1. assemble the sources of RY rows into LDS rows [c][r][x]
+  // 1. assemble the sources of RY rows into LDS lines [c][r] of LS complex values
   double acc[RY];
 #pragma unroll
   for (int r = 0; r < RY; ++r) acc[r] = 0.0;
   for (int p = tid; p < RY * N; p += NT) {
     const int r = p / N, x = p % N;
-    const T s0 = assemble_point<T, MODE>(a, N, x, y0 + r, z, sm + r * N + x, RY * N);
+    const T s0 = assemble_point<T, MODE>(a, N, x, y0 + r, z, sm + r * 2 * LS + x, RY * 2 * LS);
 #pragma unroll
     for (int rr = 0; rr < RY; ++rr)
       if (rr == r) acc[rr] += (double)s0;
@@ -297,12 +238,15 @@ __global__ __launch_bounds__(NT) void fft_x_r2c_kernel(SrcArgs<T> a, cplx<T>* sp
   }
   // 2. half-length complex FFT of every row (pairs of reals are complex values)
   cplx<T>* cs = reinterpret_cast<cplx<T>*>(sm);
-  row_stages<T, M, L, M, NT, 0, false>(cs, stw, 2);
-  // 3. post-process Z_k -> X_k (k = 0..M) and store the rows
+  row_stages<T, M, L, LS, NT, 0, false>(cs, stw, 2);
+  // 3. post-process Z_k -> X_k (k = 0..M) and store the rows, component fastest: the
+  //    spectrum is component-interleaved, so the stores of a row are contiguous
   for (int job = tid; job < L * (M + 1); job += NT) {
-    const int line = job / (M + 1), k = job % (M + 1);
-    const cplx<T> zk = cs[line * M + (k == M ? 0 : k)];
-    const cplx<T> zc = conj(cs[line * M + (k == 0 ? 0 : M - k)]);
+    const int c = job % NSRC, rk = job / NSRC;
+    const int k = rk % (M + 1), r = rk / (M + 1);
+    const int line = c * RY + r;
+    const cplx<T> zk = cs[line * LS + (k == M ? 0 : k)];
+    const cplx<T> zc = conj(cs[line * LS + (k == 0 ? 0 : M - k)]);
     const cplx<T> ev = scale(zk + zc, (T)0.5);
     const cplx<T> od = scale(zk - zc, (T)0.5);  // = i * O_k
     // X_k = E_k + W^k O_k with O_k = -i * od
@@ -310,8 +254,7 @@ __global__ __launch_bounds__(NT) void fft_x_r2c_kernel(SrcArgs<T> a, cplx<T>* sp
     const cplx<T> wk = (k == M) ? mk<T>(-1, 0) : w;
     const cplx<T> o = mk(od.y, -od.x);
     const cplx<T> xk = ev + cmul(wk, o);
-    const int c = line / RY, r = line % RY;
-    spec[c * comp_stride + ((long)z * N + (y0 + r)) * nhp + k] = xk;
+    spec[(((long)z * N + (y0 + r)) * nhp + k) * NSRC + c] = xk;
   }
 }
 
@@ -324,27 +267,29 @@ struct OutPtrs {
 };
 
 template <typename T, int N, int NOUT, int RY, int NT>
-__global__ __launch_bounds__(NT) void fft_x_c2r_kernel(const cplx<T>* spec, long comp_stride, int nhp, OutPtrs<T> out,
-                                                       T out_scale, const cplx<T>* __restrict__ tw) {
+__global__ __launch_bounds__(NT) void fft_x_c2r_kernel(const cplx<T>* spec, int nhp, OutPtrs<T> out, T out_scale,
+                                                       const cplx<T>* __restrict__ tw) {
   constexpr int M = N / 2;
+  constexpr int LS = x_line_stride(M);
   constexpr int L = NOUT * RY;
-  __shared__ cplx<T> cs[L * M];
+  __shared__ cplx<T> cs[L * LS];
   __shared__ cplx<T> stw[N];
   const int y0 = blockIdx.x * RY, z = blockIdx.y;
   const int tid = threadIdx.x;
   // 1. pre-process X_k -> Z_k = E_k + i O_k, E_k = X_k + conj X_{M-k}, O_k = (X_k - conj X_{M-k}) W^-k;
-  //    the spectrum reads are issued first, the twiddle table is staged while they are in flight
+  //    the spectrum (component-interleaved) is read component fastest, so that the loads of a row
+  //    are contiguous; the reads are issued first, the twiddle table is staged while they are in flight
   constexpr int PJ = (L * M + NT - 1) / NT;
   cplx<T> xk[PJ], xm[PJ];
 #pragma unroll
   for (int q = 0; q < PJ; ++q) {
     const int job = tid + q * NT;
     if ((L * M) % NT == 0 || job < L * M) {
-      const int line = job / M, k = job % M;
-      const int c = line / RY, r = line % RY;
-      const cplx<T>* row = spec + c * comp_stride + ((long)z * N + (y0 + r)) * nhp;
-      xk[q] = row[k];
-      xm[q] = row[M - k];
+      const int c = job % NOUT, rk = job / NOUT;
+      const int k = rk % M, r = rk / M;
+      const cplx<T>* row = spec + ((long)z * N + (y0 + r)) * nhp * NOUT;
+      xk[q] = row[k * NOUT + c];
+      xm[q] = row[(M - k) * NOUT + c];
     }
   }
   for (int j = tid; j < N; j += NT) stw[j] = tw[j];
@@ -353,7 +298,9 @@ __global__ __launch_bounds__(NT) void fft_x_c2r_kernel(const cplx<T>* spec, long
   for (int q = 0; q < PJ; ++q) {
     const int job = tid + q * NT;
     if ((L * M) % NT == 0 || job < L * M) {
-      const int line = job / M, k = job % M;
+      const int c = job % NOUT, rk = job / NOUT;
+      const int k = rk % M, r = rk / M;
+      const int line = c * RY + r;
       cplx<T> a = xk[q], b = xm[q];
       if (k == 0) {
         a.y = 0;
@@ -362,17 +309,17 @@ __global__ __launch_bounds__(NT) void fft_x_c2r_kernel(const cplx<T>* spec, long
       const cplx<T> bc = conj(b);
       const cplx<T> ev = a + bc;
       const cplx<T> od = cmulc(a - bc, stw[k]);
-      cs[line * M + k] = mk(ev.x - od.y, ev.y + od.x);
+      cs[line * LS + k] = mk(ev.x - od.y, ev.y + od.x);
     }
   }
   __syncthreads();
-  row_stages<T, M, L, M, NT, 0, true>(cs, stw, 2);
+  row_stages<T, M, L, LS, NT, 0, true>(cs, stw, 2);
   // 2. z_n = x_{2n} + i x_{2n+1}: the LDS row is the real output row
   const T* rs = reinterpret_cast<const T*>(cs);
   for (int job = tid; job < L * N; job += NT) {
     const int line = job / N, x = job % N;
     const int c = line / RY, r = line % RY;
-    out.p[c][((long)z * N + (y0 + r)) * N + x] = rs[line * N + x] * out_scale;
+    out.p[c][((long)z * N + (y0 + r)) * N + x] = rs[line * 2 * LS + x] * out_scale;
   }
 }
 
@@ -410,23 +357,19 @@ template <typename T, int N>
 static void launch_r2c(const SrcArgs<T>& a, int mode, cplx<T>* spec, int nhp, const cplx<T>* tw, hipStream_t st) {
   constexpr int RY = rows_per_block<T, N>();
   constexpr int NT = 256;
-  const long comp_stride = (long)N * N * nhp;
   dim3 grid(N / RY, N);
   switch (mode) {
     case MODE_RAW:
-      hipLaunchKernelGGL((fft_x_r2c_kernel<T, N, MODE_RAW, RY, NT>), grid, dim3(NT), 0, st, a, spec, comp_stride, nhp, tw);
+      hipLaunchKernelGGL((fft_x_r2c_kernel<T, N, MODE_RAW, RY, NT>), grid, dim3(NT), 0, st, a, spec, nhp, tw);
       break;
     case MODE_NEWTONIAN:
-      hipLaunchKernelGGL((fft_x_r2c_kernel<T, N, MODE_NEWTONIAN, RY, NT>), grid, dim3(NT), 0, st, a, spec, comp_stride,
-                         nhp, tw);
+      hipLaunchKernelGGL((fft_x_r2c_kernel<T, N, MODE_NEWTONIAN, RY, NT>), grid, dim3(NT), 0, st, a, spec, nhp, tw);
       break;
     case MODE_SCALAR:
-      hipLaunchKernelGGL((fft_x_r2c_kernel<T, N, MODE_SCALAR, RY, NT>), grid, dim3(NT), 0, st, a, spec, comp_stride, nhp,
-                         tw);
+      hipLaunchKernelGGL((fft_x_r2c_kernel<T, N, MODE_SCALAR, RY, NT>), grid, dim3(NT), 0, st, a, spec, nhp, tw);
       break;
     default:
-      hipLaunchKernelGGL((fft_x_r2c_kernel<T, N, MODE_FULL, RY, NT>), grid, dim3(NT), 0, st, a, spec, comp_stride, nhp,
-                         tw);
+      hipLaunchKernelGGL((fft_x_r2c_kernel<T, N, MODE_FULL, RY, NT>), grid, dim3(NT), 0, st, a, spec, nhp, tw);
       break;
   }
 }
@@ -437,10 +380,8 @@ static void launch_c2r_n(const cplx<T>* spec, int nhp, const OutPtrs<T>& out, T 
   constexpr int RY0 = rows_per_block<T, N>();
   constexpr int RY = (NOUT > 2 && RY0 > 1) ? RY0 / 2 : RY0;
   constexpr int NT = 256;
-  const long comp_stride = (long)N * N * nhp;
   dim3 grid(N / RY, N);
-  hipLaunchKernelGGL((fft_x_c2r_kernel<T, N, NOUT, RY, NT>), grid, dim3(NT), 0, st, spec, comp_stride, nhp, out, scale_,
-                     tw);
+  hipLaunchKernelGGL((fft_x_c2r_kernel<T, N, NOUT, RY, NT>), grid, dim3(NT), 0, st, spec, nhp, out, scale_, tw);
 }
 
 template <typename T, int N>
@@ -495,15 +436,15 @@ template <typename T>
 void fft_forward(const SrcArgsH<T>& ah, int mode, int n, int nhp, cplx<T>* spec, int ncomp, const cplx<T>* tw,
                  hipStream_t st) {
   fft_r2c_x<T>(ah, mode, n, nhp, spec, tw, st);
-  fft_cols<T>(n, nhp, spec, ncomp, false, false, tw, st);
-  fft_cols<T>(n, nhp, spec, ncomp, false, true, tw, st);
+  fft_cols<T>(n, nhp * ncomp, spec, 1, false, false, tw, st);
+  fft_cols<T>(n, nhp * ncomp, spec, 1, false, true, tw, st);
 }
 
 template <typename T>
 void fft_inverse(int n, int nhp, cplx<T>* spec, int nout, T* const* outp, double out_scale, const cplx<T>* tw,
                  hipStream_t st) {
-  fft_cols<T>(n, nhp, spec, nout, true, true, tw, st);
-  fft_cols<T>(n, nhp, spec, nout, true, false, tw, st);
+  fft_cols<T>(n, nhp * nout, spec, 1, true, true, tw, st);
+  fft_cols<T>(n, nhp * nout, spec, 1, true, false, tw, st);
   fft_c2r_x<T>(n, nhp, spec, nout, outp, out_scale, tw, st);
 }
 

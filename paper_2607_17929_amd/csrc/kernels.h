@@ -28,10 +28,15 @@ struct SrcArgsH {
 };
 
 // ---- fft.hip ----
+// Half spectra of several components are component-interleaved: [z][y][kx][c], rows of nhp kx.
+// pass X forward with source assembly: spec gets mode_nsrc(mode) interleaved components
 template <typename T>
 void fft_r2c_x(const SrcArgsH<T>& a, int mode, int n, int nhp, cplx<T>* spec, const cplx<T>* tw, hipStream_t st);
+// column passes over ncomp separate arrays of rows of nhp complex values (an interleaved spectrum
+// of c components is one array with rows of c * nhp values)
 template <typename T>
 void fft_cols(int n, int nhp, cplx<T>* spec, int ncomp, bool inv, bool along_z, const cplx<T>* tw, hipStream_t st);
+// pass X inverse of nout interleaved components into separate real arrays
 template <typename T>
 void fft_c2r_x(int n, int nhp, const cplx<T>* spec, int nout, T* const* outp, double out_scale, const cplx<T>* tw,
                hipStream_t st);
@@ -43,33 +48,47 @@ void fft_inverse(int n, int nhp, cplx<T>* spec, int nout, T* const* outp, double
                  hipStream_t st);
 
 // ---- solve.hip ----
+// solution components of a solve: phi | phi, chi | phi, chi, B_x, B_y, B_z
+__host__ __device__ constexpr int mode_nout(int mode) {
+  return (mode == MODE_FULL || mode == MODE_FULLP) ? 5 : (mode == MODE_SCALAR ? 2 : 1);
+}
+// record index of mode (kx, ky, kz) in the per-mode state arrays (tensor and parabolic B):
+// [ky][kx][kz], so that the modes of one ky and a few kx (one workgroup of the Fourier-space
+// kernel) are one contiguous block
+__host__ __device__ inline long state_index(int n, int nhp, int kx, int ky, int kz) {
+  return ((long)ky * nhp + kx) * n + kz;
+}
+
 template <typename T>
 struct SolveArgs {
-  cplx<T>* spec;      // [comp][z][y][kx] sources in, solutions out
-  long comp_stride;   // complex values per component
+  const cplx<T>* spec;  // [z][y][kx][NS] sources after passes X and Y (component-interleaved)
+  cplx<T>* out;         // [z][y][kx][NOUT] solutions (phi, chi, B) before the inverse passes Y and X
   int n, nhp;
-  int mode;           // MODE_NEWTONIAN / MODE_SCALAR / MODE_FULL
-  const T* kt;        // kt[m] = 2 n sin(pi m_signed / n), m = 0 .. n-1
+  int mode;             // MODE_NEWTONIAN / MODE_SCALAR / MODE_FULL / MODE_FULLP
+  const T* kt;          // kt[m] = 2 n sin(pi m_signed / n), m = 0 .. n-1
+  const cplx<T>* tw;    // exp(-2 pi i j / n), j = 0 .. n-1
   double hc, inv_dt, ebar, inv_n3;
   // FP64 homogeneous mode of the phi source: dc[0] = mesh sum of every term but E - ebar,
   // dc[2] = sum over particles of e; k = 0 source = dc[0] + kap_a2 dc[2] - n3 ebar
   const double* dc;
   double kap_a2, n3_ebar;
   double* phibar_out; // FP64 mean of the new phi (may be null)
-  // tensor state: polarisation amplitudes and their time derivatives
-  cplx<T>* hp; cplx<T>* hx; cplx<T>* pp; cplx<T>* px;
+  // tensor state: records (h+, hx, pi+, pix) of the polarisation amplitudes and their
+  // time derivatives at state_index
+  cplx<T>* hst;
   int tensor_op;      // 0: none, 1: reset to zero, 2: Crank-Nicolson step
   double dtau, hc_half;
-  // parabolic B state a^2 B(k) (3 half spectra, unnormalised like the sources)
-  cplx<T>* a2b[3];
+  // parabolic B state: records a^2 (B_x, B_y, B_z)(k) at state_index (unnormalised like the sources)
+  cplx<T>* a2b;
   int b_op;           // MODE_FULL: 1 = also store a^2 B of the elliptic solution; MODE_FULLP: step
   double a2_now, a2_mid;
 };
+// z transform + solves + inverse z transform (one fused kernel)
 template <typename T> void launch_solve(const SolveArgs<T>& a, hipStream_t st);
-// rebuild the six h_ij half spectra from the polarisation state (diagnostic)
+// rebuild the six h_ij half spectra [q][z][y][kx] (stride comp_stride) from the tensor state (diagnostic)
 template <typename T>
-void launch_tensor_components(cplx<T>* spec, long comp_stride, int n, int nhp, const T* kt, const cplx<T>* hp,
-                              const cplx<T>* hx, double inv_n3, hipStream_t st);
+void launch_tensor_components(cplx<T>* spec, long comp_stride, int n, int nhp, const T* kt, const cplx<T>* hst,
+                              hipStream_t st);
 // FP64 sum of count values into out[0]; out[8 .. 8 + 512) is used as scratch
 void launch_sum_f64(const double* in, long count, double* out, hipStream_t st);
 void launch_sum_as_f64(const float* in, long count, double* out, hipStream_t st);

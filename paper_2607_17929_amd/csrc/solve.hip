@@ -11,6 +11,9 @@
 // The k = 0 mode of phi uses the FP64 sum of its source (the homogeneous mode
 // evolves, Sec. 3.1); chi, B and h have no k = 0 mode.  Solutions are scaled by
 // 1/n^3 so that the unnormalised inverse FFT returns real-space fields.
+#include <type_traits>
+
+#include "fft_lds.h"
 #include "kernels.h"
 
 namespace gpm {
@@ -41,36 +44,59 @@ __device__ __forceinline__ void cn_step(cplx<T>& h, cplx<T>& p, cplx<T> s, T k2,
   p = pn;
 }
 
+// Per-mode state held in registers by the Fourier-space kernel: the tensor record (h+, hx, pi+,
+// pix) and the parabolic record a^2 (B_x, B_y, B_z), loaded before the forward transform so that
+// their latency hides behind it.
+template <typename T>
+struct ModeState {
+  cplx<T> h[4];
+  cplx<T> b[3];
+};
+
 template <typename T, int MODE>
-__global__ __launch_bounds__(256) void solve_kernel(SolveArgs<T> a) {
-  const int n = a.n, nh = n / 2 + 1;
-  const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  const long total = (long)n * n * nh;
-  if (t >= total) return;
-  const int kx = (int)(t % nh);
-  const long r = t / nh;
-  const int ky = (int)(r % n), kz = (int)(r / n);
-  const long idx = ((long)kz * n + ky) * a.nhp + kx;
+__device__ __forceinline__ bool mode_has_state(const SolveArgs<T>& a, int kx) {
+  return (MODE == MODE_FULL || MODE == MODE_FULLP) && kx <= a.n / 2;
+}
+
+template <typename T, int MODE>
+__device__ __forceinline__ void load_state(const SolveArgs<T>& a, int kx, int ky, int kz, ModeState<T>& m) {
+  if (!mode_has_state<T, MODE>(a, kx)) return;
+  const long sidx = state_index(a.n, a.nhp, kx, ky, kz);
+  if (a.tensor_op == 2) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) m.h[q] = a.hst[sidx * 4 + q];
+  }
+  if (MODE == MODE_FULLP) {
+#pragma unroll
+    for (int q = 0; q < 3; ++q) m.b[q] = a.a2b[sidx * 3 + q];
+  }
+}
+
+// Solution of one mode (kx, ky, kz) of the half spectrum from its NS source values; writes the
+// NOUT unnormalised solution coefficients (phi, chi, B_x, B_y, B_z) to o, advances the mode's
+// tensor and parabolic-B state in m and stores it.  kx beyond n/2 (row padding) gives zeros and
+// touches no state.
+template <typename T, int MODE>
+__device__ __forceinline__ void solve_mode(const SolveArgs<T>& a, int kx, int ky, int kz, const cplx<T>* src,
+                                           cplx<T>* o, ModeState<T>& ms) {
+  const int n = a.n, nh2 = n / 2;
+  constexpr int NO = mode_nout(MODE);
+  if (kx > nh2) {
+#pragma unroll
+    for (int c = 0; c < NO; ++c) o[c] = mk<T>(0, 0);
+    return;
+  }
   const T k[3] = {a.kt[kx], a.kt[ky], a.kt[kz]};
   const T k2 = k[0] * k[0] + k[1] * k[1] + k[2] * k[2];
   const T s = (T)a.inv_n3;
-  cplx<T>* sp = a.spec;
-  const long cs = a.comp_stride;
   const bool zero = (kx == 0 && ky == 0 && kz == 0);
   // chi, B and h have no Nyquist-plane modes: their projectors hold factors odd in
   // one component (kt_x kt_y, ...), whose sign is undefined where k_d = -k_d.
-  const int nh2 = n / 2;
   const bool nyq = (kx == nh2 || ky == nh2 || kz == nh2);
-
   if constexpr (MODE == MODE_NEWTONIAN) {
-    const cplx<T> src = sp[idx];
-    sp[idx] = zero ? mk<T>(0, 0) : scale(src, -s / k2);
+    o[0] = zero ? mk<T>(0, 0) : scale(src[0], -s / k2);
     return;
   } else {
-    cplx<T> src[10];
-    constexpr int NS = mode_nsrc(MODE);
-#pragma unroll
-    for (int c = 0; c < NS; ++c) src[c] = sp[c * cs + idx];
     // phi
     const T den = -k2 - (T)(3.0 * a.hc * a.inv_dt + 6.0 * a.hc * a.hc + a.ebar);
     cplx<T> phi = scale(src[0], s / den);
@@ -97,9 +123,10 @@ __global__ __launch_bounds__(256) void solve_kernel(SolveArgs<T> a) {
       const T f = -(T)0.75 / (k2 * k2) * s;
       chi = mk(f * (contr.x - k2 * tr.x / (T)3), f * (contr.y - k2 * tr.y / (T)3));
     }
-    sp[idx] = phi;
-    sp[cs + idx] = chi;
+    o[0] = phi;
+    o[1] = chi;
     if constexpr (MODE == MODE_FULL || MODE == MODE_FULLP) {
+      const long sidx = state_index(n, a.nhp, kx, ky, kz);
       cplx<T> B[3] = {mk<T>(0, 0), mk<T>(0, 0), mk<T>(0, 0)};
       if constexpr (MODE == MODE_FULL) {
         // B: transverse projection of the momentum source (Eq. 6)
@@ -119,7 +146,7 @@ __global__ __launch_bounds__(256) void solve_kernel(SolveArgs<T> a) {
           // start of the parabolic route: a^2 B from the momentum constraint
           const T a2 = (T)a.a2_now;
 #pragma unroll
-          for (int i = 0; i < 3; ++i) a.a2b[i][idx] = scale(Bu[i], a2);
+          for (int i = 0; i < 3; ++i) a.a2b[sidx * 3 + i] = scale(Bu[i], a2);
         }
       } else {
         // B from the vector part of Eq. 5: d_tau (a^2 B_j) = -i a^2 w_j / |kt|,
@@ -139,21 +166,23 @@ __global__ __launch_bounds__(256) void solve_kernel(SolveArgs<T> a) {
 #pragma unroll
           for (int j = 0; j < 3; ++j) {
             const cplx<T> w = mk(v[j].x - kh[j] * kv.x, v[j].y - kh[j] * kv.y);
-            const cplx<T> old = a.a2b[j][idx];
+            const cplx<T> old = ms.b[j];
             st[j] = mk(old.x + f * w.y, old.y - f * w.x);  // -i w = (w.y, -w.x)
             B[j] = scale(st[j], out_scale);
           }
         }
 #pragma unroll
-        for (int j = 0; j < 3; ++j) a.a2b[j][idx] = st[j];
+        for (int j = 0; j < 3; ++j) a.a2b[sidx * 3 + j] = st[j];
       }
 #pragma unroll
-      for (int i = 0; i < 3; ++i) sp[(2 + i) * cs + idx] = B[i];
-      // h: two polarisation amplitudes
+      for (int i = 0; i < 3; ++i) o[2 + i] = B[i];
+      // h: two polarisation amplitudes, state record (h+, hx, pi+, pix)
+      cplx<T>* hs = a.hst + sidx * 4;
       if (a.tensor_op == 1 || (a.tensor_op == 2 && nyq)) {
-        a.hp[idx] = mk<T>(0, 0); a.hx[idx] = mk<T>(0, 0);
-        a.pp[idx] = mk<T>(0, 0); a.px[idx] = mk<T>(0, 0);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) hs[q] = mk<T>(0, 0);
       } else if (a.tensor_op == 2 && !zero) {
+        cplx<T>* hr = ms.h;
         T e1[3], e2[3];
         polarisation_basis(k[0], k[1], k[2], k2, e1, e2);
         // s_plus = (e1 Sigma e1 - e2 Sigma e2) / 2, s_cross = e1 Sigma e2
@@ -167,33 +196,144 @@ __global__ __launch_bounds__(256) void solve_kernel(SolveArgs<T> a) {
           spl = mk(spl.x + cpl * sg[q].x, spl.y + cpl * sg[q].y);
           scr = mk(scr.x + ccr * sg[q].x, scr.y + ccr * sg[q].y);
         }
-        cplx<T> hp = a.hp[idx], pp = a.pp[idx], hx = a.hx[idx], px = a.px[idx];
+        cplx<T> hp = hr[0], hx = hr[1], pp = hr[2], px = hr[3];
         cn_step(hp, pp, spl, k2, (T)a.dtau, (T)a.hc_half);
         cn_step(hx, px, scr, k2, (T)a.dtau, (T)a.hc_half);
-        a.hp[idx] = hp; a.pp[idx] = pp; a.hx[idx] = hx; a.px[idx] = px;
+        hs[0] = hp; hs[1] = hx; hs[2] = pp; hs[3] = px;
       }
     }
   }
 }
 
-template <typename T>
-void launch_solve(const SolveArgs<T>& a, hipStream_t st) {
-  const long total = (long)a.n * a.n * (a.n / 2 + 1);
-  dim3 grid((unsigned)((total + 255) / 256));
-  if (a.mode == MODE_NEWTONIAN)
-    hipLaunchKernelGGL((solve_kernel<T, MODE_NEWTONIAN>), grid, dim3(256), 0, st, a);
-  else if (a.mode == MODE_SCALAR)
-    hipLaunchKernelGGL((solve_kernel<T, MODE_SCALAR>), grid, dim3(256), 0, st, a);
-  else if (a.mode == MODE_FULLP)
-    hipLaunchKernelGGL((solve_kernel<T, MODE_FULLP>), grid, dim3(256), 0, st, a);
-  else
-    hipLaunchKernelGGL((solve_kernel<T, MODE_FULL>), grid, dim3(256), 0, st, a);
+// Fourier-space stage of the solve, fused: for one ky and KXT consecutive kx, the NS source
+// columns along z (component-interleaved, so a row of the tile is KXT * NS contiguous complex
+// values) are transformed along z in LDS, every mode is solved, and the NOUT solution columns
+// are transformed back along z and written to the output spectrum.  Each value of the source
+// and output spectra crosses HBM once.
+// grid: x = kx tile, y = ky.
+#ifndef GPM_KSPACE_TWPOW
+#define GPM_KSPACE_TWPOW 1     // twiddle powers by products (the table may live in global memory)
+#endif
+constexpr bool KS_TWPOW = GPM_KSPACE_TWPOW != 0;
+
+template <typename T, int N, int MODE, int KXT, int NT, bool TW_LDS>
+__global__ __launch_bounds__(NT) void kspace_kernel(SolveArgs<T> a) {
+  constexpr int NS = mode_nsrc(MODE), NO = mode_nout(MODE);
+  constexpr int CI = KXT * NS, CO = KXT * NO;
+  static_assert(nstages(N) >= 2, "the first stage's barrier publishes the twiddle table");
+  using IX = typename std::conditional<((long)N * N * (N / 2 + 16) * NS < (1L << 31)), uint32_t, uint64_t>::type;
+  __shared__ cplx<T> sm[N * CI];
+  __shared__ cplx<T> stw_s[TW_LDS ? N : 1];
+  const cplx<T>* stw = a.tw;
+  if constexpr (TW_LDS) {
+    for (int j = threadIdx.x; j < N; j += NT) stw_s[j] = a.tw[j];
+    stw = stw_s;
+  }
+  const int ky = blockIdx.y, kx0 = blockIdx.x * KXT;
+  const cplx<T>* gin = a.spec + ((long)ky * a.nhp + kx0) * NS;
+  cplx<T>* gout = a.out + ((long)ky * a.nhp + kx0) * NO;
+  constexpr int MODES = N * KXT;
+  constexpr int PM = (MODES + NT - 1) / NT;
+  // this thread's modes: kxl fastest; their state records are requested first
+  ModeState<T> ms[PM];
+#pragma unroll
+  for (int p = 0; p < PM; ++p) {
+    const int m = threadIdx.x + p * NT;
+    if (MODES % NT == 0 || m < MODES) load_state<T, MODE>(a, kx0 + m % KXT, ky, m / KXT, ms[p]);
+  }
+  // forward transform along z: global -> LDS
+  col_stages<T, N, CI, NT, 0, false, true, false, IX, KS_TWPOW>(sm, gin, (IX)N * a.nhp * NS, nullptr, (IX)0, stw);
+  // solves: the sources of this thread's modes to registers, barrier, solutions to LDS as CO columns
+  cplx<T> src[PM][NS];
+#pragma unroll
+  for (int p = 0; p < PM; ++p) {
+    const int m = threadIdx.x + p * NT;
+    if (MODES % NT == 0 || m < MODES) {
+      const int kxl = m % KXT, kz = m / KXT;
+#pragma unroll
+      for (int c = 0; c < NS; ++c) src[p][c] = sm[kz * CI + kxl * NS + c];
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int p = 0; p < PM; ++p) {
+    const int m = threadIdx.x + p * NT;
+    if (MODES % NT == 0 || m < MODES) {
+      const int kxl = m % KXT, kz = m / KXT;
+      cplx<T> o[NO];
+      solve_mode<T, MODE>(a, kx0 + kxl, ky, kz, src[p], o, ms[p]);
+#pragma unroll
+      for (int c = 0; c < NO; ++c) sm[kz * CO + kxl * NO + c] = o[c];
+    }
+  }
+  __syncthreads();
+  // inverse transform along z: LDS -> global
+  col_stages<T, N, CO, NT, 0, true, false, true, IX, KS_TWPOW>(sm, nullptr, (IX)0, gout, (IX)N * a.nhp * NO, stw);
 }
 
-// h_ij(k) = h_plus e+_ij + h_cross ex_ij with e+ = e1 e1 - e2 e2, ex = e1 e2 + e2 e1
+// Tile shape (measured at 512^3, FP32 full physics: rows of 4 kx x 10 components = 320 B in a
+// 160 KB tile, one workgroup per CU, run faster than 160 B rows with two workgroups per CU)
+#ifndef GPM_KSPACE_BYTES
+#define GPM_KSPACE_BYTES 256   // contiguous bytes wanted per row of a tile
+#endif
+#ifndef GPM_KSPACE_LDS
+#define GPM_KSPACE_LDS 163840  // LDS budget of a tile
+#endif
+#ifndef GPM_KSPACE_NT
+#define GPM_KSPACE_NT 512
+#endif
+// kx values per workgroup: KXT * NS * sizeof(complex) >= GPM_KSPACE_BYTES contiguous bytes where the
+// LDS tile allows
+template <typename T, int N, int NS> constexpr int kspace_kxt() {
+  constexpr int want = (GPM_KSPACE_BYTES + NS * (int)sizeof(cplx<T>) - 1) / (NS * (int)sizeof(cplx<T>));
+  int k = 1;
+  while (k < want) k *= 2;
+  while (k > 1 && (long)N * k * NS * (long)sizeof(cplx<T>) > GPM_KSPACE_LDS) k /= 2;
+  return k;
+}
+
+template <typename T, int N, int MODE>
+static void launch_kspace_n(const SolveArgs<T>& a, hipStream_t st) {
+  constexpr int NS = mode_nsrc(MODE);
+  constexpr int KXT = kspace_kxt<T, N, NS>();
+  constexpr int NT = N * KXT >= GPM_KSPACE_NT ? GPM_KSPACE_NT : (N * KXT >= 256 ? 256 : 64);
+  constexpr bool TW_LDS =
+      (long)N * KXT * NS * (long)sizeof(cplx<T>) + N * (long)sizeof(cplx<T>) <= GPM_KSPACE_LDS;
+  static_assert((long)N * KXT * NS * (long)sizeof(cplx<T>) + (TW_LDS ? N : 0) * (long)sizeof(cplx<T>) <= 160 * 1024,
+                "LDS tile too large");
+  const int nh = N / 2 + 1;
+  dim3 grid((unsigned)((nh + KXT - 1) / KXT), N);
+  hipLaunchKernelGGL((kspace_kernel<T, N, MODE, KXT, NT, TW_LDS>), grid, dim3(NT), 0, st, a);
+}
+
+template <typename T, int N>
+static void launch_kspace_modes(const SolveArgs<T>& a, hipStream_t st) {
+  switch (a.mode) {
+    case MODE_NEWTONIAN: launch_kspace_n<T, N, MODE_NEWTONIAN>(a, st); break;
+    case MODE_SCALAR: launch_kspace_n<T, N, MODE_SCALAR>(a, st); break;
+    case MODE_FULLP: launch_kspace_n<T, N, MODE_FULLP>(a, st); break;
+    default: launch_kspace_n<T, N, MODE_FULL>(a, st); break;
+  }
+}
+
+template <typename T>
+void launch_solve(const SolveArgs<T>& a, hipStream_t st) {
+  switch (a.n) {
+    case 16: launch_kspace_modes<T, 16>(a, st); break;
+    case 32: launch_kspace_modes<T, 32>(a, st); break;
+    case 64: launch_kspace_modes<T, 64>(a, st); break;
+    case 128: launch_kspace_modes<T, 128>(a, st); break;
+    case 256: launch_kspace_modes<T, 256>(a, st); break;
+    case 512: launch_kspace_modes<T, 512>(a, st); break;
+    default: launch_kspace_modes<T, 1024>(a, st); break;
+  }
+}
+
+// h_ij(k) = h_plus e+_ij + h_cross ex_ij with e+ = e1 e1 - e2 e2, ex = e1 e2 + e2 e1, written as
+// six separate half spectra [q][z][y][kx] (stride cs) for the inverse transform
 template <typename T>
 __global__ __launch_bounds__(256) void tensor_components_kernel(cplx<T>* spec, long cs, int n, int nhp, const T* kt,
-                                                               const cplx<T>* hp, const cplx<T>* hx) {
+                                                               const cplx<T>* hst) {
   const int nh = n / 2 + 1;
   const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= (long)n * n * nh) return;
@@ -210,7 +350,8 @@ __global__ __launch_bounds__(256) void tensor_components_kernel(cplx<T>* spec, l
   }
   T e1[3], e2[3];
   polarisation_basis(k[0], k[1], k[2], k2, e1, e2);
-  const cplx<T> a = hp[idx], b = hx[idx];
+  const long sidx = state_index(n, nhp, kx, ky, kz);
+  const cplx<T> a = hst[sidx * 4 + 0], b = hst[sidx * 4 + 1];
   for (int q = 0; q < 6; ++q) {
     const int i = si[q], j = sj[q];
     const T ep = e1[i] * e1[j] - e2[i] * e2[j];
@@ -220,11 +361,11 @@ __global__ __launch_bounds__(256) void tensor_components_kernel(cplx<T>* spec, l
 }
 
 template <typename T>
-void launch_tensor_components(cplx<T>* spec, long comp_stride, int n, int nhp, const T* kt, const cplx<T>* hp,
-                              const cplx<T>* hx, double, hipStream_t st) {
+void launch_tensor_components(cplx<T>* spec, long comp_stride, int n, int nhp, const T* kt, const cplx<T>* hst,
+                              hipStream_t st) {
   const long total = (long)n * n * (n / 2 + 1);
   hipLaunchKernelGGL((tensor_components_kernel<T>), dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, spec,
-                     comp_stride, n, nhp, kt, hp, hx);
+                     comp_stride, n, nhp, kt, hst);
 }
 
 // deterministic FP64 sum (input values widened to FP64): a fixed number of
@@ -272,8 +413,8 @@ void launch_sum_as_f64(const float* in, long count, double* out, hipStream_t st)
 template void launch_solve<float>(const SolveArgs<float>&, hipStream_t);
 template void launch_solve<double>(const SolveArgs<double>&, hipStream_t);
 template void launch_tensor_components<float>(cplx<float>*, long, int, int, const float*, const cplx<float>*,
-                                              const cplx<float>*, double, hipStream_t);
+                                              hipStream_t);
 template void launch_tensor_components<double>(cplx<double>*, long, int, int, const double*, const cplx<double>*,
-                                               const cplx<double>*, double, hipStream_t);
+                                               hipStream_t);
 
 }  // namespace gpm

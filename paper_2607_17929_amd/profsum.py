@@ -29,21 +29,21 @@ CSRC = os.path.join(os.path.dirname(os.path.abspath(__file__)), "csrc")
 STAGE_KERNELS = {
     "deposit": [(r"deposit_kernel<{T}, 10", 1)],
     "fft_x_fwd": [(r"fft_x_r2c_kernel<{T}", 1)],
-    "fft_yz_fwd": [(r"fft_cols_kernel<{T}, \d+, \d+, \d+, false>", 2)],
-    "ksolve": [(r"solve_kernel<{T}", 1)],
-    "fft_zy_inv": [(r"fft_cols_kernel<{T}, \d+, \d+, \d+, true>", 2)],
+    "fft_y_fwd": [(r"fft_cols_kernel<{T}, \d+, \d+, \d+, false>", 1)],
+    "kspace": [(r"kspace_kernel<{T}", 1)],
+    "fft_y_inv": [(r"fft_cols_kernel<{T}, \d+, \d+, \d+, true>", 1)],
     "fft_x_inv": [(r"fft_x_c2r_kernel<{T}", 1)],
     "kick_drift": [(r"kick_drift_kernel<{T}", 1)],
     "sort": [(r"scan_reduce_kernel", 1), (r"scan_blocks_kernel", 1), (r"scan_apply_kernel", 1),
              (r"scatter_kernel<{T}", 1)],
 }
 # stages whose kernels run as separate launches (the bench reports per-launch figures for them)
-LAUNCHES = {"fft_yz_fwd": 2, "fft_zy_inv": 2}
+LAUNCHES: dict = {}
 # source files each stage's kernels are built from
 STAGE_SOURCES = {
     "deposit": ["particles.hip"], "kick_drift": ["particles.hip"], "sort": ["particles.hip"],
-    "fft_x_fwd": ["fft.hip"], "fft_yz_fwd": ["fft.hip"], "fft_zy_inv": ["fft.hip"], "fft_x_inv": ["fft.hip"],
-    "ksolve": ["solve.hip"],
+    "fft_x_fwd": ["fft.hip"], "fft_y_fwd": ["fft.hip", "fft_lds.h"], "fft_y_inv": ["fft.hip", "fft_lds.h"],
+    "fft_x_inv": ["fft.hip"], "kspace": ["solve.hip", "fft_lds.h"],
 }
 COMMON_SOURCES = ["common.h", "kernels.h"]
 
