@@ -40,64 +40,6 @@ __global__ __launch_bounds__(NT) void fft_cols_kernel(cplx<T>* data, uint32_t es
   col_stages<T, N, C, NT, 0, INV, true, true, uint32_t>(sm, g, es, g, es, stw);
 }
 
-// LDS line stride (complex values) of pass X: M + 7 makes the line stride 14 words modulo the 64
-// banks (FP32; 28 for FP64), so that a wave reading one k of up to ten component lines, and the
-// next k's, spreads over the banks
-__host__ __device__ constexpr int x_line_stride(int m) { return m + 7; }
-
-// ---------------------------------------------------------------------------
-// Row FFTs in LDS (pass X): L lines of M complex values, line stride LS.
-// Job j -> line j / (M/R), butterfly j % (M/R).
-// ---------------------------------------------------------------------------
-template <typename T, int M, int L, int LS, int NT, int S, bool INV>
-__device__ __forceinline__ void row_stage(cplx<T>* sm, const cplx<T>* __restrict__ tw, int twstep) {
-  constexpr int R = stage_radix(M, S);
-  constexpr int NS = stage_ns(M, S);
-  constexpr int B = M / R;
-  constexpr int J = L * B;
-  constexpr int PER = (J + NT - 1) / NT;
-  const int tid = threadIdx.x;
-  cplx<T> v[PER][R];
-#pragma unroll
-  for (int p = 0; p < PER; ++p) {
-    const int job = tid + p * NT;
-    if (J % NT == 0 || job < J) {
-      const int line = job / B, i = job % B;
-#pragma unroll
-      for (int r = 0; r < R; ++r) v[p][r] = sm[line * LS + i + r * B];
-    }
-  }
-  __syncthreads();
-#pragma unroll
-  for (int p = 0; p < PER; ++p) {
-    const int job = tid + p * NT;
-    if (J % NT == 0 || job < J) {
-      const int line = job / B, i = job % B;
-      const int k = i % NS;
-      if (NS > 1) {
-#pragma unroll
-        for (int r = 1; r < R; ++r) {
-          const cplx<T> w = tw[(r * k) * (M / (NS * R)) * twstep];
-          v[p][r] = INV ? cmulc(v[p][r], w) : cmul(v[p][r], w);
-        }
-      }
-      dftR<T, R, INV>(v[p]);
-      const int j0 = (i / NS) * NS * R + k;
-#pragma unroll
-      for (int r = 0; r < R; ++r) sm[line * LS + j0 + r * NS] = v[p][r];
-    }
-  }
-  __syncthreads();
-}
-
-template <typename T, int M, int L, int LS, int NT, int S, bool INV>
-__device__ __forceinline__ void row_stages(cplx<T>* sm, const cplx<T>* tw, int twstep) {
-  if constexpr (S < nstages(M)) {
-    row_stage<T, M, L, LS, NT, S, INV>(sm, tw, twstep);
-    row_stages<T, M, L, LS, NT, S + 1, INV>(sm, tw, twstep);
-  }
-}
-
 // ---------------------------------------------------------------------------
 // Source assembly (the paper's per-site mesh kernel, Sec. 2.2), fused into pass X.
 // ---------------------------------------------------------------------------
@@ -193,27 +135,34 @@ __device__ __forceinline__ T assemble_point(const SrcArgs<T>& a, int n, int x, i
 
 // ---------------------------------------------------------------------------
 // Pass X forward: assembly + R2C.  grid: x = y-chunk (RY rows), y = z plane.
+// The L = NSRC * RY lines (line = c * RY + r) sit in LDS as [element][line], so that
+// the half-length transforms are the column stages of fft_lds.h over L columns
+// (consecutive lanes touch consecutive words in every stage) and the post-processing,
+// component fastest, reads consecutive words too.
 // ---------------------------------------------------------------------------
 template <typename T, int N, int MODE, int RY, int NT>
 __global__ __launch_bounds__(NT) void fft_x_r2c_kernel(SrcArgs<T> a, cplx<T>* spec, int nhp,
                                                        const cplx<T>* __restrict__ tw) {
   constexpr int M = N / 2;
-  constexpr int LS = x_line_stride(M);
   constexpr int NSRC = mode_nsrc(MODE);
   constexpr int L = NSRC * RY;
-  __shared__ T sm[L * 2 * LS];
-  __shared__ cplx<T> stw[N];
+  __shared__ cplx<T> cs[M * L];
+  __shared__ cplx<T> stw[N];   // W_N^j for the post-processing
+  __shared__ cplx<T> stwm[M];  // W_M^j = W_N^(2j) for the half-length transforms
   __shared__ double red[RY][NT / 64];
   const int y0 = blockIdx.x * RY, z = blockIdx.y;
   const int tid = threadIdx.x;
   for (int j = tid; j < N; j += NT) stw[j] = tw[j];
-  // 1. assemble the sources of RY rows into LDS lines [c][r] of LS complex values
+  for (int j = tid; j < M; j += NT) stwm[j] = tw[2 * j];
+  // 1. assemble the sources of RY rows: real x of line (c, r) is element x / 2, real (x even) or
+  //    imaginary (x odd) part
+  T* smr = reinterpret_cast<T*>(cs);
   double acc[RY];
 #pragma unroll
   for (int r = 0; r < RY; ++r) acc[r] = 0.0;
   for (int p = tid; p < RY * N; p += NT) {
     const int r = p / N, x = p % N;
-    const T s0 = assemble_point<T, MODE>(a, N, x, y0 + r, z, sm + r * 2 * LS + x, RY * 2 * LS);
+    const T s0 = assemble_point<T, MODE>(a, N, x, y0 + r, z, smr + ((x >> 1) * L + r) * 2 + (x & 1), 2 * RY);
 #pragma unroll
     for (int rr = 0; rr < RY; ++rr)
       if (rr == r) acc[rr] += (double)s0;
@@ -236,17 +185,16 @@ __global__ __launch_bounds__(NT) void fft_x_r2c_kernel(SrcArgs<T> a, cplx<T>* sp
   } else {
     __syncthreads();
   }
-  // 2. half-length complex FFT of every row (pairs of reals are complex values)
-  cplx<T>* cs = reinterpret_cast<cplx<T>*>(sm);
-  row_stages<T, M, L, LS, NT, 0, false>(cs, stw, 2);
+  // 2. half-length complex FFT of every line (pairs of reals are complex values)
+  col_stages<T, M, L, NT, 0, false, false, false, uint32_t>(cs, nullptr, 0u, nullptr, 0u, stwm);
   // 3. post-process Z_k -> X_k (k = 0..M) and store the rows, component fastest: the
   //    spectrum is component-interleaved, so the stores of a row are contiguous
   for (int job = tid; job < L * (M + 1); job += NT) {
     const int c = job % NSRC, rk = job / NSRC;
     const int k = rk % (M + 1), r = rk / (M + 1);
     const int line = c * RY + r;
-    const cplx<T> zk = cs[line * LS + (k == M ? 0 : k)];
-    const cplx<T> zc = conj(cs[line * LS + (k == 0 ? 0 : M - k)]);
+    const cplx<T> zk = cs[(k == M ? 0 : k) * L + line];
+    const cplx<T> zc = conj(cs[(k == 0 ? 0 : M - k) * L + line]);
     const cplx<T> ev = scale(zk + zc, (T)0.5);
     const cplx<T> od = scale(zk - zc, (T)0.5);  // = i * O_k
     // X_k = E_k + W^k O_k with O_k = -i * od
@@ -259,7 +207,8 @@ __global__ __launch_bounds__(NT) void fft_x_r2c_kernel(SrcArgs<T> a, cplx<T>* sp
 }
 
 // ---------------------------------------------------------------------------
-// Pass X inverse: C2R of NOUT components into separate real arrays.
+// Pass X inverse: C2R of NOUT components into separate real arrays; the lines sit in
+// LDS as [element][line] like the forward pass.
 // ---------------------------------------------------------------------------
 template <typename T>
 struct OutPtrs {
@@ -270,15 +219,15 @@ template <typename T, int N, int NOUT, int RY, int NT>
 __global__ __launch_bounds__(NT) void fft_x_c2r_kernel(const cplx<T>* spec, int nhp, OutPtrs<T> out, T out_scale,
                                                        const cplx<T>* __restrict__ tw) {
   constexpr int M = N / 2;
-  constexpr int LS = x_line_stride(M);
   constexpr int L = NOUT * RY;
-  __shared__ cplx<T> cs[L * LS];
+  __shared__ cplx<T> cs[M * L];
   __shared__ cplx<T> stw[N];
+  __shared__ cplx<T> stwm[M];
   const int y0 = blockIdx.x * RY, z = blockIdx.y;
   const int tid = threadIdx.x;
   // 1. pre-process X_k -> Z_k = E_k + i O_k, E_k = X_k + conj X_{M-k}, O_k = (X_k - conj X_{M-k}) W^-k;
   //    the spectrum (component-interleaved) is read component fastest, so that the loads of a row
-  //    are contiguous; the reads are issued first, the twiddle table is staged while they are in flight
+  //    are contiguous; the reads are issued first, the twiddle tables are staged while they are in flight
   constexpr int PJ = (L * M + NT - 1) / NT;
   cplx<T> xk[PJ], xm[PJ];
 #pragma unroll
@@ -293,6 +242,7 @@ __global__ __launch_bounds__(NT) void fft_x_c2r_kernel(const cplx<T>* spec, int 
     }
   }
   for (int j = tid; j < N; j += NT) stw[j] = tw[j];
+  for (int j = tid; j < M; j += NT) stwm[j] = tw[2 * j];
   __syncthreads();
 #pragma unroll
   for (int q = 0; q < PJ; ++q) {
@@ -309,17 +259,17 @@ __global__ __launch_bounds__(NT) void fft_x_c2r_kernel(const cplx<T>* spec, int 
       const cplx<T> bc = conj(b);
       const cplx<T> ev = a + bc;
       const cplx<T> od = cmulc(a - bc, stw[k]);
-      cs[line * LS + k] = mk(ev.x - od.y, ev.y + od.x);
+      cs[k * L + line] = mk(ev.x - od.y, ev.y + od.x);
     }
   }
   __syncthreads();
-  row_stages<T, M, L, LS, NT, 0, true>(cs, stw, 2);
-  // 2. z_n = x_{2n} + i x_{2n+1}: the LDS row is the real output row
+  col_stages<T, M, L, NT, 0, true, false, false, uint32_t>(cs, nullptr, 0u, nullptr, 0u, stwm);
+  // 2. z_n = x_{2n} + i x_{2n+1}: real x of line (c, r) is element x / 2
   const T* rs = reinterpret_cast<const T*>(cs);
   for (int job = tid; job < L * N; job += NT) {
     const int line = job / N, x = job % N;
     const int c = line / RY, r = line % RY;
-    out.p[c][((long)z * N + (y0 + r)) * N + x] = rs[line * 2 * LS + x] * out_scale;
+    out.p[c][((long)z * N + (y0 + r)) * N + x] = rs[((x >> 1) * L + line) * 2 + (x & 1)] * out_scale;
   }
 }
 
