@@ -132,6 +132,25 @@ def run_gpu(args):
         del src, dst
         torch.cuda.empty_cache()
 
+    # achievable streaming ceiling on this device: the runtime's device-to-device copy kernel
+    nb = 2 ** 31 // 4
+    src = torch.ones(nb, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    c0 = torch.cuda.Event(enable_timing=True)
+    c1 = torch.cuda.Event(enable_timing=True)
+    c0.record()
+    for _ in range(5):
+        dst.copy_(src)
+    c1.record()
+    torch.cuda.synchronize()
+    copy_ms = c0.elapsed_time(c1) / 5
+    copy_gbs = 2 * nb * 4 / (copy_ms * 1e-3) / 1e9
+    log(f"copy ceiling: {copy_gbs:.0f} GB/s (read + write of {nb * 4} bytes in {copy_ms:.3f} ms)")
+    del src, dst
+    torch.cuda.empty_cache()
+
     # FP32 path from the same snapshot
     pos_d, u_d = ctx64.get_particles(device=True)
     ctx32 = PMContext(n, n_p, box, physics="full", precision="fp32", timings=True)
@@ -140,7 +159,7 @@ def run_gpu(args):
     torch.cuda.synchronize()
     ms32, st32 = timed(ctx32, "fp32")
     res = {"ms32": ms32, "st32": st32, "n": n, "n_p": n_p, "box": box, "a_snap": a_s,
-           "ws32": ctx32.ws_bytes, "ws64": ctx64.ws_bytes}
+           "ws32": ctx32.ws_bytes, "ws64": ctx64.ws_bytes, "copy_gbs": copy_gbs}
     del ctx32
     torch.cuda.empty_cache()
     if not args.no_parabolic:
@@ -218,6 +237,7 @@ def main():
     achieved = nbytes[dom] / (per_launch[dom] * 1e-3) / 1e9
     roof = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(n, dom),
+            "frac_of_copy": round(achieved / r["copy_gbs"], 4),
             "algorithmic_bytes_per_launch": nbytes[dom], "ms_per_launch": round(per_launch[dom], 4)}
     stages = {k: {"ms_per_launch": round(per_launch.get(k, 0.0), 4),
                   "GBs": round(nbytes[k] / (per_launch[k] * 1e-3) / 1e9, 1) if k in per_launch else None}
@@ -242,6 +262,8 @@ def main():
                    "precision": "FP32 fields/FFT/deposit/momenta, FP64 positions and zero mode"},
         "stages_fp32": stages,
         "roofline": roof,
+        "copy_ceiling": {"GBs": round(r["copy_gbs"], 1), "kind": "device-to-device copy of 2 GiB (runtime copy kernel)",
+                         "frac_of_peak": round(r["copy_gbs"] / HBM_PEAK_GBS, 4)},
         "workspace_GB": {"fp32": round(r["ws32"] / 1e9, 2), "fp64": round(r["ws64"] / 1e9, 2)},
     }
     if "msp" in r:

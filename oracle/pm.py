@@ -12,7 +12,9 @@ design notes of the repository):
     arrays are indexed [z][y][x] with x fastest (the paper's fast index, Sec. 2);
   * Einstein-de Sitter background: a = (H0 tau / 2)^2, H_conf = 2/tau,
     4 pi G a^2 rho_bar = (3/2) H0^2 / a;
-  * equal-mass particles carrying u = q/m; 4 pi G m N_p = (3/2) H0^2;
+  * equal-mass particles carrying u = q/m; 4 pi G m N_p = (3/2) H0^2; an optional
+    second species of another particle mass carries a fraction f of the rest mass
+    (4 pi G m_2 N_2 = (3/2) H0^2 f) and enters the deposit weighted by m_2 / m_1;
   * cloud-in-cell (CIC) assignment and interpolation (Sec. 3.1, below Eq. 13);
   * 7-point Laplacian (symbol -kt^2, kt_d = 2 n sin(pi m_d / n)) and centred
     differences for gradients; projectors use kt_d;
@@ -68,9 +70,10 @@ class Background:
         """4 pi G a^2 rho_bar (Friedmann equation, EdS): (3/2) H0^2 / a."""
         return 1.5 * self.h0 ** 2 / a
 
-    def kappa(self, n: int, n_p: int) -> float:
-        """4 pi G m / dx^3 for equal masses with 4 pi G m N_p = (3/2) H0^2."""
-        return 1.5 * self.h0 ** 2 * n ** 3 / n_p
+    def kappa(self, n: int, n_p: int, mass_fraction: float = 1.0) -> float:
+        """4 pi G m / dx^3 for N_p equal masses m carrying the fraction `mass_fraction` of the total
+        rest mass, the total fixed by the Friedmann equation: 4 pi G m N_p = (3/2) H0^2 mass_fraction."""
+        return 1.5 * self.h0 ** 2 * n ** 3 * mass_fraction / n_p
 
 
 # ---------------------------------------------------------------------------
@@ -370,6 +373,11 @@ class OracleSim:
     tau: float
     ids: np.ndarray = None
     b_route: str = "elliptic"  # full physics: B from Eq. 6 ("elliptic") or from the vector part of Eq. 5
+    # optional second particle species (its own particle mass, e.g. a hot, neutrino-like set):
+    # positions, momenta per unit mass and the fraction of the total rest mass it carries
+    pos2: np.ndarray = None
+    u2: np.ndarray = None
+    mass_fraction2: float = 0.0
     bg: Background = field(init=False)
 
     def __post_init__(self):
@@ -378,6 +386,13 @@ class OracleSim:
         self.u = np.array(self.u, dtype=np.float64)
         if self.ids is None:
             self.ids = np.arange(self.pos.shape[0], dtype=np.int64)
+        if self.pos2 is not None:
+            self.pos2 = np.array(self.pos2, dtype=np.float64)
+            self.u2 = np.array(self.u2, dtype=np.float64)
+            if not 0.0 < self.mass_fraction2 < 1.0:
+                raise ValueError("a second species needs 0 < mass_fraction2 < 1")
+        elif self.mass_fraction2 != 0.0:
+            raise ValueError("mass_fraction2 without a second species")
         n = self.n
         z = np.zeros((n, n, n))
         self.dep = None
@@ -399,11 +414,31 @@ class OracleSim:
     def n_p(self) -> int:
         return self.pos.shape[0]
 
+    @property
+    def n_p2(self) -> int:
+        return 0 if self.pos2 is None else self.pos2.shape[0]
+
+    def species_weight(self) -> float:
+        """Particle mass of species 2 over that of species 1: (f / N_2) / ((1 - f) / N_1)."""
+        f = self.mass_fraction2
+        return (f / self.n_p2) / ((1.0 - f) / self.n_p)
+
+    def kappa(self) -> float:
+        """4 pi G m_1 / dx^3: species 1 carries the fraction 1 - f of the rest mass."""
+        return self.bg.kappa(self.n, self.n_p, 1.0 - self.mass_fraction2)
+
     # -- stage 1 ----------------------------------------------------------
     def deposit(self):
+        """The stress-energy sums run over the particles of every species, each weighted by its
+        mass (Sec. 3.1, the sums over particles below Eq. 10); the deposit is kept in units of the
+        species-1 particle mass: dep = dep_1 + (m_2 / m_1) dep_2."""
         a = self.bg.a(self.tau)
         rel = self.physics != NEWTONIAN
-        self.dep = deposit(self.pos, self.u, a, self.n, relativistic=rel, ncomp=10 if rel else 1)
+        nc = 10 if rel else 1
+        self.dep = deposit(self.pos, self.u, a, self.n, relativistic=rel, ncomp=nc)
+        if self.pos2 is not None:
+            self.dep = self.dep + self.species_weight() * deposit(self.pos2, self.u2, a, self.n, relativistic=rel,
+                                                                  ncomp=nc)
         return self.dep
 
     # -- stage 2 ----------------------------------------------------------
@@ -411,7 +446,7 @@ class OracleSim:
         """Mesh sources from the deposit and the lagged fields (metric factors applied mesh-side)."""
         n = self.n
         a = self.bg.a(self.tau)
-        kap = self.bg.kappa(n, self.n_p) / (a * a)
+        kap = self.kappa() / (a * a)
         E = kap * self.dep[0]
         J = [kap * self.dep[1 + i] for i in range(3)]
         K = [kap * self.dep[4 + s] for s in range(6)]
@@ -458,7 +493,7 @@ class OracleSim:
             raise RuntimeError("deposit() must run before solve()")
         if self.physics == NEWTONIAN:
             a = self.bg.a(self.tau)
-            E = self.bg.kappa(n, self.n_p) / (a * a) * self.dep[0]
+            E = self.kappa() / (a * a) * self.dep[0]
             eb = self.bg.ebar(a)
             kt = lattice_symbols(n)
             k2 = kt[0] ** 2 + kt[1] ** 2 + kt[2] ** 2
@@ -520,14 +555,15 @@ class OracleSim:
         return [ifft3(hk, self.n) for hk in self.h_k]
 
     # -- stage 3 ----------------------------------------------------------
-    def gathered(self):
-        """CIC-interpolated fields at the particles: phi, chi, B (3), g_phi (3), g_chi (3), G_ij = d_i B_j (9)."""
+    def gathered(self, pos=None):
+        """CIC-interpolated fields at the particles (species 1, or the positions given): phi, chi,
+        B (3), g_phi (3), g_chi (3), G_ij = d_i B_j (9)."""
         n = self.n
         fields = [self.phi, self.chi] + list(self.B)
         fields += grad(self.phi, n) + grad(self.chi, n)
         gB = [grad(self.B[j], n) for j in range(3)]
         fields += [gB[j][i] for i in range(3) for j in range(3)]
-        return interpolate(fields, self.pos, n)
+        return interpolate(fields, self.pos if pos is None else pos, n)
 
     def update(self, dtau: float, extra_gphi: np.ndarray | None = None):
         """Kick u^{n-1/2} -> u^{n+1/2} and drift x^n -> x^{n+1} (Eqs. 9-10 to first order in phi, psi, B).
@@ -538,11 +574,18 @@ class OracleSim:
             dx_i = dtau [ (u_i / e') (1 + (3 - |u|^2/e'^2) phi - chi) + B_i ]
         Newtonian limit (Sec. 3.2): du = -dtau a grad psi, dx = dtau u / a'.
         All fields are taken at x^n.  ``extra_gphi`` (3, N_p) is added to the
-        gathered gradient of phi (the learned closure's correction).
+        gathered gradient of phi (the learned closure's correction).  The equations are per unit
+        mass, so a second species takes the same update in the same fields.
         """
         a = self.bg.a(self.tau)
         ah = self.bg.a(self.tau + 0.5 * dtau)
-        g = self.gathered()
+        self.pos, self.u = self._kick_drift(self.pos, self.u, a, ah, dtau, extra_gphi)
+        if self.pos2 is not None:
+            self.pos2, self.u2 = self._kick_drift(self.pos2, self.u2, a, ah, dtau, None)
+        self.tau += dtau
+
+    def _kick_drift(self, pos, u_in, a, ah, dtau, extra_gphi):
+        g = self.gathered(pos)
         phi_p, chi_p = g[0], g[1]
         B_p = g[2:5]
         gphi = g[5:8].copy()
@@ -550,10 +593,10 @@ class OracleSim:
         G = g[11:20].reshape(3, 3, -1)  # G[i][j] = d_i B_j
         if extra_gphi is not None:
             gphi = gphi + extra_gphi
-        u = self.u.T.copy()
+        u = u_in.T.copy()
         if self.physics == NEWTONIAN:
             u = u - dtau * a * gphi
-            x = self.pos.T + dtau * u / ah
+            x = pos.T + dtau * u / ah
         else:
             u2 = np.sum(u * u, axis=0)
             e = np.sqrt(a * a + u2)
@@ -566,10 +609,8 @@ class OracleSim:
             vel = (u / eh) * (1.0 + (3.0 - u2 / (eh * eh)) * phi_p - chi_p)
             if self.physics == FULL:
                 vel = vel + B_p
-            x = self.pos.T + dtau * vel
-        self.u = u.T.copy()
-        self.pos = wrap_positions(x.T.copy())
-        self.tau += dtau
+            x = pos.T + dtau * vel
+        return wrap_positions(x.T.copy()), u.T.copy()
 
     # -- whole step ---------------------------------------------------------
     def step(self, dtau: float, dtau_prev: float | None = None):
@@ -586,3 +627,7 @@ class OracleSim:
     def particles_by_id(self):
         order = np.argsort(self.ids, kind="stable")
         return self.pos[order], self.u[order]
+
+    def species2(self):
+        """Positions and momenta of the second species (in their given order)."""
+        return self.pos2, self.u2

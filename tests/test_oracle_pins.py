@@ -594,3 +594,79 @@ def test_p18_parabolic_and_elliptic_routes_agree():
     num = math.sqrt(sum(np.sum((sims[1].B[j] - sims[0].B[j]) ** 2) for j in range(3)))
     den = math.sqrt(sum(np.sum(sims[0].B[j] ** 2) for j in range(3)))
     assert den > 0 and num / den < 0.1, num / den
+
+
+# ---------------------------------------------------------------------------
+# P19: a second particle species (the stress-energy sums run over all particles, each with its
+# own mass, Sec. 3.1 below Eq. 10; the kick and drift are per unit mass and keep the momentum
+# non-perturbative, so a hot species takes the same update)
+# ---------------------------------------------------------------------------
+
+def _two_species_fields(sim):
+    return [sim.phi, sim.chi] + list(sim.B) + sim.h_real()
+
+
+def test_p19_splitting_one_species_into_two_changes_nothing():
+    """Half of the particles as species 2 with half of the mass (equal particle masses): the same run."""
+    from synth import config_particles
+    pos, u, tau0, dtau = config_particles("c1_32_scalar_fp64", n=16)
+    one = pm.OracleSim(n=16, box_mpch=160.0, physics=pm.FULL, pos=pos, u=u, tau=tau0)
+    two = pm.OracleSim(n=16, box_mpch=160.0, physics=pm.FULL, pos=pos[0::2], u=u[0::2], tau=tau0,
+                       pos2=pos[1::2], u2=u[1::2], mass_fraction2=0.5)
+    assert abs(two.species_weight() - 1.0) < 1e-15 and abs(two.kappa() - one.kappa()) < 1e-15 * one.kappa()
+    for _ in range(3):
+        one.step(dtau)
+        two.step(dtau)
+    for f1, f2 in zip(_two_species_fields(one), _two_species_fields(two)):
+        assert np.max(np.abs(f1 - f2)) <= 1e-12 * (np.max(np.abs(f1)) + 1e-300)
+    assert np.max(np.abs(one.pos[0::2] - two.pos)) < 1e-14
+    assert np.max(np.abs(one.pos[1::2] - two.pos2)) < 1e-14
+    assert np.max(np.abs(one.u[1::2] - two.u2)) < 1e-14 * np.max(np.abs(one.u))
+
+
+@pytest.mark.parametrize("f", [0.3, 1e-9])
+def test_p19_copy_as_second_species_is_a_test_population(f):
+    """Species 2 = an exact copy of species 1 carrying any fraction f of the mass: the mesh sees the
+    same total (m_1 N (1 + m_2/m_1) is the whole mass either way), so the fields equal those of
+    species 1 alone, and the copy follows the same trajectories."""
+    from synth import config_particles
+    pos, u, tau0, dtau = config_particles("c1_32_scalar_fp64", n=16)
+    one = pm.OracleSim(n=16, box_mpch=160.0, physics=pm.FULL, pos=pos, u=u, tau=tau0)
+    two = pm.OracleSim(n=16, box_mpch=160.0, physics=pm.FULL, pos=pos, u=u, tau=tau0,
+                       pos2=pos.copy(), u2=u.copy(), mass_fraction2=f)
+    for _ in range(3):
+        one.step(dtau)
+        two.step(dtau)
+    for f1, f2 in zip(_two_species_fields(one), _two_species_fields(two)):
+        assert np.max(np.abs(f1 - f2)) <= 1e-12 * (np.max(np.abs(f1)) + 1e-300)
+    assert np.max(np.abs(two.pos2 - two.pos)) == 0.0 and np.max(np.abs(two.u2 - two.u)) == 0.0
+    assert np.max(np.abs(two.pos - one.pos)) < 1e-14
+
+
+def test_p19_hot_species_raises_the_homogeneous_mode_by_its_kinetic_energy():
+    """Species 1 at rest, species 2 with |u| = U in random directions, fraction f of the mass.  The mesh
+    mean of kappa a^-2 n00 is (1 - f + f sqrt(1 + U^2/a^2)) ebar (CIC partition of unity), so the first
+    quasi-static pass (phi = chi = 0 lagged, no remainder) gives the mean
+    phi = f ebar (sqrt(1 + U^2/a^2) - 1) / (-6 H^2 - ebar)."""
+    r = np.random.default_rng(19)
+    n, box, f = 8, 80.0, 0.2
+    bg = pm.Background(box)
+    tau = bg.tau(0.05)
+    a = bg.a(tau)
+    U = 3.0 * a
+    d = r.normal(size=(300, 3))
+    u2 = U * d / np.linalg.norm(d, axis=1)[:, None]
+    sim = pm.OracleSim(n=n, box_mpch=box, physics=pm.FULL, pos=lattice_positions(n), u=np.zeros((n ** 3, 3)),
+                       tau=tau, pos2=r.random((300, 3)), u2=u2, mass_fraction2=f)
+    sim.deposit()
+    z = np.zeros((n, n, n))
+    phi, _, _, _ = sim._solve_once(z, z, z, 0.0)
+    eb, hc = bg.ebar(a), bg.hconf(tau)
+    expect = f * eb * (math.sqrt(1.0 + (U / a) ** 2) - 1.0) / (-6.0 * hc * hc - eb)
+    assert abs(phi.mean() - expect) < 1e-12 * abs(expect)
+    # without the hot species' kinetic energy (U = 0) the mean vanishes
+    sim0 = pm.OracleSim(n=n, box_mpch=box, physics=pm.FULL, pos=lattice_positions(n), u=np.zeros((n ** 3, 3)),
+                        tau=tau, pos2=sim.pos2, u2=np.zeros_like(u2), mass_fraction2=f)
+    sim0.deposit()
+    phi0, _, _, _ = sim0._solve_once(z, z, z, 0.0)
+    assert abs(phi0.mean()) < 1e-14 * abs(expect) / f
