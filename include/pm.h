@@ -111,6 +111,18 @@ typedef struct pm_config {
   double box_mpch;      /* box side in Mpc/h (sets H0 in box units) */
   int32_t physics;      /* PM_NEWTONIAN, PM_SCALAR or PM_FULL */
   uint32_t flags;       /* PM_FLAG_* */
+  /* Optional second particle species of another particle mass (e.g. a hot,
+   * neutrino-like set; Sec. 3.1: the stress-energy sums run over all particles,
+   * each with its own mass, and the update keeps momenta non-perturbative).
+   * n_particles_2 = 0 (and mass_fraction_2 = 0): none.  Otherwise the species
+   * holds n_particles_2 (1 .. 2^31 - 1) particles carrying the fraction
+   * 0 < mass_fraction_2 < 1 of the total rest mass (species 1 carries the rest;
+   * the background stays Einstein-de Sitter).  Both species deposit into the
+   * same fields, species 2 weighted by its particle mass over species 1's, and
+   * both take the same kick and drift.  P(k) and the closure's grad-phi gather
+   * use species 1. */
+  int64_t n_particles_2;
+  double mass_fraction_2;
 } pm_config;
 
 typedef struct pm_ctx pm_ctx;
@@ -133,6 +145,14 @@ pm_status pm_destroy(pm_ctx* ctx);
  * device (1) or host (0) memory. */
 pm_status pm_init_particles(pm_ctx* ctx, const double* pos, const void* u, const uint32_t* ids, int64_t n,
                             double tau0, int src_on_device);
+
+/* Load the second species (same conventions as pm_init_particles; n must equal
+ * cfg.n_particles_2; ids a permutation of 0..n-1 or NULL).  Call after
+ * pm_init_particles (which takes the start time and unloads the second species);
+ * PM_EINVAL if the configuration has no second species.  pm_deposit returns
+ * PM_ESTATE while a configured second species is not loaded. */
+pm_status pm_init_particles_2(pm_ctx* ctx, const double* pos, const void* u, const uint32_t* ids, int64_t n,
+                              int src_on_device);
 
 /* Stage 1: CIC deposit of e, u_i and u_i u_j / e at a(tau) (Sec. 3.1, Eqs. 11-13). */
 pm_status pm_deposit(pm_ctx* ctx);
@@ -160,6 +180,9 @@ pm_status pm_set_field(pm_ctx* ctx, int field_id, const void* src, int src_on_de
 /* Particles in identifier order: pos [n][3] doubles, u [n][3] context precision,
  * ids [n] (may be NULL; any of pos/u may be NULL). */
 pm_status pm_get_particles(pm_ctx* ctx, double* pos, void* u, uint32_t* ids, int dst_on_device);
+
+/* The second species in identifier order (as pm_get_particles). */
+pm_status pm_get_particles_2(pm_ctx* ctx, double* pos, void* u, uint32_t* ids, int dst_on_device);
 
 /* Current conformal time, scale factor and number of completed steps. */
 pm_status pm_get_time(pm_ctx* ctx, double* tau, double* a, int64_t* steps);
@@ -201,7 +224,8 @@ pm_status pm_power_spectrum(pm_ctx* ctx, int subtract_shot_noise, double* k_out,
  * everything the next steps depend on: the particles in their sorted order,
  * the cell offsets of the sort, phi of the latest and the previous solve, chi,
  * B_i, the tensor state (h and its time derivative, two polarisations, Sec. 3.1),
- * the parabolic a^2 B state, the FP64 homogeneous-mode scalars, tau, the step
+ * the parabolic a^2 B state, the second species' particles and cell offsets,
+ * the FP64 homogeneous-mode scalars, tau, the step
  * counter, the last two time steps, the call-order state and, between
  * pm_deposit and pm_solve_metric, the deposit.  Not included: the closure's
  * parameters and its enable switch (bind them again after a restore).

@@ -26,6 +26,8 @@ bool is_pow2(long v) { return v > 0 && (v & (v - 1)) == 0; }
 // byte offsets of every device buffer inside the workspace
 struct Layout {
   size_t pos[2], mom[2], ids[2], rank, cnt, cell_start, bsum;
+  // second particle species (zero offsets without one)
+  size_t pos2[2], mom2[2], ids2[2], rank2, cnt2, cell_start2;
   size_t dep, part, phi[3], chi, b[3], spec, spec_out, hst, a2b, tw, kt, rowsum, scal, err;
   // learned closure (PM_FLAG_CLOSURE): activations, gradients, packed weights, partials
   size_t cl_act[3], cl_dact[3], cl_corr, cl_dcorr, cl_wf, cl_wb, cl_bias, cl_part, cl_scal;
@@ -60,9 +62,21 @@ Layout make_layout(const pm_config& c) {
   L.rank = take(np * 4);
   L.cnt = take(n3 * 4);
   L.cell_start = take((n3 + 1) * 4);
+  const long np2 = c.n_particles_2;
+  if (np2 > 0) {
+    for (int b = 0; b < 2; ++b) {
+      L.pos2[b] = take(3 * np2 * 8 + 2 * kSkew);
+      L.mom2[b] = take(3 * np2 * rs + 2 * kSkew);
+      L.ids2[b] = take(np2 * 4);
+    }
+    L.rank2 = take(np2 * 4);
+    L.cnt2 = take(n3 * 4);
+    L.cell_start2 = take((n3 + 1) * 4);
+  }
   L.bsum = take(scan_block_sums_count(n3) * 4 + 64);
   L.dep = take(L.ndep * n3 * rs);
-  L.part = take((n3 / 512 + 64) * 8);  // one FP64 partial per deposit block (16 x 8 x 4 vertices)
+  // one FP64 energy partial per deposit block and species
+  L.part = take(((size_t)deposit_blocks((int)n) * (np2 > 0 ? 2 : 1) + 64) * 8);
   for (int i = 0; i < 3; ++i) L.phi[i] = take(n3 * rs);
   L.chi = mode != MODE_NEWTONIAN ? take(n3 * rs) : 0;
   for (int i = 0; i < 3; ++i) L.b[i] = mode == MODE_FULL ? take(n3 * rs) : 0;
@@ -104,6 +118,9 @@ pm_status check_config(const pm_config* c) {
   if (c->precision != PM_FP32 && c->precision != PM_FP64) return PM_EINVAL;
   if (c->physics < PM_NEWTONIAN || c->physics > PM_FULL) return PM_EINVAL;
   if (c->n_particles < 1 || c->n_particles > 2147483647LL) return PM_ERANGE;
+  if (c->n_particles_2 < 0 || c->n_particles_2 > 2147483647LL) return PM_ERANGE;
+  if (c->n_particles_2 > 0 ? !(c->mass_fraction_2 > 0.0 && c->mass_fraction_2 < 1.0) : c->mass_fraction_2 != 0.0)
+    return PM_EINVAL;
   if (!(c->box_mpch > 0) || !isfinite(c->box_mpch)) return PM_EINVAL;
   return PM_OK;
 }
@@ -129,7 +146,9 @@ struct pm_ctx {
   pm_config cfg;
   Layout L;
   int n = 0, mode = 0;
-  long n3 = 0, np = 0;
+  long n3 = 0, np = 0, np2 = 0;
+  int cur2 = 0;                // particle buffer holding the sorted second species
+  bool have_particles2 = false;
   size_t rs = 4;
   hipStream_t st = nullptr;
   unsigned char* ws = nullptr;
@@ -153,7 +172,13 @@ struct pm_ctx {
   double a_of(double t) const { const double x = 0.5 * h0() * t; return x * x; }
   double hc_of(double t) const { return 2.0 / t; }
   double ebar(double a) const { return 1.5 * h0() * h0() / a; }
-  double kappa() const { return 1.5 * h0() * h0() * (double)n3 / (double)np; }
+  // 4 pi G m_1 / dx^3: species 1 carries the fraction 1 - f of the rest mass
+  double kappa() const { return 1.5 * h0() * h0() * (double)n3 * (1.0 - cfg.mass_fraction_2) / (double)np; }
+  // particle mass of species 2 over that of species 1
+  double weight2() const {
+    const double f = cfg.mass_fraction_2;
+    return np2 > 0 ? (f / (double)np2) / ((1.0 - f) / (double)np) : 0.0;
+  }
 
   pm_status fail(pm_status s, const char* msg) {
     last_error = msg;
@@ -205,16 +230,18 @@ struct pm_ctx {
     ev_n[s] += 1;
   }
 
-  template <typename T> Particles<T> parts(int b) {
+  template <typename T> Particles<T> parts_at(size_t pos, size_t mom, size_t ids, long cnt) {
     Particles<T> p;
-    double* pb = at<double>(L.pos[b]);
-    T* mb = at<T>(L.mom[b]);
+    double* pb = at<double>(pos);
+    T* mb = at<T>(mom);
     const long sd = (long)(kSkew / sizeof(double)), st_ = (long)(kSkew / sizeof(T));
-    p.px = pb; p.py = pb + np + sd; p.pz = pb + 2 * (np + sd);
-    p.ux = mb; p.uy = mb + np + st_; p.uz = mb + 2 * (np + st_);
-    p.id = at<uint32_t>(L.ids[b]);
+    p.px = pb; p.py = pb + cnt + sd; p.pz = pb + 2 * (cnt + sd);
+    p.ux = mb; p.uy = mb + cnt + st_; p.uz = mb + 2 * (cnt + st_);
+    p.id = at<uint32_t>(ids);
     return p;
   }
+  template <typename T> Particles<T> parts(int b) { return parts_at<T>(L.pos[b], L.mom[b], L.ids[b], np); }
+  template <typename T> Particles<T> parts2(int b) { return parts_at<T>(L.pos2[b], L.mom2[b], L.ids2[b], np2); }
   void* field_ptr(int id) {
     if (id >= PM_FIELD_N00 && id <= PM_FIELD_NZZ) {
       if (id >= L.ndep) return nullptr;
@@ -350,6 +377,15 @@ void sort_particles(pm_ctx* c) {
 }
 
 template <typename T>
+void sort_particles2(pm_ctx* c) {
+  const Layout& L = c->L;
+  launch_scan(c->at<uint32_t>(L.cnt2), c->at<uint32_t>(L.cell_start2), c->n3, c->at<uint32_t>(L.bsum), c->st);
+  launch_scatter<T>(c->parts2<T>(c->cur2), c->parts2<T>(1 - c->cur2), c->np2, c->n, c->at<uint32_t>(L.rank2),
+                    c->at<uint32_t>(L.cell_start2), c->st);
+  c->cur2 = 1 - c->cur2;
+}
+
+template <typename T>
 pm_status do_init(pm_ctx* c, const double* pos, const void* u, const uint32_t* ids, int on_device) {
   const Layout& L = c->L;
   const long np = c->np;
@@ -382,6 +418,32 @@ pm_status do_init(pm_ctx* c, const double* pos, const void* u, const uint32_t* i
   sort_particles<T>(c);
   if (!on_device) hipStreamSynchronize(c->st);  // host buffers may be released after return
   return c->hip_check("init_particles");
+}
+
+// the second species: ingest (positions wrapped, identifiers checked) and sort by cell
+template <typename T>
+pm_status do_init2(pm_ctx* c, const double* pos, const void* u, const uint32_t* ids, int on_device) {
+  const Layout& L = c->L;
+  const long np = c->np2;
+  const double* dpos = pos;
+  const T* du = reinterpret_cast<const T*>(u);
+  const uint32_t* dids = ids;
+  if (!on_device) {
+    double* sp = c->at<double>(L.pos2[1]);
+    T* su = c->at<T>(L.mom2[1]);
+    uint32_t* si = c->at<uint32_t>(L.ids2[1]);
+    hipMemcpyAsync(sp, pos, 3 * np * sizeof(double), hipMemcpyHostToDevice, c->st);
+    hipMemcpyAsync(su, u, 3 * np * sizeof(T), hipMemcpyHostToDevice, c->st);
+    if (ids) hipMemcpyAsync(si, ids, np * sizeof(uint32_t), hipMemcpyHostToDevice, c->st);
+    dpos = sp; du = su; dids = ids ? si : nullptr;
+  }
+  c->zero(L.cnt2, c->n3 * 4);
+  launch_ingest<T>(dpos, du, dids, np, c->parts2<T>(0), c->n, c->at<uint32_t>(L.rank2), c->at<uint32_t>(L.cnt2),
+                   c->at<int>(L.err), c->st);
+  c->cur2 = 0;
+  sort_particles2<T>(c);
+  if (!on_device) hipStreamSynchronize(c->st);
+  return c->hip_check("init_particles_2");
 }
 
 // features of the last deposit (n00) and the latest phi -> three convolutions -> FP32 SoA output
@@ -428,9 +490,13 @@ pm_status do_update(pm_ctx* c, double dtau) {
   c->stage_begin(PM_STAGE_KICK_DRIFT);
   launch_kick_drift<T>(c->parts<T>(c->cur), c->np, c->n, c->at<uint32_t>(L.cell_start), g, c->at<uint32_t>(L.rank),
                        c->at<uint32_t>(L.cnt), c->at<int>(L.err), c->st);
+  if (c->np2 > 0)  // the second species: the same update (per unit mass) in the same fields
+    launch_kick_drift<T>(c->parts2<T>(c->cur2), c->np2, c->n, c->at<uint32_t>(L.cell_start2), g,
+                         c->at<uint32_t>(L.rank2), c->at<uint32_t>(L.cnt2), c->at<int>(L.err), c->st);
   c->stage_end(PM_STAGE_KICK_DRIFT);
   c->stage_begin(PM_STAGE_SORT);
   sort_particles<T>(c);
+  if (c->np2 > 0) sort_particles2<T>(c);
   c->stage_end(PM_STAGE_SORT);
   c->tau += dtau;
   c->steps += 1;
@@ -478,6 +544,7 @@ pm_status pm_create(const pm_config* cfg, void* d_workspace, size_t bytes, void*
   c->n = cfg->n_mesh;
   c->n3 = (long)c->n * c->n * c->n;
   c->np = cfg->n_particles;
+  c->np2 = cfg->n_particles_2;
   c->mode = mode_of(cfg->physics);
   c->rs = cfg->precision == PM_FP64 ? 8 : 4;
   c->st = reinterpret_cast<hipStream_t>(hip_stream);
@@ -515,6 +582,7 @@ pm_status pm_init_particles(pm_ctx* c, const double* pos, const void* u, const u
   c->i_phi = 0;
   c->i_prev = 1;
   c->deposited = c->solved = c->solved_once = false;
+  c->have_particles2 = false;  // a second species is loaded again for the new start
   pm_status s = DISPATCH(c, do_init, c, pos, u, ids, src_on_device);
   if (s != PM_OK) return s;
   c->have_particles = true;
@@ -525,16 +593,28 @@ pm_status pm_deposit(pm_ctx* c) {
   if (!c) return PM_EINVAL;
   if (!c->have_particles) return c->fail(PM_ESTATE, "deposit before init_particles");
   if (c->sticky) return (pm_status)c->sticky;
+  if (c->np2 > 0 && !c->have_particles2) return c->fail(PM_ESTATE, "deposit before init_particles_2");
   const double a = c->a_of(c->tau);
+  const Layout& L = c->L;
+  const bool rel = c->mode != MODE_NEWTONIAN;
+  const long nb = deposit_blocks(c->n);
+  double* part = c->at<double>(L.part);
   c->stage_begin(PM_STAGE_DEPOSIT);
-  if (c->cfg.precision == PM_FP64)
-    launch_deposit<double>(c->parts<double>(c->cur), c->at<uint32_t>(c->L.cell_start), c->n, c->L.ndep,
-                           c->mode != MODE_NEWTONIAN, a, c->at<double>(c->L.dep), c->at<double>(c->L.part),
-                           c->at<double>(c->L.scal) + 2, c->st);
-  else
-    launch_deposit<float>(c->parts<float>(c->cur), c->at<uint32_t>(c->L.cell_start), c->n, c->L.ndep,
-                          c->mode != MODE_NEWTONIAN, a, c->at<float>(c->L.dep), c->at<double>(c->L.part),
-                          c->at<double>(c->L.scal) + 2, c->st);
+  if (c->cfg.precision == PM_FP64) {
+    launch_deposit<double>(c->parts<double>(c->cur), c->at<uint32_t>(L.cell_start), c->n, L.ndep, rel, a, 1.0, false,
+                           c->at<double>(L.dep), part, c->st);
+    if (c->np2 > 0)
+      launch_deposit<double>(c->parts2<double>(c->cur2), c->at<uint32_t>(L.cell_start2), c->n, L.ndep, rel, a,
+                             c->weight2(), true, c->at<double>(L.dep), part + nb, c->st);
+  } else {
+    launch_deposit<float>(c->parts<float>(c->cur), c->at<uint32_t>(L.cell_start), c->n, L.ndep, rel, a, 1.0, false,
+                          c->at<float>(L.dep), part, c->st);
+    if (c->np2 > 0)
+      launch_deposit<float>(c->parts2<float>(c->cur2), c->at<uint32_t>(L.cell_start2), c->n, L.ndep, rel, a,
+                            c->weight2(), true, c->at<float>(L.dep), part + nb, c->st);
+  }
+  // FP64 sum over particles of e (species 2 weighted by its mass ratio), fixed order
+  if (L.ndep > 1) launch_sum_f64(part, nb * (c->np2 > 0 ? 2 : 1), c->at<double>(L.scal) + 2, c->st);
   c->stage_end(PM_STAGE_DEPOSIT);
   c->deposited = true;
   return c->hip_check("deposit");
@@ -660,6 +740,44 @@ pm_status pm_get_particles(pm_ctx* c, double* pos, void* u, uint32_t* ids, int d
   return dst_on_device ? PM_OK : read_sticky(c);
 }
 
+pm_status pm_init_particles_2(pm_ctx* c, const double* pos, const void* u, const uint32_t* ids, int64_t n,
+                              int src_on_device) {
+  if (!c || !pos || !u) return PM_EINVAL;
+  if (c->np2 == 0) return c->fail(PM_EINVAL, "the configuration has no second species");
+  if (n != c->np2) return c->fail(PM_EINVAL, "n differs from the configured count of the second species");
+  if (!c->have_particles) return c->fail(PM_ESTATE, "init_particles_2 before init_particles");
+  if (c->sticky) return (pm_status)c->sticky;
+  pm_status s = DISPATCH(c, do_init2, c, pos, u, ids, src_on_device);
+  if (s != PM_OK) return s;
+  c->have_particles2 = true;
+  c->deposited = c->solved = false;
+  return PM_OK;
+}
+
+pm_status pm_get_particles_2(pm_ctx* c, double* pos, void* u, uint32_t* ids, int dst_on_device) {
+  if (!c) return PM_EINVAL;
+  if (c->np2 == 0 || !c->have_particles2) return c->fail(PM_ESTATE, "no second species loaded");
+  const Layout& L = c->L;
+  const long np = c->np2;
+  const int other = 1 - c->cur2;
+  double* sp = dst_on_device ? pos : (pos ? c->at<double>(L.pos2[other]) : nullptr);
+  void* su = dst_on_device ? u : (u ? (void*)(c->ws + L.mom2[other]) : nullptr);
+  uint32_t* si = dst_on_device ? ids : (ids ? c->at<uint32_t>(L.ids2[other]) : nullptr);
+  if (c->cfg.precision == PM_FP64)
+    launch_export<double>(c->parts2<double>(c->cur2), np, sp, reinterpret_cast<double*>(su), si, c->st);
+  else
+    launch_export<float>(c->parts2<float>(c->cur2), np, sp, reinterpret_cast<float*>(su), si, c->st);
+  if (!dst_on_device) {
+    if (pos) hipMemcpyAsync(pos, sp, 3 * np * sizeof(double), hipMemcpyDeviceToHost, c->st);
+    if (u) hipMemcpyAsync(u, su, 3 * np * c->rs, hipMemcpyDeviceToHost, c->st);
+    if (ids) hipMemcpyAsync(ids, si, np * sizeof(uint32_t), hipMemcpyDeviceToHost, c->st);
+    hipStreamSynchronize(c->st);
+  }
+  pm_status s = c->hip_check("get_particles_2");
+  if (s != PM_OK) return s;
+  return dst_on_device ? PM_OK : read_sticky(c);
+}
+
 pm_status pm_get_time(pm_ctx* c, double* tau, double* a, int64_t* steps) {
   if (!c) return PM_EINVAL;
   if (tau) *tau = c->tau;
@@ -752,7 +870,7 @@ template <typename T>
 pm_status do_power_spectrum(pm_ctx* c, int subtract, double* k_out, double* p_out, double* modes_out) {
   const Layout& L = c->L;
   T* dep = c->at<T>(L.dep);
-  launch_deposit<T>(c->parts<T>(c->cur), c->at<uint32_t>(L.cell_start), c->n, 1, false, 1.0, dep, nullptr, nullptr,
+  launch_deposit<T>(c->parts<T>(c->cur), c->at<uint32_t>(L.cell_start), c->n, 1, false, 1.0, 1.0, false, dep, nullptr,
                     c->st);
   SrcArgsH<T> s;
   s.raw = dep;
@@ -797,7 +915,7 @@ pm_status pm_power_spectrum(pm_ctx* c, int subtract_shot_noise, double* k_out, d
 namespace {
 
 constexpr uint64_t kStateMagic = 0x31455441545347ULL;  // "GSTATE1" (little-endian bytes)
-constexpr uint32_t kStateVersion = 1;
+constexpr uint32_t kStateVersion = 2;
 constexpr size_t kStateHeader = 1024;
 constexpr int kStateMaxSec = 32;
 
@@ -809,6 +927,8 @@ struct StateHeader {
   double tau, last_step, dtau_last;
   int64_t steps;
   int32_t deposited, solved, solved_once, pad;
+  int64_t n_particles_2;
+  double mass_fraction_2;
   uint64_t total;
   uint64_t off[kStateMaxSec], bytes[kStateMaxSec];
 };
@@ -817,7 +937,7 @@ static_assert(sizeof(StateHeader) <= kStateHeader, "state header too large");
 // workspace regions that make up the state: the sorted particles (buffer `cur`), the cell offsets
 // of the sort, phi of the latest and the previous solve, chi, B, the tensor and parabolic-B
 // spectra, the FP64 scalars and, between a deposit and its solve, the deposit
-int state_sections(const pm_ctx* c, int cur, int i_phi, int i_prev, bool with_dep, size_t* ws_off,
+int state_sections(const pm_ctx* c, int cur, int cur2, int i_phi, int i_prev, bool with_dep, size_t* ws_off,
                    size_t* bytes) {
   const Layout& L = c->L;
   const long np = c->np, n3 = c->n3;
@@ -828,6 +948,13 @@ int state_sections(const pm_ctx* c, int cur, int i_phi, int i_prev, bool with_de
   add(L.mom[cur], 3 * np * rs + 2 * kSkew);
   add(L.ids[cur], np * 4);
   add(L.cell_start, (n3 + 1) * 4);
+  if (c->np2 > 0) {
+    const long np2 = c->np2;
+    add(L.pos2[cur2], 3 * np2 * 8 + 2 * kSkew);
+    add(L.mom2[cur2], 3 * np2 * rs + 2 * kSkew);
+    add(L.ids2[cur2], np2 * 4);
+    add(L.cell_start2, (n3 + 1) * 4);
+  }
   add(L.phi[i_phi], n3 * rs);
   add(L.phi[i_prev], n3 * rs);
   if (L.chi) add(L.chi, n3 * rs);
@@ -856,9 +983,10 @@ extern "C" {
 pm_status pm_get_state(pm_ctx* c, void* blob, size_t* bytes, int dst_on_device) {
   if (!c || !bytes) return PM_EINVAL;
   if (!c->have_particles) return c->fail(PM_ESTATE, "no particles");
+  if (c->np2 > 0 && !c->have_particles2) return c->fail(PM_ESTATE, "no second species loaded");
   if (c->sticky) return (pm_status)c->sticky;
   size_t ws_off[kStateMaxSec], sb[kStateMaxSec];
-  const int nsec = state_sections(c, c->cur, c->i_phi, c->i_prev, c->deposited, ws_off, sb);
+  const int nsec = state_sections(c, c->cur, c->cur2, c->i_phi, c->i_prev, c->deposited, ws_off, sb);
   StateHeader h;
   memset(&h, 0, sizeof(h));
   const size_t total = state_blob_offsets(nsec, sb, h.off);
@@ -878,6 +1006,8 @@ pm_status pm_get_state(pm_ctx* c, void* blob, size_t* bytes, int dst_on_device) 
   h.physics = c->cfg.physics;
   h.parabolic = c->L.a2b ? 1 : 0;
   h.n_particles = c->np;
+  h.n_particles_2 = c->np2;
+  h.mass_fraction_2 = c->cfg.mass_fraction_2;
   h.tau = c->tau;
   h.last_step = c->last_step;
   h.dtau_last = c->dtau_last;
@@ -926,14 +1056,15 @@ pm_status pm_set_state(pm_ctx* c, const void* blob, size_t bytes, int src_on_dev
   }
   if (h.magic != kStateMagic || h.version != kStateVersion) return c->fail(PM_EINVAL, "not a state blob");
   if (h.n_mesh != c->n || h.precision != c->cfg.precision || h.physics != c->cfg.physics ||
-      h.parabolic != (c->L.a2b ? 1 : 0) || h.n_particles != c->np)
+      h.parabolic != (c->L.a2b ? 1 : 0) || h.n_particles != c->np || h.n_particles_2 != c->np2 ||
+      h.mass_fraction_2 != c->cfg.mass_fraction_2)
     return c->fail(PM_EINVAL, "state blob of another configuration");
   if (!(h.tau > 0) || !isfinite(h.tau) || h.steps < 0 || h.total > bytes)
     return c->fail(PM_EINVAL, "corrupt state header");
   // restore into particle buffer 0 and phi slots 0 (latest) and 1 (previous)
   size_t ws_off[kStateMaxSec], sb[kStateMaxSec];
   uint64_t off[kStateMaxSec];
-  const int nsec = state_sections(c, 0, 0, 1, h.deposited != 0, ws_off, sb);
+  const int nsec = state_sections(c, 0, 0, 0, 1, h.deposited != 0, ws_off, sb);
   const size_t total = state_blob_offsets(nsec, sb, off);
   if ((int)h.nsec != nsec || h.total != total) return c->fail(PM_EINVAL, "corrupt state header");
   for (int i = 0; i < nsec; ++i)
@@ -943,9 +1074,12 @@ pm_status pm_set_state(pm_ctx* c, const void* blob, size_t bytes, int src_on_dev
   for (int i = 0; i < nsec; ++i) (void)hipMemcpyAsync(c->ws + ws_off[i], src + off[i], sb[i], kind, c->st);
   // the per-cell counters are zero between sorts; the device error flag starts clear
   c->zero(c->L.cnt, c->n3 * 4);
+  if (c->np2 > 0) c->zero(c->L.cnt2, c->n3 * 4);
   c->zero(c->L.err, 64);
   if (!src_on_device) (void)hipStreamSynchronize(c->st);
   c->cur = 0;
+  c->cur2 = 0;
+  c->have_particles2 = c->np2 > 0;
   c->i_phi = 0;
   c->i_prev = 1;
   c->tau = h.tau;

@@ -113,9 +113,13 @@ struct Particles {
 template <typename T>
 void launch_ingest(const double* pos_aos, const T* u_aos, const uint32_t* ids, long n, Particles<T> out, int nmesh,
                    uint32_t* rank, uint32_t* cnt, int* err, hipStream_t st);
+// CIC deposit of one species: stores the sums (accumulate = false) or adds weight x the sums
+// (accumulate = true, a further species of particle mass weight x the first's); writes one FP64
+// energy partial (weight x the sum of e over the block's own cells) per block to esum_part
+int deposit_blocks(int n);
 template <typename T>
 void launch_deposit(const Particles<T>& p, const uint32_t* cell_start, int n, int ncomp, bool relativistic, double a,
-                    T* dep, double* esum_part, double* esum, hipStream_t st);
+                    double weight, bool accumulate, T* dep, double* esum_part, hipStream_t st);
 template <typename T>
 struct GatherArgs {
   const T* phi; const T* chi; const T* bx; const T* by; const T* bz;

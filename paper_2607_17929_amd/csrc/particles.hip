@@ -116,7 +116,8 @@ __device__ __forceinline__ void wave_row_offsets(uint32_t c, uint32_t* off) {
 
 template <typename T, int NC, bool REL>
 __global__ __launch_bounds__(DEP_NT, DEP_MIN_WAVES) void deposit_kernel(Particles<T> p, const uint32_t* __restrict__ cell_start, int n,
-                                                         T a, T* __restrict__ dep, double* __restrict__ esum) {
+                                                         T a, T w, double wd, int accumulate, T* __restrict__ dep,
+                                                         double* __restrict__ esum) {
   constexpr int CAP = dep_capacity<T>();
   constexpr int TX = DEP_TX, TY = DEP_TY, CX = DEP_CX, ROWS = DEP_ROWS, GW = TX + 3;
   constexpr int NQ = (ROWS * GW + DEP_NT - 1) / DEP_NT;  // cell_start reads per thread
@@ -282,8 +283,14 @@ __global__ __launch_bounds__(DEP_NT, DEP_MIN_WAVES) void deposit_kernel(Particle
     const int v = tid + k * DEP_NT;
     const int lvx = v % TX, lvy = (v / TX) % TY, lvz = v / (TX * TY);
     const long o = ((long)(z0 + lvz) * n + (y0 + lvy)) * n + (x0 + lvx);
+    if (accumulate) {
+      // a further species: its sums, weighted by its particle mass over the first species', are added
 #pragma unroll
-    for (int c = 0; c < NC; ++c) dep[c * n3 + o] = acc[k][c];
+      for (int c = 0; c < NC; ++c) dep[c * n3 + o] += w * acc[k][c];
+    } else {
+#pragma unroll
+      for (int c = 0; c < NC; ++c) dep[c * n3 + o] = acc[k][c];
+    }
   }
   if (esum) {
     // fixed-order reduction: within each wave, then the waves' sums in order
@@ -295,27 +302,29 @@ __global__ __launch_bounds__(DEP_NT, DEP_MIN_WAVES) void deposit_kernel(Particle
       double t = 0.0;
 #pragma unroll
       for (int w = 0; w < DEP_NT / 64; ++w) t += red[w];
-      esum[(bz * gridDim.y + by) * gridDim.x + bx] = t;
+      esum[(bz * gridDim.y + by) * gridDim.x + bx] = wd * t;
     }
   }
 }
 
+int deposit_blocks(int n) { return (n / DEP_TX) * (n / DEP_TY) * (n / DEP_TZ); }
+
 template <typename T>
 void launch_deposit(const Particles<T>& p, const uint32_t* cell_start, int n, int ncomp, bool relativistic, double a,
-                    T* dep, double* esum_part, double* esum, hipStream_t st) {
+                    double weight, bool accumulate, T* dep, double* esum_part, hipStream_t st) {
   dim3 grid(n / DEP_TX, n / DEP_TY, n / DEP_TZ);  // n >= 16
+  const int acc = accumulate ? 1 : 0;
   if (ncomp == 1) {
-    hipLaunchKernelGGL((deposit_kernel<T, 1, false>), grid, dim3(DEP_NT), 0, st, p, cell_start, n, (T)a, dep,
-                       (double*)nullptr);
+    hipLaunchKernelGGL((deposit_kernel<T, 1, false>), grid, dim3(DEP_NT), 0, st, p, cell_start, n, (T)a, (T)weight,
+                       weight, acc, dep, (double*)nullptr);
     return;
   }
   if (relativistic)
-    hipLaunchKernelGGL((deposit_kernel<T, 10, true>), grid, dim3(DEP_NT), 0, st, p, cell_start, n, (T)a, dep,
-                       esum_part);
+    hipLaunchKernelGGL((deposit_kernel<T, 10, true>), grid, dim3(DEP_NT), 0, st, p, cell_start, n, (T)a, (T)weight,
+                       weight, acc, dep, esum_part);
   else
-    hipLaunchKernelGGL((deposit_kernel<T, 10, false>), grid, dim3(DEP_NT), 0, st, p, cell_start, n, (T)a, dep,
-                       esum_part);
-  launch_sum_f64(esum_part, (long)grid.x * grid.y * grid.z, esum, st);
+    hipLaunchKernelGGL((deposit_kernel<T, 10, false>), grid, dim3(DEP_NT), 0, st, p, cell_start, n, (T)a, (T)weight,
+                       weight, acc, dep, esum_part);
 }
 
 // ---------------------------------------------------------------------------
@@ -773,8 +782,8 @@ void launch_copy_unpad(const cplx<T>* spec, int n, int nhp, cplx<T>* out, bool t
 #define GPM_INST(T)                                                                                                   \
   template void launch_ingest<T>(const double*, const T*, const uint32_t*, long, Particles<T>, int, uint32_t*,         \
                                  uint32_t*, int*, hipStream_t);                                                        \
-  template void launch_deposit<T>(const Particles<T>&, const uint32_t*, int, int, bool, double, T*, double*, double*, \
-                                  hipStream_t);                                                                       \
+  template void launch_deposit<T>(const Particles<T>&, const uint32_t*, int, int, bool, double, double, bool, T*,     \
+                                  double*, hipStream_t);                                                              \
   template void launch_kick_drift<T>(const Particles<T>&, long, int, const uint32_t*, const GatherArgs<T>&, uint32_t*, \
                                      uint32_t*, int*, hipStream_t);                                                    \
   template void launch_scatter<T>(const Particles<T>&, Particles<T>, long, int, const uint32_t*, const uint32_t*,      \

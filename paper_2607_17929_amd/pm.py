@@ -17,13 +17,15 @@ _PREC = {"fp32": L.PM_FP32, "fp64": L.PM_FP64}
 
 
 def make_config(n_mesh: int, n_particles: int, box_mpch: float, physics: str = "full", precision: str = "fp32",
-                timings: bool = False, closure: bool = False, b_route: str = "elliptic") -> L.PMConfig:
+                timings: bool = False, closure: bool = False, b_route: str = "elliptic", n_particles_2: int = 0,
+                mass_fraction_2: float = 0.0) -> L.PMConfig:
     if b_route not in ("elliptic", "parabolic"):
         raise ValueError("b_route must be 'elliptic' or 'parabolic'")
     flags = ((L.PM_FLAG_TIMINGS if timings else 0) | (L.PM_FLAG_CLOSURE if closure else 0)
              | (L.PM_FLAG_B_PARABOLIC if b_route == "parabolic" else 0))
     return L.PMConfig(n_mesh=n_mesh, precision=_PREC[precision], n_particles=n_particles, box_mpch=box_mpch,
-                      physics=_PHYS[physics], flags=flags)
+                      physics=_PHYS[physics], flags=flags, n_particles_2=n_particles_2,
+                      mass_fraction_2=mass_fraction_2)
 
 
 def query_workspace(cfg: L.PMConfig) -> int:
@@ -59,11 +61,14 @@ class PMContext:
 
     def __init__(self, n_mesh: int, n_particles: int, box_mpch: float, physics: str = "full",
                  precision: str = "fp32", timings: bool = False, device: str | torch.device = "cuda:0",
-                 stream: torch.cuda.Stream | None = None, closure: bool = False, b_route: str = "elliptic"):
+                 stream: torch.cuda.Stream | None = None, closure: bool = False, b_route: str = "elliptic",
+                 n_particles_2: int = 0, mass_fraction_2: float = 0.0):
         self.lib = L.load()
-        self.cfg = make_config(n_mesh, n_particles, box_mpch, physics, precision, timings, closure, b_route)
+        self.cfg = make_config(n_mesh, n_particles, box_mpch, physics, precision, timings, closure, b_route,
+                               n_particles_2, mass_fraction_2)
         self.n = n_mesh
         self.np = n_particles
+        self.np2 = n_particles_2
         self.physics = physics
         self.precision = precision
         self.dtype = torch.float64 if precision == "fp64" else torch.float32
@@ -110,6 +115,33 @@ class PMContext:
             self._chk(self.lib.pm_init_particles(self.ctx, pos.ctypes.data, u.ctypes.data,
                                                  idh.ctypes.data if idh is not None else None,
                                                  pos.shape[0], tau0, 0), "pm_init_particles")
+
+    def init_particles_2(self, pos, u, ids=None):
+        """The second species (pm_init_particles_2): pos [n2][3] float64, u [n2][3] context precision,
+        numpy (host) or CUDA tensors (device); after init_particles."""
+        if isinstance(pos, torch.Tensor):
+            pos = pos.to(torch.float64).contiguous()
+            u = u.to(self.dtype).contiguous()
+            idp = ids.to(torch.int32).contiguous() if ids is not None else None
+            self._keep2 = (pos, u, idp)
+            self._chk(self.lib.pm_init_particles_2(self.ctx, C.c_void_p(_ptr(pos)), C.c_void_p(_ptr(u)),
+                                                   C.c_void_p(_ptr(idp)) if idp is not None else None,
+                                                   pos.shape[0], 1), "pm_init_particles_2")
+        else:
+            pos = np.ascontiguousarray(pos, dtype=np.float64)
+            u = np.ascontiguousarray(u, dtype=self.np_dtype)
+            idh = np.ascontiguousarray(ids, dtype=np.uint32) if ids is not None else None
+            self._chk(self.lib.pm_init_particles_2(self.ctx, pos.ctypes.data, u.ctypes.data,
+                                                   idh.ctypes.data if idh is not None else None,
+                                                   pos.shape[0], 0), "pm_init_particles_2")
+
+    def get_particles_2(self):
+        """(pos [n2][3] float64, u [n2][3]) of the second species in identifier order (host)."""
+        pos = np.empty((self.np2, 3), dtype=np.float64)
+        u = np.empty((self.np2, 3), dtype=self.np_dtype)
+        self._chk(self.lib.pm_get_particles_2(self.ctx, pos.ctypes.data, u.ctypes.data, None, 0),
+                  "pm_get_particles_2")
+        return pos, u
 
     def deposit(self):
         self._chk(self.lib.pm_deposit(self.ctx), "pm_deposit")

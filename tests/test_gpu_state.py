@@ -151,7 +151,7 @@ def test_foreign_or_damaged_blobs_are_rejected():
     with pytest.raises(PMError):
         a.set_state(bad)
     bad = blob.copy()
-    bad[96:104] = 0xFF  # the first section's offset
+    bad[112:120] = 0xFF  # the first section's offset
     with pytest.raises(PMError):
         a.set_state(bad)
     # the context still holds its own state and steps on
