@@ -693,7 +693,7 @@ void launch_scan(uint32_t* cnt, uint32_t* cell_start, long ncell, uint32_t* bloc
 // scatter into the other buffer at cell_start[cell] + rank; the cell is
 // recomputed from the stored position exactly as the kick/drift computed it
 // ---------------------------------------------------------------------------
-constexpr int SC_PER = 4;  // particles per thread: independent load chains in flight
+constexpr int SC_PER = 2;  // particles per thread: independent load chains in flight (2 measured best of 2, 4, 8)
 
 template <typename T>
 __global__ __launch_bounds__(256) void scatter_kernel(Particles<T> s, Particles<T> d, long np, int nmesh,
