@@ -13,12 +13,11 @@
 //           that every global access is a C*sizeof(complex) = 128-byte segment.
 // The inverse runs pass Z, pass Y and the C2R pass X.  In the PM solve, pass Z,
 // the Fourier-space solves and the inverse pass Z are one fused kernel
-// (solve.hip).  Each 1D FFT is a
-// Stockham auto-sort radix-8/4/2 transform done in place in LDS: every thread
-// loads its butterflies' inputs into registers, the workgroup synchronises,
-// and the results are written back, so one tile buffer suffices.  The first
-// stage of a column pass reads straight from global memory and its last stage
-// writes straight to global memory.  Twiddles come from a table of
+// (solve.hip).  Every 1D FFT, along x too, is the Stockham auto-sort
+// radix-8/4/2 transform of fft_lds.h on an LDS tile of interleaved columns
+// (the lines of pass X sit in LDS as [element][line]).  The first stage of a
+// column pass reads straight from global memory and its last stage writes
+// straight to global memory.  Twiddles come from a table of
 // exp(-2 pi i j / n) computed in FP64 on the host.
 #include "common.h"
 #include "fft_lds.h"

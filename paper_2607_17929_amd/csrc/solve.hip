@@ -1,4 +1,5 @@
-// Fourier-space metric solves (Sec. 3.1 of the paper), one thread per mode of the half spectrum.
+// Fourier-space metric solves (Sec. 3.1 of the paper), per mode of the half spectrum, inside the
+// kernel that also runs the transforms along z.
 //
 // With the sources of the forward pass X (S_phi, Sigma_ij, S_i) and the
 // lattice wave vector kt_d = 2 n sin(pi m_d / n) (so that -kt^2 is the symbol
