@@ -199,9 +199,9 @@ def max_pk_deviation(k, ratio, kmax):
 
 def calibrate_amplitude(params, n_p1: int, box: float, rms_cells: float, seeds, scales=(1.0, 1.1, 1.2, 1.3, 1.4, 1.5),
                         steps: int = 100, log=print):
-    """Output amplitude of the closure chosen on training boxes: each box is run on the 2x mesh and on the 1x
-    mesh with the closure scaled by s; the s whose box-averaged P(k) ratio to the 2x runs deviates least up
-    to half the 1x Nyquist frequency is returned with the table of deviations."""
+    """Output amplitude of the closure chosen on calibration runs: each seeded box of n_p1^3 particles is run on
+    the 2x mesh and on the 1x mesh with the closure scaled by s; the s whose box-averaged P(k) ratio to the 2x
+    runs deviates least up to half the 1x Nyquist frequency is returned with the table of deviations."""
     from synth import spectrum_power_law_m2, zeldovich_particles
     from synth.ics import eds_a_of_tau
 
@@ -216,19 +216,33 @@ def calibrate_amplitude(params, n_p1: int, box: float, rms_cells: float, seeds, 
         u_d = torch.tensor(u, device="cuda", dtype=torch.float32)
         p2, _ = run_pm(2 * n_p1, pos_d, u_d, tau0, tau1, steps, box, None, log=None)
         k, pk2, _ = power_spectrum(p2, n_p1, box)
+        del p2
         for s in scales:
             p1, _ = run_pm(n_p1, pos_d, u_d, tau0, tau1, steps, box, scaled_output(params, s), log=None)
             ratios[s].append(power_spectrum(p1, n_p1, box)[1] / pk2)
+            if log:
+                log(f"  calibration seed {seed}, s = {s:.3f}: max deviation "
+                    f"{max_pk_deviation(k, ratios[s][-1], kmax):.4f}")
     table = {s: max_pk_deviation(k, np.mean(ratios[s], axis=0), kmax) for s in scales}
     if log:
-        log("calibration: " + ", ".join(f"s={s:.1f}: {d:.4f}" for s, d in table.items()))
+        log("calibration: " + ", ".join(f"s={s:.2f}: {d:.4f}" for s, d in table.items()))
     return min(table, key=table.get), table
 
 
+# P(k) at half the Nyquist frequency moves by about 2 % per 1 % of output amplitude, so the grid is fine
+CAL_SCALES = tuple(round(1.0 + 0.005 * i, 3) for i in range(31))
+VALIDATION_SEEDS = (7, 8)  # the application runs seed 3
+
+
 def experiment(n_app: int = 512, n_train_p: int = 128, train_box: float = 512.0, n_boxes: int = 64,
-               iters: int = 12000, lr: float = 1e-3, augment: bool = True, calibrate: bool = False, log=print):
+               iters: int = 12000, lr: float = 1e-3, augment: bool = True, calibrate: str = "validation", log=print):
     """Train on seeded boxes (1x and 2x meshes), apply to n_app^3 particles on an n_app^3 mesh and compare
-    P(k) and cost with the plain n_app^3 and 2 n_app^3 meshes at a = 0.5."""
+    P(k) and cost with the plain n_app^3 and 2 n_app^3 meshes at a = 0.5.
+
+    calibrate: "validation" scales the output by the amplitude that best matches the 2x spectrum, averaged
+    over other realizations of the application (same box, mesh and recipe, seeds VALIDATION_SEEDS; the
+    application's own seed is never used to choose it); "train" chooses it on 4 training boxes; "none" keeps the trained
+    output."""
     from synth import spectrum_power_law_m2, zeldovich_particles
     from synth.ics import eds_a_of_tau
 
@@ -255,12 +269,20 @@ def experiment(n_app: int = 512, n_train_p: int = 128, train_box: float = 512.0,
         f"closure {res['heldout_closure']:.4e}")
     del c1, snaps
     torch.cuda.empty_cache()
-    if calibrate:
+    if calibrate not in ("validation", "train", "none"):
+        raise ValueError("calibrate must be 'validation', 'train' or 'none'")
+    if calibrate != "none":
         t0 = time.time()
-        s, table = calibrate_amplitude(params, n_train_p, train_box, rms_train, seeds=range(1000, 1000 + 4), log=log)
+        if calibrate == "train":
+            s, table = calibrate_amplitude(params, n_train_p, train_box, rms_train, seeds=range(1000, 1000 + 4),
+                                           scales=CAL_SCALES, log=log)
+        else:
+            s, table = calibrate_amplitude(params, n_app, app_box, 0.2, seeds=VALIDATION_SEEDS, scales=CAL_SCALES,
+                                           log=log)
         params = scaled_output(params, s)
         res["amplitude"], res["calibration"], res["calibration_s"] = s, table, time.time() - t0
-        log(f"output amplitude {s:.2f} from the training boxes' 2x spectra ({res['calibration_s']:.1f} s)")
+        res["calibration_on"] = calibrate
+        log(f"output amplitude {s:.2f} chosen on the {calibrate} runs ({res['calibration_s']:.1f} s)")
     # application
     tau0, tau1 = tau_of_a(app_box, 0.02), tau_of_a(app_box, 0.5)
     steps = 100
@@ -307,9 +329,12 @@ def summary_md(res: dict, command: str) -> str:
              f"Held-out particle force error (units of rms|grad phi|^2): plain 1x {res['heldout_plain']:.3e}, "
              f"with closure {res['heldout_closure']:.3e}."]
     if "amplitude" in res:
-        lines.append(f"Output amplitude chosen on 4 training boxes: s = {res['amplitude']:.2f} "
-                     f"({res['calibration_s']:.1f} s); max deviation per s: "
-                     + ", ".join(f"{float(k):.1f}: {v:.4f}" for k, v in res["calibration"].items()) + ".")
+        where = ("two other realizations of the application (seeds 7 and 8; the application is seed 3)"
+                 if res.get("calibration_on", "train") == "validation" else "4 training boxes")
+        lines.append(f"Output amplitude chosen on {where}: s = {res['amplitude']:.3f} "
+                     f"({res['calibration_s']:.1f} s; per realization one 2x run and {len(res['calibration'])} 1x runs); "
+                     f"max deviation per s there: "
+                     + ", ".join(f"{float(k):.3f}: {v:.4f}" for k, v in res["calibration"].items()) + ".")
     lines += ["", "| run | wall time, 100 steps | max abs(P/P_2x - 1), k <= k_Ny/2 |", "|---|---|---|",
               f"| plain 512^3 mesh | {res['plain_1x_wall_s']:.1f} s | {res['plain_1x_maxdev']:.4f} |",
               f"| 512^3 mesh + closure | {res['closure_1x_wall_s']:.1f} s | {res['closure_1x_maxdev']:.4f} |",
@@ -334,8 +359,9 @@ if __name__ == "__main__":
     ap.add_argument("--boxes", type=int, default=64)
     ap.add_argument("--iters", type=int, default=12000)
     ap.add_argument("--no-augment", action="store_true")
-    ap.add_argument("--calibrate", action="store_true",
-                    help="scale the output by the amplitude that best matches the training boxes' 2x spectra")
+    ap.add_argument("--calibrate", choices=("validation", "train", "none"), default="validation",
+                    help="choose the output amplitude on another realization of the application (default), on "
+                         "training boxes, or keep the trained output")
     ap.add_argument("--out", default="gpurun_out/closure_experiment.json")
     ap.add_argument("--summarize", metavar="RESULT_JSON", help="print the markdown summary of a stored result")
     ap.add_argument("--command", default="python -u -m paper_2607_17929_amd.closure --out gpurun_out/closure_experiment.json")
