@@ -338,12 +338,15 @@ void launch_deposit(const Particles<T>& p, const uint32_t* cell_start, int n, in
 // and takes its rank inside its new cell (the sort recomputes the cell from
 // the stored position).
 // ---------------------------------------------------------------------------
-// Blocks are TX x 4 x 8 cells with TX = 32 (16 on a 16^3 mesh): rows of 32 cells keep the
-// row segments of the 4-byte particle arrays at whole 128-byte lines more often, and the field
-// tile is 2.6 values per cell of the block.
-constexpr int KD_TY = 4, KD_TZ = 8, KD_NT = 512;
-template <int TX> struct KdTile {
-  static constexpr int GX = TX + 3, GY = KD_TY + 3, GZ = KD_TZ + 3, G = GX * GY * GZ;
+// Blocks are TX x TY x TZ cells with TX = 32 (16 on a 16^3 mesh): rows of 32 cells keep the
+// row segments of the 4-byte particle arrays at whole 128-byte lines more often.  FP32: 32x4x8
+// cells and 512 threads (the field tile is 2.6 values per cell of the block).  FP64: 32x2x4 cells
+// and 256 threads: its 152 VGPRs allow 12 waves per CU, three such workgroups (measured at 512^3:
+// 8.5 ms against 9.6 ms for 32x4x8 with 512 threads, whose 108 KB tile holds one per CU).
+template <typename T> struct KdShape { static constexpr int TY = 4, TZ = 8, NT = 512; };
+template <> struct KdShape<double> { static constexpr int TY = 2, TZ = 4, NT = 256; };
+template <typename T, int TX> struct KdTile {
+  static constexpr int GX = TX + 3, GY = KdShape<T>::TY + 3, GZ = KdShape<T>::TZ + 3, G = GX * GY * GZ;
 };
 
 template <typename T, int GX, int GY>
@@ -398,12 +401,14 @@ __device__ __forceinline__ uint32_t rank_in_cell(uint32_t* cnt, uint32_t k) {
 }
 
 template <typename T, int MODE, int TX>
-__global__ __launch_bounds__(KD_NT) void kick_drift_kernel(Particles<T> p, const uint32_t* __restrict__ cell_start, int n,
-                                                           GatherArgs<T> ga, uint32_t* rank, uint32_t* cnt,
-                                                           int* err) {
+__global__ __launch_bounds__(KdShape<T>::NT) void kick_drift_kernel(Particles<T> p,
+                                                                    const uint32_t* __restrict__ cell_start, int n,
+                                                                    GatherArgs<T> ga, uint32_t* rank, uint32_t* cnt,
+                                                                    int* err) {
+  constexpr int KD_TY = KdShape<T>::TY, KD_TZ = KdShape<T>::TZ, KD_NT = KdShape<T>::NT;
   constexpr int NF = MODE == MODE_FULL ? 5 : (MODE == MODE_SCALAR ? 2 : 1);
   constexpr int NR = KD_TY * KD_TZ;                   // particle rows of the block
-  constexpr int KD_GX = KdTile<TX>::GX, KD_GY = KdTile<TX>::GY, KD_G = KdTile<TX>::G;
+  constexpr int KD_GX = KdTile<T, TX>::GX, KD_GY = KdTile<T, TX>::GY, KD_G = KdTile<T, TX>::G;
   constexpr int NTL = (KD_G + KD_NT - 1) / KD_NT;     // tile entries per thread and field
   static_assert(NR <= 64, "row scan in one wave");
   __shared__ T tile[NF][KD_G];
@@ -558,7 +563,8 @@ __global__ __launch_bounds__(KD_NT) void kick_drift_kernel(Particles<T> p, const
 template <typename T, int TX>
 static void launch_kick_drift_tx(const Particles<T>& p, int n, const uint32_t* cell_start, const GatherArgs<T>& g,
                                  uint32_t* rank, uint32_t* cnt, int* err, hipStream_t st) {
-  dim3 grid(n / TX, n / KD_TY, n / KD_TZ);
+  constexpr int KD_NT = KdShape<T>::NT;
+  dim3 grid(n / TX, n / KdShape<T>::TY, n / KdShape<T>::TZ);
   if (g.mode == MODE_NEWTONIAN)
     hipLaunchKernelGGL((kick_drift_kernel<T, MODE_NEWTONIAN, TX>), grid, dim3(KD_NT), 0, st, p, cell_start, n, g, rank,
                        cnt, err);
