@@ -243,3 +243,25 @@ def test_full_parabolic_b_route_c2_shape_small():
     for k, v in worst.items():
         assert v < FIELD_TOL["fp32"], (k, v)
     assert dxmax < POS_TOL["fp32"]
+
+
+@pytest.mark.parametrize("case", ["one_particle", "one_cell"])
+def test_degenerate_inputs_full_steps(case):
+    """Whole FP64 full-physics steps on a 16^3 mesh for one particle, and for 1000 particles that all start
+    in one cell (one crowded row, every rank in one counter), against the oracle."""
+    _say(f"degenerate {case}")
+    r = np.random.default_rng(41)
+    n, box = 16, 160.0
+    if case == "one_particle":
+        pos = np.array([[0.3, 0.71, 0.999]])
+        u = np.array([[1e-3, -2e-3, 5e-4]])
+    else:
+        pos = (np.array([5.0, 9.0, 2.0]) + r.random((1000, 3))) / n
+        u = r.normal(0.0, 1e-3, (1000, 3))
+    tau0 = opm.Background(box).tau(0.05)
+    worst, dxmax, urel, *_ = _run_both(n, box, "full", "fp64", pos, u, tau0, [0.02 * tau0] * 3, check_every=True)
+    _say(worst, dxmax, urel)
+    for k, v in worst.items():
+        assert v < FIELD_TOL["fp64"], (k, v)
+    assert dxmax < POS_TOL["fp64"]
+    assert urel < 1e-10
