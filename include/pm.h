@@ -184,7 +184,18 @@ pm_status pm_get_particles(pm_ctx* ctx, double* pos, void* u, uint32_t* ids, int
 /* The second species in identifier order (as pm_get_particles). */
 pm_status pm_get_particles_2(pm_ctx* ctx, double* pos, void* u, uint32_t* ids, int dst_on_device);
 
-/* Current conformal time, scale factor and number of completed steps. */
+/* Conservation diagnostics in FP64 (a per-step log for the caller; synchronises):
+ * out[0] = sum over particles of e = sqrt(a^2 + u^2) at the last pm_deposit (the
+ *          homogeneous mode's energy sum; species 2 weighted by m_2/m_1),
+ * out[1] = mean phi of the last pm_solve_metric (the FP64 homogeneous mode),
+ * out[2..4] = total momentum per unit mass of species 1, sum of u_i over the
+ *          particles as they are now (species 2 weighted by m_2/m_1).
+ * out[0] and out[1] are 0 before the first deposit / solve and with Newtonian
+ * physics (which solves without the FP64 homogeneous mode).
+ * n: entries of out to write (1 .. 5). */
+pm_status pm_diagnostics(pm_ctx* ctx, double* out, int n);
+
+/* Current conformal time, scale factor and number of completed steps. *//* Current conformal time, scale factor and number of completed steps. */
 pm_status pm_get_time(pm_ctx* ctx, double* tau, double* a, int64_t* steps);
 
 /* Background of a configuration (host only): a(tau) and H_conf(tau) = d ln a / d tau. */

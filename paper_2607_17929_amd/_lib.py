@@ -29,7 +29,7 @@ EXPORTS = (
     "pm_background", "pm_tau_of_a", "pm_get_timings", "pm_sync", "pm_debug_fft", "pm_status_string",
     "pm_last_error", "pm_gather_grad_phi", "pm_power_spectrum", "pm_closure_set_params", "pm_closure_enable", "pm_closure_forward",
     "pm_closure_gather", "pm_closure_backward", "pm_closure_adam", "pm_closure_scale", "pm_get_state", "pm_set_state",
-    "pm_init_particles_2", "pm_get_particles_2",
+    "pm_init_particles_2", "pm_get_particles_2", "pm_diagnostics",
 )
 
 
@@ -77,6 +77,7 @@ def load():
         "pm_set_field": [vp, C.c_int, vp, C.c_int],
         "pm_get_particles": [vp, vp, vp, vp, C.c_int],
         "pm_init_particles_2": [vp, vp, vp, vp, C.c_int64, C.c_int],
+        "pm_diagnostics": [vp, C.POINTER(C.c_double), C.c_int],
         "pm_get_particles_2": [vp, vp, vp, vp, C.c_int],
         "pm_get_time": [vp, C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(C.c_int64)],
         "pm_background": [cfgp, C.c_double, C.POINTER(C.c_double), C.POINTER(C.c_double)],

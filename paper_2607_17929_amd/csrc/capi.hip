@@ -402,9 +402,10 @@ pm_status do_init(pm_ctx* c, const double* pos, const void* u, const uint32_t* i
     if (ids) hipMemcpyAsync(si, ids, np * sizeof(uint32_t), hipMemcpyHostToDevice, c->st);
     dpos = sp; du = su; dids = ids ? si : nullptr;
   }
-  // clear counts, error flag, fields and tensor state
+  // clear counts, error flag, FP64 scalars, fields and tensor state
   c->zero(L.cnt, c->n3 * 4);
   c->zero(L.err, 64);
+  c->zero(L.scal, 8 * 8);
   for (int i = 0; i < 3; ++i) c->zero(L.phi[i], c->n3 * c->rs);
   if (L.chi) c->zero(L.chi, c->n3 * c->rs);
   for (int i = 0; i < 3; ++i)
@@ -776,6 +777,43 @@ pm_status pm_get_particles_2(pm_ctx* c, double* pos, void* u, uint32_t* ids, int
   pm_status s = c->hip_check("get_particles_2");
   if (s != PM_OK) return s;
   return dst_on_device ? PM_OK : read_sticky(c);
+}
+
+pm_status pm_diagnostics(pm_ctx* c, double* out, int n) {
+  if (!c || !out || n < 1) return PM_EINVAL;
+  if (!c->have_particles || (c->np2 > 0 && !c->have_particles2)) return c->fail(PM_ESTATE, "no particles");
+  if (c->sticky) return (pm_status)c->sticky;
+  double* sc = c->at<double>(c->L.scal);
+  // total momentum per unit mass of species 1: FP64 sums of the SoA momenta (scalars 3..5 for species 1,
+  // then 3..5 again for species 2 after species 1's were read)
+  double mom[3] = {0, 0, 0};
+  for (int s = 0; s < (c->np2 > 0 ? 2 : 1); ++s) {
+    const double w = s == 0 ? 1.0 : c->weight2();
+    for (int d = 0; d < 3; ++d) {
+      if (c->cfg.precision == PM_FP64) {
+        const Particles<double> p = s == 0 ? c->parts<double>(c->cur) : c->parts2<double>(c->cur2);
+        const double* u = d == 0 ? p.ux : (d == 1 ? p.uy : p.uz);
+        launch_sum_f64(u, s == 0 ? c->np : c->np2, sc + 3 + d, c->st);
+      } else {
+        const Particles<float> p = s == 0 ? c->parts<float>(c->cur) : c->parts2<float>(c->cur2);
+        const float* u = d == 0 ? p.ux : (d == 1 ? p.uy : p.uz);
+        launch_sum_as_f64(u, s == 0 ? c->np : c->np2, sc + 3 + d, c->st);
+      }
+    }
+    double h[6];
+    if (hipMemcpyAsync(h, sc, 6 * sizeof(double), hipMemcpyDeviceToHost, c->st) != hipSuccess ||
+        hipStreamSynchronize(c->st) != hipSuccess)
+      return c->fail(PM_EHIP, "reading the diagnostics failed");
+    for (int d = 0; d < 3; ++d) mom[d] += w * h[3 + d];
+    if (s == 0) {
+      const double v[5] = {h[2], h[1], 0, 0, 0};
+      for (int i = 0; i < n && i < 2; ++i) out[i] = v[i];
+    }
+  }
+  for (int i = 2; i < n && i < 5; ++i) out[i] = mom[i - 2];
+  pm_status st = c->hip_check("diagnostics");
+  if (st != PM_OK) return st;
+  return read_sticky(c);
 }
 
 pm_status pm_get_time(pm_ctx* c, double* tau, double* a, int64_t* steps) {

@@ -116,8 +116,8 @@ __device__ __forceinline__ void wave_row_offsets(uint32_t c, uint32_t* off) {
 
 template <typename T, int NC, bool REL>
 __global__ __launch_bounds__(DEP_NT, DEP_MIN_WAVES) void deposit_kernel(Particles<T> p, const uint32_t* __restrict__ cell_start, int n,
-                                                         T a, T w, double wd, int accumulate, T* __restrict__ dep,
-                                                         double* __restrict__ esum) {
+                                                         T a, double a64, T w, double wd, int accumulate,
+                                                         T* __restrict__ dep, double* __restrict__ esum) {
   constexpr int CAP = dep_capacity<T>();
   constexpr int TX = DEP_TX, TY = DEP_TY, CX = DEP_CX, ROWS = DEP_ROWS, GW = TX + 3;
   constexpr int NQ = (ROWS * GW + DEP_NT - 1) / DEP_NT;  // cell_start reads per thread
@@ -179,7 +179,7 @@ __global__ __launch_bounds__(DEP_NT, DEP_MIN_WAVES) void deposit_kernel(Particle
   for (int k = 0; k < DEP_VPT; ++k)
 #pragma unroll
     for (int c = 0; c < NC; ++c) acc[k][c] = (T)0;
-  const double ad = (double)a;
+  const double ad = a64;  // the FP64 energy sum takes the scale factor in FP64
   double e_own = 0.0;
   for (uint32_t c0 = 0; c0 < total; c0 += CAP) {
     const uint32_t c1 = min(total, c0 + (uint32_t)CAP);
@@ -315,15 +315,15 @@ void launch_deposit(const Particles<T>& p, const uint32_t* cell_start, int n, in
   dim3 grid(n / DEP_TX, n / DEP_TY, n / DEP_TZ);  // n >= 16
   const int acc = accumulate ? 1 : 0;
   if (ncomp == 1) {
-    hipLaunchKernelGGL((deposit_kernel<T, 1, false>), grid, dim3(DEP_NT), 0, st, p, cell_start, n, (T)a, (T)weight,
+    hipLaunchKernelGGL((deposit_kernel<T, 1, false>), grid, dim3(DEP_NT), 0, st, p, cell_start, n, (T)a, a, (T)weight,
                        weight, acc, dep, (double*)nullptr);
     return;
   }
   if (relativistic)
-    hipLaunchKernelGGL((deposit_kernel<T, 10, true>), grid, dim3(DEP_NT), 0, st, p, cell_start, n, (T)a, (T)weight,
+    hipLaunchKernelGGL((deposit_kernel<T, 10, true>), grid, dim3(DEP_NT), 0, st, p, cell_start, n, (T)a, a, (T)weight,
                        weight, acc, dep, esum_part);
   else
-    hipLaunchKernelGGL((deposit_kernel<T, 10, false>), grid, dim3(DEP_NT), 0, st, p, cell_start, n, (T)a, (T)weight,
+    hipLaunchKernelGGL((deposit_kernel<T, 10, false>), grid, dim3(DEP_NT), 0, st, p, cell_start, n, (T)a, a, (T)weight,
                        weight, acc, dep, esum_part);
 }
 

@@ -190,6 +190,12 @@ class PMContext:
         self._chk(self.lib.pm_get_particles(self.ctx, pos.ctypes.data, u.ctypes.data, None, 0), "pm_get_particles")
         return pos, u
 
+    def diagnostics(self) -> dict:
+        """pm_diagnostics: FP64 energy sum of the last deposit, mean phi of the last solve, total momentum."""
+        out = (C.c_double * 5)()
+        self._chk(self.lib.pm_diagnostics(self.ctx, out, 5), "pm_diagnostics")
+        return {"energy_sum": out[0], "phi_mean": out[1], "momentum": (out[2], out[3], out[4])}
+
     def time(self):
         tau, a, steps = C.c_double(), C.c_double(), C.c_int64()
         self._chk(self.lib.pm_get_time(self.ctx, C.byref(tau), C.byref(a), C.byref(steps)), "pm_get_time")
