@@ -241,7 +241,7 @@ def main():
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+        print("bench.py runs on one GPU only: this library has no multi-GPU path "
               "(the PM step is measured on a single MI355X); use --gpus 1", file=sys.stderr)
         sys.exit(2)
 

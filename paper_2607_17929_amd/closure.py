@@ -323,7 +323,7 @@ def experiment(n_app: int = 512, n_train_p: int = 128, train_box: float = 512.0,
 def summary_md(res: dict, command: str) -> str:
     """Markdown summary of an experiment result (the committed profile of the closure experiment)."""
     lines = ["# Learned closure experiment: 512^3 particles, 512^3 mesh + closure vs plain 1024^3 mesh", "",
-             "Command (repository root, GPU box):", "", f"    {command}", "",
+             "Command (repository root, on the MI355X machine):", "", f"    {command}", "",
              f"Training: {res.get('iters')} Adam iterations (cosine decay), cube-symmetry augmentation "
              f"{'on' if res.get('augment') else 'off'}; pairs {res['pairs_s']:.1f} s, training {res['train_s']:.1f} s.",
              f"Held-out particle force error (units of rms|grad phi|^2): plain 1x {res['heldout_plain']:.3e}, "

@@ -136,7 +136,7 @@ def traffic(fetch_csv: str, write_csv: str, probe_bytes: int, steps: int, n: int
 def traffic_md(res: dict, command_fetch: str, command_write: str) -> str:
     n = res["n"]
     lines = [f"# HBM traffic per launch: PM step, {n}^3 clustered workload", "",
-             "Commands (from the repository root on the GPU box):", "",
+             "Commands (from the repository root on the MI355X machine):", "",
              f"    {command_fetch}", f"    {command_write}", "",
              f"Calibration: the copy probe moves {res['probe_bytes']} bytes; FETCH_SIZE reads "
              f"{res['fetch_probe_kib']:.1f} KiB and WRITE_SIZE {res['write_probe_kib']:.1f} KiB for it, so read "
