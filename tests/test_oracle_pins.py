@@ -5,6 +5,7 @@ invariant, a brute-force evaluation or a special case that reduces to a
 textbook result.
 """
 import math
+import os
 
 import numpy as np
 import pytest
@@ -670,3 +671,58 @@ def test_p19_hot_species_raises_the_homogeneous_mode_by_its_kinetic_energy():
     sim0.deposit()
     phi0, _, _, _ = sim0._solve_once(z, z, z, 0.0)
     assert abs(phi0.mean()) < 1e-14 * abs(expect) / f
+
+
+# --------------------------------------------------------------------------
+# Transform count of one step against the per-field count of Sec. 4.1
+# --------------------------------------------------------------------------
+
+def _golden_fft_counts():
+    rows = {}
+    with open(os.path.join(os.path.dirname(__file__), "golden", "fft_counts_per_step.txt")) as fh:
+        for line in fh:
+            line = line.split("#")[0].split()
+            if line:
+                rows[line[0]] = (int(line[1]), int(line[2]))
+    return rows
+
+
+def _counted_step(monkeypatch, physics, b_route):
+    """Second step of a small run (the first is the quasi-static start); returns the sequence of
+    3D transforms it made, 'F' forward and 'B' backward."""
+    pos, u = _rand_particles(200, seed=3, umax=0.01)
+    s = pm.OracleSim(n=16, box_mpch=320.0, physics=physics, pos=pos, u=u, tau=30.0, b_route=b_route)
+    s.step(0.3)
+    calls = []
+    fwd, inv = pm.fft3, pm.ifft3
+    monkeypatch.setattr(pm, "fft3", lambda f: (calls.append("F"), fwd(f))[1])
+    monkeypatch.setattr(pm, "ifft3", lambda fk, n: (calls.append("B"), inv(fk, n))[1])
+    s.step(0.3)
+    return "".join(calls)
+
+
+def test_fft_count_of_a_parabolic_b_step_matches_sec_4_1(monkeypatch):
+    g = _golden_fft_counts()
+    seq = _counted_step(monkeypatch, pm.FULL, "parabolic")
+    # phi: its source forward, phi back; chi: the six Sigma_ij forward, chi back; B: three back
+    expect = ("F" * g["phi"][0] + "B" * g["phi"][1] + "F" * g["chi"][0] + "B" * g["chi"][1]
+              + "F" * g["B"][0] + "B" * g["B"][1])
+    assert seq == expect
+    assert len(seq) == 12
+
+
+def test_fft_counts_of_the_other_routes():
+    """The same accounting for the other physics settings: B from the momentum constraint adds
+    the three forward transforms of S_i (15 in all); scalar physics drops B (9); Newtonian
+    gravity needs one transform each way (2)."""
+    mp = pytest.MonkeyPatch()
+    try:
+        assert _counted_step(mp, pm.FULL, "elliptic") == "FB" + "F" * 6 + "B" + "F" * 3 + "B" * 3
+    finally:
+        mp.undo()
+    for physics, want in ((pm.SCALAR, "FB" + "F" * 6 + "B"), (pm.NEWTONIAN, "FB")):
+        mp = pytest.MonkeyPatch()
+        try:
+            assert _counted_step(mp, physics, "elliptic") == want
+        finally:
+            mp.undo()
