@@ -20,9 +20,11 @@ design notes of the repository):
     differences for gradients; projectors use kt_d;
   * forward FFT unnormalised, inverse scaled by 1/n^3 (numpy's convention).
 
-Parity unpinned: the quadratic gradient products in the trace-free source and
-the lagged non-linear remainder of the Hamiltonian constraint are pinned only
-through fixed-point and special-case tests, not by closed forms.
+Pins: the quadratic gradient products in the trace-free source and the gradient
+term of the Hamiltonian remainder are checked against an exact solution of general
+relativity (the exterior Schwarzschild metric in isotropic coordinates); the
+remainder's time-derivative and energy terms only through fixed-point tests of the
+non-linear constraint and the linear plane wave, not by a closed form.
 """
 from __future__ import annotations
 

@@ -726,3 +726,78 @@ def test_fft_counts_of_the_other_routes():
             assert _counted_step(mp, physics, "elliptic") == want
         finally:
             mp.undo()
+
+
+# --------------------------------------------------------------------------
+# P21: the exterior Schwarzschild metric in isotropic coordinates, an exact static vacuum
+# solution of general relativity, pins the quadratic gradient terms of the scalar sources
+# --------------------------------------------------------------------------
+
+def _schwarzschild_isotropic(n_pts=400, seed=21, mass=1.0):
+    """phi, chi = phi - psi and their derivatives at random points 2M <= r <= 40M.
+
+    Isotropic form: g_tt = -((1 - M/2r) / (1 + M/2r))^2, g_ij = (1 + M/2r)^4 delta_ij; with the
+    metric of Sec. 3.1 (g_00 = -a^2 e^{2 psi}, g_ij = a^2 e^{-2 phi} delta_ij at a = 1) that is
+    e^{2 psi} = -g_tt and e^{-2 phi} = g_xx.  Derivatives are taken symbolically.
+    """
+    import sympy as sp
+    X = sp.symbols("x y z", real=True)
+    r = sp.sqrt(X[0] ** 2 + X[1] ** 2 + X[2] ** 2)
+    q = mass / (2 * r)
+    g_tt = -((1 - q) / (1 + q)) ** 2
+    g_xx = (1 + q) ** 4
+    psi = sp.log(-g_tt) / 2
+    phi = -sp.log(g_xx) / 2
+    chi = phi - psi
+    f = lambda e: sp.lambdify(X, e, "numpy")
+    rng = np.random.default_rng(seed)
+    d = rng.normal(size=(n_pts, 3))
+    d /= np.linalg.norm(d, axis=1)[:, None]
+    pts = d * rng.uniform(2.0 * mass, 40.0 * mass, size=(n_pts, 1))
+    ev = lambda e: np.broadcast_to(np.asarray(f(e)(*pts.T), dtype=float), (n_pts,)).copy()
+    out = {"phi": ev(phi), "chi": ev(chi),
+           "gphi": [ev(sp.diff(phi, v)) for v in X], "gchi": [ev(sp.diff(chi, v)) for v in X],
+           "hchi": [[ev(sp.diff(chi, u, v)) for v in X] for u in X],
+           "lap_phi": ev(sum(sp.diff(phi, v, 2) for v in X))}
+    return out
+
+
+def _trace_free(t):
+    tr = (t[0] + t[3] + t[5]) / 3.0
+    return [t[s] - (tr if i == j else 0.0) for s, (i, j) in enumerate(pm.SYM)]
+
+
+def test_p21_schwarzschild_satisfies_the_trace_free_space_space_equation():
+    """In vacuum (K = 0) the trace-free part of Eq. 5 reads TF[d_i d_j chi] = TF[Sigma_ij] / 2 with
+    the oracle's Sigma; the exact metric satisfies it to rounding.  chi is second order in M/r, so
+    the equation checks the d phi d phi term at O((M/r)^2), its balance with the phi-chi cross term
+    at O((M/r)^3) and the d chi d chi term at O((M/r)^4)."""
+    s = _schwarzschild_isotropic()
+    zero = np.zeros_like(s["phi"])
+    sig = pm.traceless_source([zero] * 6, s["phi"], s["chi"], s["gphi"], s["gchi"])
+    sig_tf = _trace_free(sig)
+    hess_tf = _trace_free([s["hchi"][i][j] for (i, j) in pm.SYM])
+    scale = max(np.abs(x).max() for x in sig_tf)
+    assert scale > 1e-4
+    res = max(np.abs(2.0 * h - g).max() for h, g in zip(hess_tf, sig_tf))
+    assert res <= 1e-12 * scale, res / scale
+    # each quadratic term is needed: dropping any one of them leaves a residual far above rounding
+    gp, gc = s["gphi"], s["gchi"]
+    for drop in range(3):
+        terms = [[gp[i] * gp[j], -(gp[i] * gc[j] + gc[i] * gp[j]), gc[i] * gc[j]] for (i, j) in pm.SYM]
+        coef = [4.0, 4.0, 2.0]
+        alt = _trace_free([sum(coef[t] * terms[s_][t] for t in range(3) if t != drop) for s_ in range(6)])
+        bad = max(np.abs(2.0 * h - g).max() for h, g in zip(hess_tf, alt))
+        assert bad > 1e-6 * scale, drop
+
+
+def test_p21_schwarzschild_satisfies_the_hamiltonian_constraint():
+    """Static vacuum with H = 0 and Ebar = 0: the lagged phi equation becomes Delta phi = R with
+    R the oracle's non-linear remainder; for the exact metric (e^{-phi/2} = 1 + M/2r is harmonic)
+    it holds to rounding."""
+    s = _schwarzschild_isotropic()
+    zero = np.zeros_like(s["phi"])
+    R = pm.hamiltonian_remainder(zero, 0.0, 0.0, s["phi"], s["chi"], 0.0, s["gphi"])
+    scale = np.abs(s["lap_phi"]).max()
+    assert scale > 1e-4
+    assert np.abs(s["lap_phi"] - R).max() <= 1e-12 * scale
