@@ -402,6 +402,36 @@ def test_p12_zero_mode_time_derivative_root():
     assert abs(phi.mean() - exact) < 1e-12 * abs(exact)
 
 
+def test_p12_zero_mode_time_derivative_root_with_slip():
+    """The same with a homogeneous slip chi: the fixed point solves
+    (3/2)(H - phidot)^2 exp(-2 (2 phi - chi)) = E exp(phi), i.e. Eq. 4 over exp(2 phi) with psi = phi - chi."""
+    s = _uniform_sim(0.2)
+    a = s.bg.a(s.tau)
+    E = s.bg.kappa(4, 64) / a ** 2 * s.dep[0].mean()
+    hc = s.bg.hconf(s.tau)
+    eb = s.bg.ebar(a)
+    phi_prev, dt = -0.0021, 0.9
+    for chi0 in (0.004, -0.006):
+        def F(p):
+            pd = (p - phi_prev) / dt
+            return 1.5 * (hc - pd) ** 2 * math.exp(-2 * (2 * p - chi0)) - E * math.exp(p)
+
+        exact = brentq(F, -0.05, 0.05, xtol=1e-16)
+        z = np.zeros((4, 4, 4))
+        chi = z + chi0
+        phi = z + phi_prev
+        for _ in range(80):
+            pd = (phi - phi_prev) / dt
+            E_, J, K, gphi, gchi = s._sources(phi, chi, pd)
+            R = pm.hamiltonian_remainder(E_, eb, hc, phi, chi, pd, gphi)
+            rhs = (E_ - eb) - 3 * hc / dt * phi_prev - 3 * hc * hc * chi + R
+            phi = rhs / (-3 * hc / dt - 6 * hc * hc - eb)
+        assert abs(phi.mean() - exact) < 1e-12 * abs(exact), chi0
+        # the slip moves the root by far more than the tolerance
+        assert abs(exact - brentq(lambda p: 1.5 * (hc - (p - phi_prev) / dt) ** 2 * math.exp(-4 * p)
+                                  - E * math.exp(p), -0.05, 0.05, xtol=1e-16)) > 1e-4
+
+
 def test_p12_fixed_point_satisfies_full_constraint_pointwise():
     """A spatially varying fixed point satisfies Eq. 4 / exp(2 phi) in real space (7-point Laplacian)."""
     n = 8
