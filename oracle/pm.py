@@ -22,9 +22,10 @@ design notes of the repository):
 
 Pins: the quadratic gradient products in the trace-free source and the gradient
 term of the Hamiltonian remainder are checked against an exact solution of general
-relativity (the exterior Schwarzschild metric in isotropic coordinates); the
-remainder's time-derivative and energy terms only through fixed-point tests of the
-non-linear constraint and the linear plane wave, not by a closed form.
+relativity (the exterior Schwarzschild metric in isotropic coordinates); the whole
+remainder through fixed points of the lagged equation that must satisfy Eq. 4
+pointwise.  Parity unpinned: the -phidot d_i psi term and the exp(psi + 3 phi)
+factor of the momentum source (only B from the current alone is pinned).
 """
 from __future__ import annotations
 

@@ -454,6 +454,40 @@ def test_p12_fixed_point_satisfies_full_constraint_pointwise():
     assert np.max(np.abs(phi)) > 1e-4  # non-trivial field
 
 
+def test_p12_fixed_point_with_time_derivative_and_slip_pointwise():
+    """Spatially varying fields with a time derivative and a varying slip: iterating the lagged
+    equation (implicit operator, remainder R at the current iterate) to its fixed point satisfies
+    Eq. 4 / exp(2 phi) pointwise, with phidot = (phi - phi_prev) / dtau and the real-space Laplacian."""
+    n = 8
+    r = np.random.default_rng(22)
+    pos = lattice_positions(n) + 0.3 / n * (r.random((n ** 3, 3)) - 0.5)
+    u = 0.05 * (r.random((n ** 3, 3)) - 0.5)
+    s = pm.OracleSim(n=n, box_mpch=4000.0, physics=pm.SCALAR, pos=pos, u=u, tau=3.0)
+    s.deposit()
+    a, hc = s.bg.a(s.tau), s.bg.hconf(s.tau)
+    eb = s.bg.ebar(a)
+    x = (np.arange(n) + 0.0) / n
+    Z, Y, X = np.meshgrid(x, x, x, indexing="ij")
+    phi_prev = -1e-3 + 4e-4 * np.cos(2 * np.pi * X) * np.sin(2 * np.pi * Y)
+    chi = 3e-4 * np.cos(2 * np.pi * Z) + 1e-4
+    dt = 0.3
+    E = s.kappa() / a ** 2 * s.dep[0]
+    kt = pm.lattice_symbols(n)
+    denom = -(kt[0] ** 2 + kt[1] ** 2 + kt[2] ** 2) - 3 * hc / dt - 6 * hc * hc - eb
+    phi = phi_prev.copy()
+    for _ in range(100):
+        pd = (phi - phi_prev) / dt
+        R = pm.hamiltonian_remainder(E, eb, hc, phi, chi, pd, pm.grad(phi, n))
+        rhs = (E - eb) - 3 * hc / dt * phi_prev - 3 * hc * hc * chi + R
+        phi = pm.ifft3(pm.fft3(rhs) / denom, n)
+    pd = (phi - phi_prev) / dt
+    g = pm.grad(phi, n)
+    F = (pm.laplacian7(phi, n) - 0.5 * (g[0] ** 2 + g[1] ** 2 + g[2] ** 2)
+         + 1.5 * (hc - pd) ** 2 * np.exp(-2 * (2 * phi - chi)) - E * np.exp(phi))
+    assert np.max(np.abs(pd)) > 1e-4 * hc  # a real time derivative
+    assert np.max(np.abs(F)) < 1e-10 * np.max(np.abs(E - eb))
+
+
 # --------------------------------------------------------------------------
 # P13-P14: linear plane wave; Zel'dovich growth
 # --------------------------------------------------------------------------
