@@ -162,19 +162,19 @@ def plane_wave_particles(n: int, n_p: int, amp_disp: float, amp_mom: float, mode
 
 CONFIGS = {
     # 32^3 particles and mesh, FP64, scalar (phi, chi) physics, 10 steps a = 0.02 -> 0.05
-    "c1_32_scalar_fp64": dict(n=32, box=320.0, spectrum=spectrum_power_law_m2, rms_cells=0.2,
+    "zeldovich_32_scalar_fp64": dict(n=32, box=320.0, spectrum=spectrum_power_law_m2, rms_cells=0.2,
                               a_ref=0.02, a_init=0.02, a_end=0.05, steps=10, physics="scalar",
                               precision="fp64", seed=1),
     # 256^3 full scalar+vector+tensor, FP32 fields, start at a = 0.1, steps of 1% in tau
-    "c2_256_full": dict(n=256, box=1024.0, spectrum=spectrum_k_transfer, rms_cells=0.2,
+    "ktk_256_full": dict(n=256, box=1024.0, spectrum=spectrum_k_transfer, rms_cells=0.2,
                         a_ref=0.02, a_init=0.1, a_end=None, steps=None, physics="full",
                         precision="fp32", seed=2),
     # 512^3 clustered: k^-2 spectrum from a = 0.02, evolved to a = 0.5 in 100 uniform-tau steps
-    "c3_512_clustered": dict(n=512, box=2048.0, spectrum=spectrum_power_law_m2, rms_cells=0.2,
+    "clustered_512": dict(n=512, box=2048.0, spectrum=spectrum_power_law_m2, rms_cells=0.2,
                              a_ref=0.02, a_init=0.02, a_end=0.5, steps=100, physics="full",
                              precision="fp32", seed=3),
     # 1024^3 memory scale, Zel'dovich at a = 0.1
-    "c4_1024_memory": dict(n=1024, box=4096.0, spectrum=spectrum_power_law_m2, rms_cells=0.2,
+    "memory_1024": dict(n=1024, box=4096.0, spectrum=spectrum_power_law_m2, rms_cells=0.2,
                            a_ref=0.02, a_init=0.1, a_end=None, steps=None, physics="full",
                            precision="fp32", seed=4),
 }

@@ -24,9 +24,9 @@ def _say(msg):
 
 
 @pytest.mark.parametrize("precision", ["fp32", "fp64"])
-def test_c2_256_full_two_steps_against_oracle(precision):
+def test_ktk_256_full_two_steps_against_oracle(precision):
     from paper_2607_17929_amd import PMContext
-    pos, u, tau0, dtau = config_particles("c2_256_full")
+    pos, u, tau0, dtau = config_particles("ktk_256_full")
     n, box = 256, 1024.0
     ctx = PMContext(n, pos.shape[0], box, physics="full", precision=precision)
     u_in = u.astype(ctx.np_dtype)
@@ -34,7 +34,7 @@ def test_c2_256_full_two_steps_against_oracle(precision):
     sim = opm.OracleSim(n=n, box_mpch=box, physics="full", pos=pos, u=u_in.astype(np.float64), tau=tau0)
     del u
     for i in range(2):
-        _say(f"c2 256^3 {precision}: step {i + 1}")
+        _say(f"256^3 full physics {precision}: step {i + 1}")
         ctx.step(dtau)
         sim.step(dtau)
     gf, of = gpu_fields(ctx, "full"), oracle_fields(sim, "full")

@@ -22,7 +22,7 @@ torch = pytest.importorskip("torch")
 
 def _setup():
     from paper_2607_17929_amd import PMContext
-    pos, u, tau0, _ = config_particles("c1_32_scalar_fp64")
+    pos, u, tau0, _ = config_particles("zeldovich_32_scalar_fp64")
     n = 32
     ctx = PMContext(n, pos.shape[0], 320.0, physics="scalar", precision="fp64", closure=True)
     ctx.init_particles(pos, u, tau0)

@@ -23,7 +23,7 @@ def _ctx(n, n_p, box, physics, precision, n2=0, f2=0.0):
 
 
 def test_newtonian_total_momentum_is_conserved():
-    pos, u, tau0, dtau = config_particles("c1_32_scalar_fp64")
+    pos, u, tau0, dtau = config_particles("zeldovich_32_scalar_fp64")
     ctx = _ctx(32, pos.shape[0], 320.0, "newtonian", "fp64")
     ctx.init_particles(pos, u, tau0)
     p0 = np.array(ctx.diagnostics()["momentum"])
@@ -42,7 +42,7 @@ def test_newtonian_total_momentum_is_conserved():
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
 def test_energy_sum_and_two_species_momentum(precision):
-    pos, u, tau0, dtau = config_particles("c1_32_scalar_fp64")
+    pos, u, tau0, dtau = config_particles("zeldovich_32_scalar_fp64")
     r = np.random.default_rng(5)
     p2, u2 = r.random((999, 3)), r.normal(0.0, 0.05, (999, 3))
     f2 = 0.1

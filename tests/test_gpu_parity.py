@@ -64,12 +64,12 @@ def _random_particles(n_p, seed, umax):
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
-@pytest.mark.parametrize("case", ["c1", "random_ragged", "clustered", "single"])
+@pytest.mark.parametrize("case", ["zeldovich_32", "random_ragged", "clustered", "single"])
 def test_deposit_parity(case, precision):
     _say(f"deposit {case} {precision}")
     box = 320.0
-    if case == "c1":
-        pos, u, tau0, _ = config_particles("c1_32_scalar_fp64")
+    if case == "zeldovich_32":
+        pos, u, tau0, _ = config_particles("zeldovich_32_scalar_fp64")
         n = 32
     elif case == "random_ragged":
         n = 32
@@ -126,10 +126,10 @@ def _run_both(n, box, physics, precision, pos, u, tau0, dtaus, check_every=False
     return worst, periodic_max_dx(gp, op, n), rel_l2(gu, ou), ctx, sim
 
 
-def test_c1_fp64_scalar_ten_steps():
+def test_zeldovich_32_fp64_scalar_ten_steps():
     """32^3 particles and mesh, FP64, scalar physics, 10 steps a = 0.02 -> 0.05."""
-    _say("c1 fp64 scalar 10 steps")
-    pos, u, tau0, dtau = config_particles("c1_32_scalar_fp64")
+    _say("zeldovich 32^3 fp64 scalar 10 steps")
+    pos, u, tau0, dtau = config_particles("zeldovich_32_scalar_fp64")
     worst, dxmax, urel, ctx, sim = _run_both(32, 320.0, "scalar", "fp64", pos, u, tau0, [dtau] * 10, check_every=True)
     _say(worst, dxmax, urel)
     for k, v in worst.items():
@@ -143,7 +143,7 @@ def test_c1_fp64_scalar_ten_steps():
 @pytest.mark.parametrize("physics", ["newtonian", "full"])
 def test_fp64_step_parity_physics(physics):
     _say(f"fp64 {physics}")
-    pos, u, tau0, dtau = config_particles("c1_32_scalar_fp64")
+    pos, u, tau0, dtau = config_particles("zeldovich_32_scalar_fp64")
     worst, dxmax, urel, *_ = _run_both(32, 320.0, physics, "fp64", pos, u, tau0, [dtau] * 4, check_every=True)
     _say(worst, dxmax, urel)
     for k, v in worst.items():
@@ -153,9 +153,10 @@ def test_fp64_step_parity_physics(physics):
 
 @pytest.mark.parametrize("physics", ["scalar", "full"])
 def test_fp32_ten_steps(physics):
-    """FP32 fields/momenta, FP64 positions: 10 steps on C1 initial conditions."""
+    """FP32 fields/momenta, FP64 positions: 10 steps on the 32^3 workload's initial conditions (box 320 Mpc/h,
+    k^-2 spectrum, Zel'dovich start at a = 0.02)."""
     _say(f"fp32 {physics} 10 steps")
-    pos, u, tau0, dtau = config_particles("c1_32_scalar_fp64")
+    pos, u, tau0, dtau = config_particles("zeldovich_32_scalar_fp64")
     worst, dxmax, urel, *_ = _run_both(32, 320.0, physics, "fp32", pos, u, tau0, [dtau] * 10)
     _say(worst, dxmax, urel)
     for k, v in worst.items():
@@ -163,10 +164,11 @@ def test_fp32_ten_steps(physics):
     assert dxmax < POS_TOL["fp32"]
 
 
-def test_fp32_full_c2_shape_small():
-    """C2's spectrum and physics at a reduced 64^3 size, started at a = 0.1 (several tiles, all passes)."""
-    _say("fp32 c2-like 64^3")
-    pos, u, tau0, dtau = config_particles("c2_256_full", n=64)
+def test_fp32_full_ktk_spectrum_64():
+    """The 256^3 full-physics workload's k T(k) spectrum and physics at a reduced 64^3 size, started at
+    a = 0.1 (several tiles, all passes)."""
+    _say("fp32 k T(k) spectrum 64^3")
+    pos, u, tau0, dtau = config_particles("ktk_256_full", n=64)
     box = 1024.0 * 64 / 256
     worst, dxmax, urel, *_ = _run_both(64, box, "full", "fp32", pos, u, tau0, [dtau] * 10)
     _say(worst, dxmax, urel)
@@ -223,7 +225,7 @@ def test_nan_particles_are_reported():
 def test_full_parabolic_b_route(precision):
     """Full physics with B integrated from the vector part of the space-space equation (12 FFTs per step)."""
     _say(f"{precision} full, parabolic B")
-    pos, u, tau0, dtau = config_particles("c1_32_scalar_fp64")
+    pos, u, tau0, dtau = config_particles("zeldovich_32_scalar_fp64")
     steps = 4 if precision == "fp64" else 10
     worst, dxmax, urel, *_ = _run_both(32, 320.0, "full", precision, pos, u, tau0, [dtau] * steps,
                                        check_every=precision == "fp64", b_route="parabolic")
@@ -233,10 +235,11 @@ def test_full_parabolic_b_route(precision):
     assert dxmax < POS_TOL[precision]
 
 
-def test_full_parabolic_b_route_c2_shape_small():
-    """The parabolic route on C2's spectrum at 64^3 (several tiles), FP32, 10 steps."""
-    _say("fp32 c2-like 64^3 parabolic B")
-    pos, u, tau0, dtau = config_particles("c2_256_full", n=64)
+def test_full_parabolic_b_route_ktk_spectrum_64():
+    """The parabolic route on the k T(k) spectrum of the 256^3 full-physics workload at 64^3 (several
+    tiles), FP32, 10 steps."""
+    _say("fp32 k T(k) spectrum 64^3 parabolic B")
+    pos, u, tau0, dtau = config_particles("ktk_256_full", n=64)
     box = 1024.0 * 64 / 256
     worst, dxmax, urel, *_ = _run_both(64, box, "full", "fp32", pos, u, tau0, [dtau] * 10, b_route="parabolic")
     _say(worst, dxmax, urel)

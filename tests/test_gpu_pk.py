@@ -18,11 +18,11 @@ def _both(pos, m, box, precision, shot):
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
-@pytest.mark.parametrize("case", ["c1_zeldovich", "poisson_64"])
+@pytest.mark.parametrize("case", ["zeldovich_32", "poisson_64"])
 def test_power_spectrum_matches_oracle(precision, case):
     print("pk", precision, case, flush=True)
-    if case == "c1_zeldovich":
-        pos, _, _, _ = config_particles("c1_32_scalar_fp64")
+    if case == "zeldovich_32":
+        pos, _, _, _ = config_particles("zeldovich_32_scalar_fp64")
         m, box = 32, 320.0
     else:
         pos = np.random.default_rng(12).random((100003, 3))

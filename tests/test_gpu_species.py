@@ -1,6 +1,6 @@
 """A second particle species through the C ABI (pm_init_particles_2 / pm_get_particles_2).
 
-* Parity with the oracle: C1's Zel'dovich set as species 1 plus a hot species (|u| = 2a in random
+* Parity with the oracle: the 32^3 workload's Zel'dovich set (box 320 Mpc/h) as species 1 plus a hot species (|u| = 2a in random
   directions, speeds near 0.9 c, a ragged count of 5003 particles) carrying 10 % of the rest mass:
   FP64 full and scalar physics 4 steps at the FP64 bar; FP32 full physics with parabolic B 10 steps
   at the FP32 bar; fields and both species' positions.
@@ -43,7 +43,7 @@ def _hot_species(n2, a, seed=29):
                                                              ("fp32", "full", 10, "parabolic")])
 def test_hot_second_species_matches_oracle(precision, physics, steps, b_route):
     _say(f"two species {precision} {physics} {b_route}")
-    pos, u, tau0, dtau = config_particles("c1_32_scalar_fp64")
+    pos, u, tau0, dtau = config_particles("zeldovich_32_scalar_fp64")
     n, box, f2, n2 = 32, 320.0, 0.1, 5003
     bg = opm.Background(box)
     pos2, u2 = _hot_species(n2, bg.a(tau0 - 0.5 * dtau))
@@ -79,7 +79,7 @@ def test_hot_second_species_matches_oracle(precision, physics, steps, b_route):
 
 def test_split_species_reproduces_one_species():
     _say("two species: split invariance")
-    pos, u, tau0, dtau = config_particles("c1_32_scalar_fp64")
+    pos, u, tau0, dtau = config_particles("zeldovich_32_scalar_fp64")
     n, box = 32, 320.0
     one = _ctx(n, pos.shape[0], box, "full", "fp64")
     one.init_particles(pos, u, tau0)
@@ -102,7 +102,7 @@ def test_split_species_reproduces_one_species():
 def test_second_species_call_order_and_arguments():
     from paper_2607_17929_amd import PMError
     _say("two species: argument checks")
-    pos, u, tau0, dtau = config_particles("c1_32_scalar_fp64")
+    pos, u, tau0, dtau = config_particles("zeldovich_32_scalar_fp64")
     ctx = _ctx(32, pos.shape[0], 320.0, "scalar", "fp64", 100, 0.05)
     p2, u2 = _hot_species(100, 0.02)
     with pytest.raises(PMError) as e:
@@ -129,7 +129,7 @@ def test_second_species_call_order_and_arguments():
 
 def test_checkpoint_carries_the_second_species():
     _say("two species: checkpoint")
-    pos, u, tau0, dtau = config_particles("c1_32_scalar_fp64")
+    pos, u, tau0, dtau = config_particles("zeldovich_32_scalar_fp64")
     p2, u2 = _hot_species(777, 0.02)
     a = _ctx(32, pos.shape[0], 320.0, "scalar", "fp64", 777, 0.1)
     a.init_particles(pos, u, tau0)

@@ -49,7 +49,7 @@ CASES = [("fp64", "full", "parabolic"), ("fp64", "full", "elliptic"), ("fp64", "
 @pytest.mark.parametrize("precision,physics,b_route", CASES)
 def test_restart_continues_the_run(precision, physics, b_route):
     _say(f"restart {precision} {physics} {b_route}")
-    pos, u, tau0, dtau = config_particles("c1_32_scalar_fp64")
+    pos, u, tau0, dtau = config_particles("zeldovich_32_scalar_fp64")
     n, box = 32, 320.0
     a = _ctx(n, pos.shape[0], box, physics, precision, b_route)
     u_in = u.astype(a.np_dtype)
@@ -87,7 +87,7 @@ def test_restart_continues_the_run(precision, physics, b_route):
 
 def test_blob_round_trip_is_exact():
     _say("state blob round trip")
-    pos, u, tau0, dtau = config_particles("c1_32_scalar_fp64")
+    pos, u, tau0, dtau = config_particles("zeldovich_32_scalar_fp64")
     a = _ctx(32, pos.shape[0], 320.0, "full", "fp32", "parabolic")
     a.init_particles(pos, u.astype(np.float32), tau0)
     for _ in range(2):
@@ -110,7 +110,7 @@ def test_blob_round_trip_is_exact():
 
 def test_checkpoint_between_deposit_and_solve():
     _say("state between deposit and solve")
-    pos, u, tau0, dtau = config_particles("c1_32_scalar_fp64")
+    pos, u, tau0, dtau = config_particles("zeldovich_32_scalar_fp64")
     a = _ctx(32, pos.shape[0], 320.0, "full", "fp64")
     a.init_particles(pos, u, tau0)
     a.step(dtau)
@@ -134,7 +134,7 @@ def test_checkpoint_between_deposit_and_solve():
 def test_foreign_or_damaged_blobs_are_rejected():
     from paper_2607_17929_amd import PMError
     _say("state blob validation")
-    pos, u, tau0, dtau = config_particles("c1_32_scalar_fp64")
+    pos, u, tau0, dtau = config_particles("zeldovich_32_scalar_fp64")
     a = _ctx(32, pos.shape[0], 320.0, "scalar", "fp64")
     a.init_particles(pos, u, tau0)
     a.step(dtau)
@@ -162,7 +162,7 @@ def test_foreign_or_damaged_blobs_are_rejected():
 def test_restore_clears_a_sticky_device_error():
     from paper_2607_17929_amd import PMError
     _say("state restore after a device error")
-    pos, u, tau0, dtau = config_particles("c1_32_scalar_fp64")
+    pos, u, tau0, dtau = config_particles("zeldovich_32_scalar_fp64")
     a = _ctx(32, pos.shape[0], 320.0, "scalar", "fp64")
     a.init_particles(pos, u, tau0)
     for _ in range(2):

@@ -674,7 +674,7 @@ def _two_species_fields(sim):
 def test_p19_splitting_one_species_into_two_changes_nothing():
     """Half of the particles as species 2 with half of the mass (equal particle masses): the same run."""
     from synth import config_particles
-    pos, u, tau0, dtau = config_particles("c1_32_scalar_fp64", n=16)
+    pos, u, tau0, dtau = config_particles("zeldovich_32_scalar_fp64", n=16)
     one = pm.OracleSim(n=16, box_mpch=160.0, physics=pm.FULL, pos=pos, u=u, tau=tau0)
     two = pm.OracleSim(n=16, box_mpch=160.0, physics=pm.FULL, pos=pos[0::2], u=u[0::2], tau=tau0,
                        pos2=pos[1::2], u2=u[1::2], mass_fraction2=0.5)
@@ -695,7 +695,7 @@ def test_p19_copy_as_second_species_is_a_test_population(f):
     same total (m_1 N (1 + m_2/m_1) is the whole mass either way), so the fields equal those of
     species 1 alone, and the copy follows the same trajectories."""
     from synth import config_particles
-    pos, u, tau0, dtau = config_particles("c1_32_scalar_fp64", n=16)
+    pos, u, tau0, dtau = config_particles("zeldovich_32_scalar_fp64", n=16)
     one = pm.OracleSim(n=16, box_mpch=160.0, physics=pm.FULL, pos=pos, u=u, tau=tau0)
     two = pm.OracleSim(n=16, box_mpch=160.0, physics=pm.FULL, pos=pos, u=u, tau=tau0,
                        pos2=pos.copy(), u2=u.copy(), mass_fraction2=f)
