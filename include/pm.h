@@ -139,7 +139,10 @@ pm_status pm_destroy(pm_ctx* ctx);
 /* Load particles and reset the time-stepping state.
  * pos: [n][3] doubles (x, y, z), wrapped into [0, 1) on the device.
  * u:   [n][3] momenta per unit mass in the context precision (float or double).
- * ids: [n] identifiers forming a permutation of 0..n-1, or NULL for 0..n-1.
+ * ids: [n] identifiers forming a permutation of 0..n-1, or NULL for 0..n-1
+ *      (an identifier >= n is reported as PM_EINVAL by the next synchronising
+ *      call; repeated identifiers are not detected and leave the outputs in
+ *      identifier order undefined).
  * n must equal cfg.n_particles.  tau0 > 0 is the conformal time of pos (u is
  * at tau0 - dtau/2, the leapfrog's half step).  src_on_device: pointers are
  * device (1) or host (0) memory. */

@@ -221,6 +221,34 @@ def test_nan_particles_are_reported():
         ctx.sync()
 
 
+def test_ingest_wraps_positions_and_checks_identifiers():
+    """Positions outside [0, 1) are wrapped exactly as x - floor(x) with 1.0 mapped to 0.0 (bit for
+    bit against the oracle's wrap), and an identifier out of range is reported by the next
+    synchronising call until particles are loaded again."""
+    from paper_2607_17929_amd import PMError
+    _say("ingest: wrap and identifier checks")
+    r = np.random.default_rng(31)
+    n_p = 1000
+    pos = r.uniform(-2.0, 3.0, (n_p, 3))
+    pos[:8, 0] = [1.0, -1.0, 0.0, -0.0, 2.0, -1e-17, 1.0 - 2.0 ** -53, 3.0 - 2.0 ** -51]
+    u = r.standard_normal((n_p, 3)) * 1e-3
+    ctx = _ctx(16, n_p, 100.0, "scalar", "fp64")
+    ctx.init_particles(pos, u, 10.0)
+    gp, gu = ctx.get_particles()
+    want = opm.wrap_positions(pos.copy())
+    assert np.all((gp >= 0.0) & (gp < 1.0))
+    assert np.array_equal(gp.view(np.uint64), want.view(np.uint64))
+    assert np.array_equal(gu, u)
+    ids = np.arange(n_p, dtype=np.uint32)
+    ids[17] = n_p
+    ctx.init_particles(pos, u, 10.0, ids=ids)
+    with pytest.raises(PMError) as e:
+        ctx.sync()
+    assert e.value.status == -1
+    ctx.init_particles(pos, u, 10.0)
+    ctx.sync()
+
+
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
 def test_full_parabolic_b_route(precision):
     """Full physics with B integrated from the vector part of the space-space equation (12 FFTs per step)."""
