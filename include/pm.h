@@ -198,7 +198,7 @@ pm_status pm_get_particles_2(pm_ctx* ctx, double* pos, void* u, uint32_t* ids, i
  * n: entries of out to write (1 .. 5). */
 pm_status pm_diagnostics(pm_ctx* ctx, double* out, int n);
 
-/* Current conformal time, scale factor and number of completed steps. *//* Current conformal time, scale factor and number of completed steps. */
+/* Current conformal time, scale factor and number of completed steps. */
 pm_status pm_get_time(pm_ctx* ctx, double* tau, double* a, int64_t* steps);
 
 /* Background of a configuration (host only): a(tau) and H_conf(tau) = d ln a / d tau. */
