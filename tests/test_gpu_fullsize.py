@@ -164,6 +164,32 @@ def test_fp32_against_fp64_512_clustered(clustered):
         assert err < 1e-5, (k, err)
 
 
+def test_fp32_against_fp64_512_clustered_parabolic_b(clustered):
+    """The parabolic-B route at full size: the start step (quasi-static solve, kick, drift) and the
+    next solve, whose B is integrated in time and whose h takes its first Crank-Nicolson step; FP32
+    against FP64 per field (phi, chi, B, the six h_ij) on the same input."""
+    from paper_2607_17929_amd import PMContext
+    pos, u, tau, dtau = clustered
+    _say("fp32 vs fp64 at 512 clustered, parabolic B")
+    names = ("phi", "chi", "bx", "by", "bz", "hxx", "hxy", "hxz", "hyy", "hyz", "hzz")
+    res = {}
+    for precision in ("fp64", "fp32"):
+        ctx = PMContext(N, pos.shape[0], BOX, physics="full", precision=precision, b_route="parabolic")
+        ctx.init_particles(pos, u.astype(ctx.np_dtype), tau)
+        ctx.step(dtau)
+        ctx.deposit()
+        ctx.solve_metric(dtau)
+        res[precision] = {k: ctx.get_field(k).astype(np.float64) for k in names}
+        del ctx
+        torch.cuda.empty_cache()
+    errs = {k: rel_l2(res["fp32"][k], res["fp64"][k]) for k in names}
+    _say("  " + ", ".join(f"{k} {v:.2e}" for k, v in errs.items()))
+    for k in names:
+        assert np.max(np.abs(res["fp64"][k])) > 0, k
+    for k, err in errs.items():
+        assert err < 1e-5, (k, err)
+
+
 @pytest.mark.parametrize("physics", ["newtonian", "scalar"])
 def test_plane_wave_512_follows_linear_recursion(physics):
     _say(f"plane wave 512 {physics}")
