@@ -276,11 +276,17 @@ def test_full_parabolic_b_route_ktk_spectrum_64():
     assert dxmax < POS_TOL["fp32"]
 
 
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
 @pytest.mark.parametrize("case", ["one_particle", "one_cell"])
-def test_degenerate_inputs_full_steps(case):
-    """Whole FP64 full-physics steps on a 16^3 mesh for one particle, and for 1000 particles that all start
-    in one cell (one crowded row, every rank in one counter), against the oracle."""
-    _say(f"degenerate {case}")
+def test_degenerate_inputs_full_steps(case, precision):
+    """Whole full-physics steps on a 16^3 mesh for one particle, and for 1000 particles that all start
+    in one cell (one crowded row, every rank in one counter), against the oracle; both precisions at
+    their bars, except B of the FP32 path in the one-cell case: there the transverse part of the
+    momentum source is dominated by -phidot d_i psi, and phidot is the difference of two successive FP32
+    solutions (each within 4e-7 of the oracle) that differ by about 2 %, so B carries the FP32 error of
+    phi amplified by kappa = |phi| / |phi - phi_prev| (about 50); its bar is the FP32 bar times kappa
+    (measured 1-6e-5, varying with the in-cell order of the sums)."""
+    _say(f"degenerate {case} {precision}")
     r = np.random.default_rng(41)
     n, box = 16, 160.0
     if case == "one_particle":
@@ -290,9 +296,14 @@ def test_degenerate_inputs_full_steps(case):
         pos = (np.array([5.0, 9.0, 2.0]) + r.random((1000, 3))) / n
         u = r.normal(0.0, 1e-3, (1000, 3))
     tau0 = opm.Background(box).tau(0.05)
-    worst, dxmax, urel, *_ = _run_both(n, box, "full", "fp64", pos, u, tau0, [0.02 * tau0] * 3, check_every=True)
-    _say(worst, dxmax, urel)
+    worst, dxmax, urel, _, sim = _run_both(n, box, "full", precision, pos, u, tau0, [0.02 * tau0] * 3,
+                                           check_every=True)
+    kappa = np.linalg.norm(sim.phi) / np.linalg.norm(sim.phi - sim.phi_prev)
+    _say(worst, dxmax, urel, f"kappa {kappa:.1f}")
     for k, v in worst.items():
-        assert v < FIELD_TOL["fp64"], (k, v)
-    assert dxmax < POS_TOL["fp64"]
-    assert urel < 1e-10
+        tol = FIELD_TOL[precision]
+        if precision == "fp32" and case == "one_cell" and k in ("bx", "by", "bz"):
+            tol *= kappa
+        assert v < tol, (k, v)
+    assert dxmax < POS_TOL[precision]
+    assert urel < (1e-10 if precision == "fp64" else FIELD_TOL["fp32"])
