@@ -9,6 +9,9 @@ properties that hold at any size.
 * Translation by whole cells moves the deposit by the same cells (FP64).
 * FP32 against FP64 on the same clustered input: the metric fields of the start-up solve
   (1e-5 rel-L2 per field; clustered states are compared per field, not as trajectories).
+* Gather + kick + drift: for 8192 sampled particles, the oracle's update (CIC gather of phi,
+  chi, B and their centred gradients, kick, drift, wrap) applied to the GPU's own fields and the
+  particles' state before the update, against the GPU's updated particles (both precisions).
 * A linear plane wave on the 512^3 lattice follows the scalar recursion of the discrete
   equations (Newtonian and relativistic scalar).
 
@@ -24,7 +27,7 @@ import pytest
 from oracle import pm as opm
 from synth import lattice_positions, plane_wave_particles, spectrum_power_law_m2, zeldovich_particles
 from synth.ics import eds_a_of_tau
-from tests.helpers import rel_l2
+from tests.helpers import periodic_max_dx, rel_l2
 from tests.test_oracle_pins import _linear_recursion, _project_wave
 
 pytestmark = pytest.mark.gpu
@@ -188,6 +191,41 @@ def test_fp32_against_fp64_512_clustered_parabolic_b(clustered):
         assert np.max(np.abs(res["fp64"][k])) > 0, k
     for k, err in errs.items():
         assert err < 1e-5, (k, err)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_kick_drift_512_sampled_particles(clustered, precision):
+    """The update kernel at full size in the bench's launch configuration, one particle at a time: the
+    oracle's gather, kick and drift on the GPU's fields (read back after the start-up solve) for
+    8192 sampled particles, against what the GPU made of them."""
+    pos, u, tau, dtau = clustered
+    _say(f"kick/drift 512 clustered {precision}, sampled particles")
+    ctx = _ctx(precision, pos.shape[0])
+    ctx.init_particles(pos, u.astype(ctx.np_dtype), tau)
+    ctx.deposit()
+    ctx.solve_metric(0.0)
+    fields = {k: ctx.get_field(k).astype(np.float64) for k in ("phi", "chi", "bx", "by", "bz")}
+    p0, u0 = ctx.get_particles()
+    ctx.update_particles(dtau)
+    p1, u1 = ctx.get_particles()
+    del ctx
+    torch.cuda.empty_cache()
+    r = np.random.default_rng(77)
+    sample = r.choice(pos.shape[0], 8192, replace=False)
+    sim = opm.OracleSim(n=N, box_mpch=BOX, physics=opm.FULL, pos=p0[sample], u=u0[sample].astype(np.float64),
+                        tau=tau)
+    sim.phi, sim.chi = fields["phi"], fields["chi"]
+    sim.B = [fields["bx"], fields["by"], fields["bz"]]
+    sim.update(dtau)
+    dx = periodic_max_dx(p1[sample], sim.pos, N)
+    du = rel_l2(u1[sample].astype(np.float64), sim.u)
+    moved = periodic_max_dx(p1[sample], p0[sample], N)
+    _say(f"  max |dx| {dx:.2e} cells, u rel-L2 {du:.2e}, largest move {moved:.2f} cells")
+    assert moved > 0.1
+    if precision == "fp64":
+        assert dx < 1e-9 and du < 1e-10
+    else:
+        assert dx < 1e-4 and du < 1e-5
 
 
 @pytest.mark.parametrize("physics", ["newtonian", "scalar"])
