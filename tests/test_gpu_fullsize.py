@@ -9,6 +9,8 @@ properties that hold at any size.
 * Translation by whole cells moves the deposit by the same cells (FP64).
 * FP32 against FP64 on the same clustered input: the metric fields of the start-up solve
   (1e-5 rel-L2 per field; clustered states are compared per field, not as trajectories).
+* Metric solve (FP64): the oracle's quasi-static start solve run on the GPU's own 512^3 deposit,
+  against the GPU's phi, chi and B element by element.
 * Gather + kick + drift: for 8192 sampled particles, the oracle's update (CIC gather of phi,
   chi, B and their centred gradients, kick, drift, wrap) applied to the GPU's own fields and the
   particles' state before the update, against the GPU's updated particles (both precisions).
@@ -191,6 +193,31 @@ def test_fp32_against_fp64_512_clustered_parabolic_b(clustered):
         assert np.max(np.abs(res["fp64"][k])) > 0, k
     for k, err in errs.items():
         assert err < 1e-5, (k, err)
+
+
+def test_solve_512_clustered_against_oracle(clustered):
+    """The Fourier-space solve stage at full size, element by element: the GPU's deposit of the
+    clustered input is read back and handed to the oracle's start-up solve (two predictor-corrector
+    passes: sources, 10 forward and 5 inverse transforms each); phi, chi and B against the GPU's at
+    the FP64 bar."""
+    pos, u, tau, dtau = clustered
+    _say("solve 512 clustered fp64 against the oracle")
+    ctx = _ctx("fp64", pos.shape[0])
+    ctx.init_particles(pos, u, tau)
+    ctx.deposit()
+    dep = np.stack([ctx.get_field(k) for k in DEP])
+    ctx.solve_metric(0.0)
+    gpu = {k: ctx.get_field(k) for k in ("phi", "chi", "bx", "by", "bz")}
+    del ctx
+    torch.cuda.empty_cache()
+    sim = opm.OracleSim(n=N, box_mpch=BOX, physics=opm.FULL, pos=pos, u=u, tau=tau)
+    sim.dep = dep
+    sim.solve(0.0)
+    ref = {"phi": sim.phi, "chi": sim.chi, "bx": sim.B[0], "by": sim.B[1], "bz": sim.B[2]}
+    errs = {k: rel_l2(gpu[k], ref[k]) for k in ref}
+    _say("  " + ", ".join(f"{k} {v:.2e}" for k, v in errs.items()))
+    for k, err in errs.items():
+        assert err < 1e-10, (k, err)
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
