@@ -58,3 +58,44 @@ def test_background_host_functions():
     # Einstein-de Sitter: H_conf = H0 / sqrt(a), H0 = box / (c / 100 km/s/Mpc)
     assert abs(h.value - (320.0 / 2997.92458) / math.sqrt(0.02)) < 1e-12
     assert lib.pm_background(C.byref(cfg), -1.0, C.byref(a), C.byref(h)) == L.PM_EINVAL
+
+
+def _header_constants():
+    src = open(os.path.join(ROOT, "include", "pm.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return {k: int(v) for k, v in re.findall(r"\b(PM_[A-Z0-9_]+)\s*=\s*(-?\d+)u?\b", src)}
+
+
+def test_header_constants_match_the_binding():
+    h = _header_constants()
+    for name in ("PM_OK", "PM_EINVAL", "PM_EWORKSPACE", "PM_EHIP", "PM_ENAN", "PM_ESTATE", "PM_ERANGE",
+                 "PM_EUNSUPPORTED", "PM_FP32", "PM_FP64", "PM_NEWTONIAN", "PM_SCALAR", "PM_FULL",
+                 "PM_FLAG_TIMINGS", "PM_FLAG_CLOSURE", "PM_FLAG_B_PARABOLIC", "PM_CLOSURE_NPARAM"):
+        assert h[name] == getattr(L, name), name
+    for name, fid in L.FIELDS.items():
+        assert h["PM_FIELD_" + name.upper()] == fid, name
+    assert h["PM_FIELD_COUNT"] == len(L.FIELDS)
+    for i, name in enumerate(L.STAGES):
+        assert h["PM_STAGE_" + name.upper()] == i, name
+    assert h["PM_NSTAGES"] == len(L.STAGES)
+
+
+def test_config_struct_layout_matches_c(tmp_path):
+    """The ctypes pm_config has the C struct's size and field offsets (compiled with the host compiler)."""
+    import shutil
+    import subprocess
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no host C compiler")
+    fields = [f[0] for f in L.PMConfig._fields_]
+    prog = tmp_path / "layout.c"
+    prog.write_text("#include <stddef.h>\n#include <stdio.h>\n#include \"pm.h\"\nint main(void) {\n"
+                    "  printf(\"%zu\\n\", sizeof(pm_config));\n"
+                    + "".join(f"  printf(\"%zu\\n\", offsetof(pm_config, {f}));\n" for f in fields)
+                    + "  return 0;\n}\n")
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-std=c99", "-I", os.path.join(ROOT, "include"), str(prog), "-o", str(exe)], check=True)
+    out = [int(x) for x in subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split()]
+    assert out[0] == C.sizeof(L.PMConfig)
+    for f, off in zip(fields, out[1:]):
+        assert getattr(L.PMConfig, f).offset == off, f
