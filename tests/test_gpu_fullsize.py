@@ -195,19 +195,27 @@ def test_fp32_against_fp64_512_clustered_parabolic_b(clustered):
         assert err < 1e-5, (k, err)
 
 
-def test_solve_512_clustered_against_oracle(clustered):
+def sim_energy(n_p, u, tau):
+    """FP64 sum over the particles of e = sqrt(a^2 + |u|^2) at tau."""
+    a = opm.Background(BOX).a(tau)
+    uu = u.astype(np.float64)
+    return float(np.sum(np.sqrt(a * a + np.sum(uu * uu, axis=1))))
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_solve_512_clustered_against_oracle(clustered, precision):
     """The Fourier-space solve stage at full size, element by element: the GPU's deposit of the
     clustered input is read back and handed to the oracle's start-up solve (two predictor-corrector
-    passes: sources, 10 forward and 5 inverse transforms each); phi, chi and B against the GPU's at
-    the FP64 bar."""
+    passes: sources, 10 forward and 5 inverse transforms each, in FP64); phi, chi and B against the
+    GPU's at the bar of the GPU path's precision."""
     pos, u, tau, dtau = clustered
-    _say("solve 512 clustered fp64 against the oracle")
-    ctx = _ctx("fp64", pos.shape[0])
-    ctx.init_particles(pos, u, tau)
+    _say(f"solve 512 clustered {precision} against the oracle")
+    ctx = _ctx(precision, pos.shape[0])
+    ctx.init_particles(pos, u.astype(ctx.np_dtype), tau)
     ctx.deposit()
-    dep = np.stack([ctx.get_field(k) for k in DEP])
+    dep = np.stack([ctx.get_field(k).astype(np.float64) for k in DEP])
     ctx.solve_metric(0.0)
-    gpu = {k: ctx.get_field(k) for k in ("phi", "chi", "bx", "by", "bz")}
+    gpu = {k: ctx.get_field(k).astype(np.float64) for k in ("phi", "chi", "bx", "by", "bz")}
     del ctx
     torch.cuda.empty_cache()
     sim = opm.OracleSim(n=N, box_mpch=BOX, physics=opm.FULL, pos=pos, u=u, tau=tau)
@@ -215,9 +223,15 @@ def test_solve_512_clustered_against_oracle(clustered):
     sim.solve(0.0)
     ref = {"phi": sim.phi, "chi": sim.chi, "bx": sim.B[0], "by": sim.B[1], "bz": sim.B[2]}
     errs = {k: rel_l2(gpu[k], ref[k]) for k in ref}
-    _say("  " + ", ".join(f"{k} {v:.2e}" for k, v in errs.items()))
+    # phi's homogeneous mode: the GPU takes it from the FP64 sum of the particle energies, the oracle
+    # (handed only the mesh) from the sum of the mesh values, which the FP32 deposit rounds
+    dphi_mean = (gpu["phi"].mean() - ref["phi"].mean()) / np.sqrt(np.mean(ref["phi"] ** 2))
+    varying = rel_l2(gpu["phi"] - gpu["phi"].mean(), ref["phi"] - ref["phi"].mean())
+    _say("  " + ", ".join(f"{k} {v:.2e}" for k, v in errs.items())
+         + f"; phi without its mean {varying:.2e}, mean difference / rms {dphi_mean:.2e}; n00 sum / particle "
+         f"energy sum - 1 {dep[0].sum() / sim_energy(pos.shape[0], u.astype(np.float32 if precision == 'fp32' else np.float64), tau) - 1:.2e}")
     for k, err in errs.items():
-        assert err < 1e-10, (k, err)
+        assert err < (1e-10 if precision == "fp64" else 1e-5), (k, err)
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
