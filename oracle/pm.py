@@ -6,8 +6,7 @@ use this module.  It follows the method of Adamek & Christiansen,
 numpy/scipy; it is deliberately plain (no blocking, no fusion) so that each
 line can be checked against the equations by eye.
 
-Conventions (readings of the paper where it is silent; all are listed in the
-design notes of the repository):
+Conventions (readings of the paper where it is silent):
   * box side L = 1, c = 1; mesh of n^3 vertices at x_v = v/n, periodic;
     arrays are indexed [z][y][x] with x fastest (the paper's fast index, Sec. 2);
   * Einstein-de Sitter background: a = (H0 tau / 2)^2, H_conf = 2/tau,

@@ -1,7 +1,7 @@
 """GPU parity of the learned closure's kernels against the FP64 oracle (with bfloat16 emulation),
 and a small training run that must beat the plain 1x force on held-out data.
 
-Tolerances (derived in the design notes): the forward output and the weight
+Tolerances: the forward output and the weight
 gradients are compared in relative L2; bfloat16 has a unit roundoff of 2^-9,
 and an occasional one-ulp difference in a rounded activation (FP32 versus FP64
 accumulation right at a rounding boundary) perturbs the output by about that
