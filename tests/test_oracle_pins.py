@@ -545,7 +545,7 @@ def test_p13_linear_plane_wave_matches_scalar_recursion(physics):
         assert abs(P - ref[it][1]) < 1e-5 * abs(ref[it][1]), (it, P, ref[it][1])
 
 
-def _growth_run(steps, n=32, mode=1):
+def _growth_run(steps, n=32, mode=1, physics=pm.NEWTONIAN):
     bg = pm.Background(320.0)
     tau0, tau1 = bg.tau(0.02), bg.tau(0.05)
     dtau = (tau1 - tau0) / steps
@@ -556,7 +556,7 @@ def _growth_run(steps, n=32, mode=1):
     P0 = bg.a(th) * s * U0 * (th / tau0) ** s / th
     # only the x-profile matters: use a thin lattice in y, z (n_p = n still, mesh n)
     pos, u = plane_wave_particles(n, n, U0, P0, mode=mode)
-    sim = pm.OracleSim(n=n, box_mpch=320.0, physics=pm.NEWTONIAN, pos=pos, u=u, tau=tau0)
+    sim = pm.OracleSim(n=n, box_mpch=320.0, physics=physics, pos=pos, u=u, tau=tau0)
     q = lattice_positions(n)
     for _ in range(steps):
         sim.step(dtau)
@@ -573,6 +573,24 @@ def test_p14_zeldovich_growth_second_order_convergence():
     assert errs[0] < 5e-3 * 2.5
     r1, r2 = errs[0] / errs[1], errs[1] / errs[2]
     assert 3.3 < r1 < 4.7 and 3.3 < r2 < 4.7, errs
+
+
+def test_p14_relativistic_growth_approaches_newtonian_inside_the_horizon():
+    """The relativistic scalar run of the same linear wave grows like the Newtonian one up to
+    corrections of relative size ~3 H^2 / kt^2 (the Newtonian limit holds well inside the horizon):
+    for modes 1, 2, 4 and 8 of the 320 Mpc/h box the growth ratio differs from 1 by less than
+    3 H(tau_0)^2 / kt^2 and the difference shrinks with every doubling of k."""
+    devs = []
+    bg = pm.Background(320.0)
+    h0 = bg.hconf(bg.tau(0.02))
+    for mode in (1, 2, 4, 8):
+        g_newt, _ = _growth_run(20, mode=mode)
+        g_rel, _ = _growth_run(20, mode=mode, physics=pm.SCALAR)
+        kt2 = (2 * 32 * math.sin(math.pi * mode / 32)) ** 2
+        dev = abs(g_rel / g_newt - 1.0)
+        assert dev < 3.0 * h0 * h0 / kt2, (mode, dev)
+        devs.append(dev)
+    assert all(b < a / 3 for a, b in zip(devs, devs[1:])), devs
 
 
 # --------------------------------------------------------------------------
