@@ -79,9 +79,9 @@ def test_p3_bruteforce_loop():
 # P4: FFT against a brute-force DFT
 # --------------------------------------------------------------------------
 
-def test_p4_fft_bruteforce_parseval_roundtrip():
-    n = 8
-    f = RNG.standard_normal((n, n, n))
+@pytest.mark.parametrize("n", [4, 8, 16])
+def test_p4_fft_bruteforce_parseval_roundtrip(n):
+    f = np.random.default_rng(100 + n).standard_normal((n, n, n))
     fk = pm.fft3(f)
     idx = np.arange(n)
     # brute force: sum over all n^3 points for every (kz, ky, kx) of the half spectrum
@@ -98,6 +98,26 @@ def test_p4_fft_bruteforce_parseval_roundtrip():
     w[0] = w[-1] = 1.0
     e_k = (np.abs(fk) ** 2 * w).sum() / n ** 3
     assert abs(e_k - (f ** 2).sum()) < 1e-12 * (f ** 2).sum()
+
+
+def test_p4_single_mode_lands_in_one_bin():
+    """A real cosine of lattice mode m transforms to exactly the bins +m and -m of the full
+    spectrum (in the half spectrum: one bin, or two when kx = 0 pairs them), each n^3 / 2."""
+    n = 8
+    idx = np.arange(n)
+    z, y, x = np.meshgrid(idx, idx, idx, indexing="ij")
+    for m in [(1, 0, 0), (0, 3, 0), (2, 1, 3), (0, 0, 4)]:
+        f = np.cos(2 * np.pi * (m[0] * x + m[1] * y + m[2] * z) / n)
+        fk = pm.fft3(f)
+        big = np.argwhere(np.abs(fk) > 1e-9 * n ** 3)
+        want = {((m[2]) % n, (m[1]) % n, m[0])} if m[0] > 0 else {((m[2]) % n, (m[1]) % n, 0),
+                                                                  ((-m[2]) % n, (-m[1]) % n, 0)}
+        if m[0] == n // 2:
+            want = {((m[2]) % n, (m[1]) % n, m[0]), ((-m[2]) % n, (-m[1]) % n, m[0])}
+        assert {tuple(b) for b in big} == want, (m, big)
+        val = n ** 3 / 2 if len(want) == 2 or m[0] not in (0, n // 2) else n ** 3
+        for b in want:
+            assert abs(fk[b] - val) < 1e-9 * n ** 3, (m, b, fk[b])
 
 
 # --------------------------------------------------------------------------
