@@ -99,3 +99,15 @@ def test_config_struct_layout_matches_c(tmp_path):
     assert out[0] == C.sizeof(L.PMConfig)
     for f, off in zip(fields, out[1:]):
         assert getattr(L.PMConfig, f).offset == off, f
+
+
+def test_missing_library_fails_loudly(monkeypatch, tmp_path):
+    """Without the built HIP library there is no fallback: loading it raises, and so does creating a
+    context (before any device work)."""
+    monkeypatch.setattr(L, "_lib", None)
+    monkeypatch.setattr(L, "LIB_PATH", str(tmp_path / "libgpm.so"))
+    with pytest.raises(ImportError):
+        L.load()
+    from paper_2607_17929_amd import PMContext
+    with pytest.raises(ImportError):
+        PMContext(16, 8, 100.0, physics="scalar", precision="fp64")
