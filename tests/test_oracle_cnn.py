@@ -77,3 +77,23 @@ def test_first_adam_step_moves_by_lr_times_sign():
     assert np.allclose(q - p, -1e-3 * np.sign(g), rtol=1e-6, atol=0)
     # the moments are the bias-uncorrected running averages
     assert np.allclose(m, 0.1 * g) and np.allclose(v, 0.001 * g * g)
+
+
+def test_bf16_rounding_matches_the_library_conversion():
+    """Against an independent implementation: torch's float32 -> bfloat16 conversion (round to
+    nearest, ties to even) on random values, exact ties, subnormals, infinities and signed zeros."""
+    import torch
+    r = np.random.default_rng(11)
+    v = np.concatenate([
+        r.standard_normal(20000).astype(np.float32) * np.float32(10.0) ** r.integers(-30, 30, 20000).astype(np.float32),
+        # exact ties: low 16 bits 0x8000 with both parities of the kept bit
+        (r.integers(0, 2 ** 31, 4000, dtype=np.uint64).astype(np.uint32) & np.uint32(0xFFFF0000)
+         | np.uint32(0x8000)).view(np.float32),
+        np.array([0.0, -0.0, np.inf, -np.inf, 1e-40, -3e-39, 3.4e38], dtype=np.float32),
+    ])
+    v = v[np.isfinite(v) | np.isinf(v)]
+    want = torch.from_numpy(v).to(torch.bfloat16).to(torch.float64).numpy()
+    got = cnn.bf16_round(v)
+    same = (got == want) | (np.isnan(got) & np.isnan(want))
+    assert same.all(), v[~same][:5]
+    assert np.array_equal(np.signbit(got), np.signbit(want))
