@@ -75,6 +75,26 @@ def test_p3_bruteforce_loop():
     assert np.max(np.abs(dep - ref)) <= 1e-15 * np.max(np.abs(ref)) * 10
 
 
+def test_p3_cic_interpolation_reproduces_trilinear_functions():
+    """CIC interpolation is exact for any function that is trilinear inside a cell: a field
+    f(x, y, z) = c0 + cx x + cy y + cz z + cxy x y + cxz x z + cyz y z + cxyz x y z sampled on the
+    vertices returns f at every particle whose cell does not cross the periodic seam."""
+    n = 8
+    r = np.random.default_rng(3)
+    c = r.standard_normal(8)
+    v = np.arange(n) / n
+    Z, Y, X = np.meshgrid(v, v, v, indexing="ij")
+
+    def f(x, y, z):
+        return (c[0] + c[1] * x + c[2] * y + c[3] * z + c[4] * x * y + c[5] * x * z + c[6] * y * z
+                + c[7] * x * y * z)
+
+    pos = r.uniform(0.0, (n - 1) / n, (500, 3))  # cells 0 .. n-2: no corner wraps
+    got = pm.interpolate([f(X, Y, Z)], pos, n)[0]
+    want = f(pos[:, 0], pos[:, 1], pos[:, 2])
+    assert np.max(np.abs(got - want)) < 1e-13 * np.max(np.abs(want))
+
+
 # --------------------------------------------------------------------------
 # P4: FFT against a brute-force DFT
 # --------------------------------------------------------------------------
