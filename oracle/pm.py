@@ -23,8 +23,9 @@ Pins: the quadratic gradient products in the trace-free source and the gradient
 term of the Hamiltonian remainder are checked against an exact solution of general
 relativity (the exterior Schwarzschild metric in isotropic coordinates); the whole
 remainder through fixed points of the lagged equation that must satisfy Eq. 4
-pointwise.  Parity unpinned: the -phidot d_i psi term and the exp(psi + 3 phi)
-factor of the momentum source (only B from the current alone is pinned).
+pointwise; the momentum source's time-derivative term -phidot d_i psi through an
+evolution solve on single-wave lagged fields (B in closed form by product-to-sum)
+and its metric factor exp(psi + 3 phi) through uniform offsets of phi and chi.
 """
 from __future__ import annotations
 

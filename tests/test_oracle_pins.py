@@ -279,6 +279,112 @@ def test_p7_b_closed_form_transverse_and_longitudinal():
     assert np.max(np.abs(-0.25 * pm.laplacian7(B2[1], n) - 1e-7 * _plane(n, m2))) < 1e-10 * 1e-7
 
 
+# The other terms of the momentum source S_i = exp(psi + 3 phi) J_i - phidot d_i psi (Eq. 6 with the
+# pure gradients dropped): the time-derivative term through an evolution solve whose lagged fields
+# are single waves (product-to-sum gives B in closed form), the metric factor through uniform
+# offsets of phi and chi (B is P7's closed form times exp(4 phi0 - chi0)).
+
+def _plane_sin(n, m):
+    g = np.arange(n) / n
+    z, y, x = np.meshgrid(g, g, g, indexing="ij")
+    return np.sin(2 * np.pi * (m[0] * x + m[1] * y + m[2] * z))
+
+
+def _evolution_b(n, phi1, phi2, chi1, J, dtau_last, dtau):
+    """B of one elliptic evolution solve of the oracle whose lagged fields and current are given
+    (uniform energy density, no stresses)."""
+    s = _sim_with_deposit(n, pm.FULL, None)
+    a = s.bg.a(s.tau)
+    kap = s.bg.kappa(n, n ** 3) / a ** 2
+    dep = np.zeros((10, n, n, n))
+    dep[0] = s.bg.ebar(a) / kap
+    for i in range(3):
+        dep[1 + i] = J[i] / kap
+    s.dep = dep
+    s.phi, s.phi_prev, s.chi = phi1, phi2, chi1
+    s.dtau_last = dtau_last
+    s.solved_once = True
+    s.solve(dtau)
+    return s.B
+
+
+def _b_of_wave(V, m, n):
+    """(4 / kt^2) (delta - kt kt / kt^2) V: B of a current (or momentum source) V sin/cos(k.x), P7."""
+    kt = _kt(n, m)
+    k2 = kt @ kt
+    return 4.0 / k2 * (V - kt * (kt @ V) / k2)
+
+
+def _phidot_term_error():
+    """Relative max error of B against the closed form when S_i = -phidot d_i psi alone.
+
+    phi_{n-1} = 0, phi_{n-2} = -dtau'' A cos(k1.x) -> phidot = A cos(k1.x);
+    chi_{n-1} = -C cos(k2.x)                       -> psi = phi - chi = C cos(k2.x),
+    centred difference d_i psi = -C s_i sin(k2.x) with s_i = n sin(2 pi m2_i / n), so
+    S_i = A C s_i cos(k1.x) sin(k2.x) = (A C s_i / 2) [sin((k2 + k1).x) + sin((k2 - k1).x)],
+    and each of the two waves q gets the transverse projector of P7 with its own kt(q)."""
+    n = 16
+    m1, m2 = np.array([1, 2, 0]), np.array([2, -1, 1])
+    A, C, dtl = 3e-6, 2e-4, 0.5
+    z = np.zeros((n, n, n))
+    B = _evolution_b(n, z, -dtl * A * _plane(n, m1), -C * _plane(n, m2), [z, z, z], dtl, 0.4)
+    sv = np.array([n * math.sin(2 * math.pi * mi / n) for mi in m2])
+    ref = [np.zeros((n, n, n)) for _ in range(3)]
+    for q in (m2 + m1, m2 - m1):
+        bq = _b_of_wave(0.5 * A * C * sv, q, n)
+        for i in range(3):
+            ref[i] = ref[i] + bq[i] * _plane_sin(n, q)
+    scale = max(np.max(np.abs(r)) for r in ref)
+    return max(np.max(np.abs(B[i] - ref[i])) for i in range(3)) / scale
+
+
+def _metric_factor_error():
+    """Relative max error of B against P7's closed form times exp(psi0 + 3 phi0) = exp(4 phi0 - chi0)
+    for uniform lagged phi0 (no time derivative) and chi0 and the current J = V cos(k.x)."""
+    n, m = 16, (2, -1, 1)
+    V = np.array([1.0, -2.0, 0.5]) * 1e-7
+    phi0, chi0 = 3e-3, -2e-3
+    one = np.ones((n, n, n))
+    J = [V[i] * _plane(n, m) for i in range(3)]
+    B = _evolution_b(n, phi0 * one, phi0 * one, chi0 * one, J, 0.5, 0.4)
+    ref = _b_of_wave(V, m, n) * math.exp(4 * phi0 - chi0)
+    return max(np.max(np.abs(B[i] - ref[i] * _plane(n, m))) for i in range(3)) / np.max(np.abs(ref))
+
+
+def test_p7_momentum_source_time_derivative_term_two_waves():
+    assert _phidot_term_error() < 1e-11
+
+
+def test_p7_momentum_source_metric_factor_uniform_offsets():
+    assert _metric_factor_error() < 1e-11
+
+
+def test_p7_momentum_source_pins_catch_planted_mistakes(monkeypatch):
+    """Each pin fails for a plausible mistake planted in the oracle's momentum source: the sign of the
+    time-derivative term, psi in place of phi in the derivative, and the exponent of the metric factor
+    (exp(psi + 2 phi), exp(phi - chi)... as written out below)."""
+    good = pm.momentum_source
+
+    def flipped(J, phi, chi, phidot, gphi, gchi):
+        return [np.exp(phi - chi + 3 * phi) * J[i] + phidot * (gphi[i] - gchi[i]) for i in range(3)]
+
+    def grad_phi_only(J, phi, chi, phidot, gphi, gchi):
+        return [np.exp(phi - chi + 3 * phi) * J[i] - phidot * gphi[i] for i in range(3)]
+
+    def exponent_2phi(J, phi, chi, phidot, gphi, gchi):
+        return [np.exp(phi - chi + 2 * phi) * J[i] - phidot * (gphi[i] - gchi[i]) for i in range(3)]
+
+    def exponent_plus_chi(J, phi, chi, phidot, gphi, gchi):
+        return [np.exp(phi + chi + 3 * phi) * J[i] - phidot * (gphi[i] - gchi[i]) for i in range(3)]
+
+    for bad, pin in ((flipped, _phidot_term_error), (grad_phi_only, _phidot_term_error),
+                     (exponent_2phi, _metric_factor_error), (exponent_plus_chi, _metric_factor_error)):
+        monkeypatch.setattr(pm, "momentum_source", bad)
+        assert pin() > 1e-3, bad.__name__
+    monkeypatch.setattr(pm, "momentum_source", good)
+    assert _phidot_term_error() < 1e-11 and _metric_factor_error() < 1e-11
+
+
 # --------------------------------------------------------------------------
 # P8-P9: tensor sector and projectors
 # --------------------------------------------------------------------------
