@@ -174,7 +174,10 @@ pm_status pm_update_particles(pm_ctx* ctx, double dtau);
  * quasi-static solve on the first step after pm_init_particles), update. */
 pm_status pm_step(pm_ctx* ctx, double dtau);
 
-/* Copy a real-space field ([z][y][x], n_mesh^3 values of the context precision). */
+/* Copy a real-space field ([z][y][x], n_mesh^3 values of the context precision).  The h_ij
+ * components are rebuilt from the per-mode tensor state through the spectrum buffers; no field of
+ * the time-stepping state (the deposit included) is touched, so this may be called between any
+ * two stages. */
 pm_status pm_get_field(pm_ctx* ctx, int field_id, void* dst, int dst_on_device);
 /* Overwrite a field (deposit components, PHI, CHI, B*, PHI_PREV); for tests and
  * for the closure. Setting a deposit component marks the deposit as done. */
@@ -229,8 +232,8 @@ pm_status pm_debug_fft(pm_ctx* ctx, const void* d_in, void* d_out, int direction
  * k_f = 2 pi / L, shell b = round(|m|) for b = 1 .. n/2.  Writes n/2 + 1 host
  * values to each of k_out (mean |k| of the shell, h/Mpc), p_out ((Mpc/h)^3) and
  * modes_out (modes in the shell; entry 0 and empty shells are 0).  Uses the
- * deposit and spectrum buffers as scratch (call it between steps; the next
- * pm_solve_metric needs a new pm_deposit) and synchronises the stream. */
+ * spectrum buffers as scratch, which hold nothing between a solve and the next
+ * one, so it may be called between any two stages; synchronises the stream. */
 pm_status pm_power_spectrum(pm_ctx* ctx, int subtract_shot_noise, double* k_out, double* p_out, double* modes_out);
 
 /* Checkpoint and restart.  The paper writes particle and metric snapshots
@@ -251,8 +254,14 @@ pm_status pm_power_spectrum(pm_ctx* ctx, int subtract_shot_noise, double* k_out,
  * n_particles.  dst_on_device / src_on_device: the blob is device (1) or host (0)
  * memory; either way both calls synchronise the stream before they return.
  * pm_set_state validates the header (PM_EINVAL for a blob of another
- * configuration, truncated or corrupt), clears a sticky device error and leaves
- * the context as it was when the blob was taken.  The run after a restore agrees
+ * configuration, truncated or corrupt) and then the body on the device: the cell
+ * offsets must start at 0, end at the particle count and never decrease, and every
+ * particle must have finite momenta, a position in [0, 1), an identifier below the
+ * particle count and sit inside the offsets' range of the cell its position falls
+ * in (PM_EINVAL otherwise, and the context then holds no particles until the next
+ * pm_init_particles or successful pm_set_state; repeated identifiers are not
+ * detected).  On success it clears a sticky device error and leaves the context as
+ * it was when the blob was taken.  The run after a restore agrees
  * with the uninterrupted run to rounding: particles inside a cell are ordered by
  * the sort's atomic counters, so sums over a cell's particles may round
  * differently from run to run. */

@@ -668,21 +668,22 @@ pm_status pm_get_field(pm_ctx* c, int id, void* dst, int dst_on_device) {
     // rebuild the six components into the spectrum buffer and transform the requested one
     const int comp = id - PM_FIELD_HXX;
     const Layout& L = c->L;
+    // (the real result goes to the solutions' spectrum buffer, which holds nothing between solves;
+    // the deposit, which the closure reads after a solve, stays untouched)
     if (c->cfg.precision == PM_FP64) {
       cplx<double>* spec = c->at<cplx<double>>(L.spec);
       launch_tensor_components<double>(spec, L.spec_comp, c->n, L.nhp, c->at<double>(L.kt),
                                        c->at<cplx<double>>(L.hst), c->st);
-      double* out[1] = {c->at<double>(L.dep)};
+      double* out[1] = {c->at<double>(L.spec_out)};
       fft_inverse<double>(c->n, L.nhp, spec + comp * L.spec_comp, 1, out, 1.0 / c->n3, c->at<cplx<double>>(L.tw), c->st);
     } else {
       cplx<float>* spec = c->at<cplx<float>>(L.spec);
       launch_tensor_components<float>(spec, L.spec_comp, c->n, L.nhp, c->at<float>(L.kt), c->at<cplx<float>>(L.hst),
                                       c->st);
-      float* out[1] = {c->at<float>(L.dep)};
+      float* out[1] = {c->at<float>(L.spec_out)};
       fft_inverse<float>(c->n, L.nhp, spec + comp * L.spec_comp, 1, out, 1.0 / c->n3, c->at<cplx<float>>(L.tw), c->st);
     }
-    c->deposited = false;  // the deposit buffer served as scratch
-    src = c->ws + L.dep;
+    src = c->ws + L.spec_out;
   } else {
     src = c->field_ptr(id);
     if (!src) return c->fail(PM_EINVAL, "field not present for this physics");
@@ -897,7 +898,6 @@ pm_status pm_debug_fft(pm_ctx* c, const void* d_in, void* d_out, int direction) 
       fft_inverse<float>(c->n, L.nhp, spec, 1, out, 1.0 / c->n3, c->at<cplx<float>>(L.tw), c->st);
     }
   }
-  c->deposited = false;
   return c->hip_check("debug_fft");
 }
 
@@ -907,18 +907,20 @@ namespace {
 template <typename T>
 pm_status do_power_spectrum(pm_ctx* c, int subtract, double* k_out, double* p_out, double* modes_out) {
   const Layout& L = c->L;
-  T* dep = c->at<T>(L.dep);
-  launch_deposit<T>(c->parts<T>(c->cur), c->at<uint32_t>(L.cell_start), c->n, 1, false, 1.0, 1.0, false, dep, nullptr,
+  // the count field lives in the solutions' spectrum buffer (free between solves; at least n^3
+  // values), so that the deposit and the fields of the time-stepping state stay untouched
+  T* cnt = c->at<T>(L.spec_out);
+  launch_deposit<T>(c->parts<T>(c->cur), c->at<uint32_t>(L.cell_start), c->n, 1, false, 1.0, 1.0, false, cnt, nullptr,
                     c->st);
   SrcArgsH<T> s;
-  s.raw = dep;
+  s.raw = cnt;
   cplx<T>* spec = c->at<cplx<T>>(L.spec);
   fft_forward<T>(s, MODE_RAW, c->n, L.nhp, spec, 1, c->at<cplx<T>>(L.tw), c->st);
   // the count field has been transformed: its buffer holds the partials and the result
-  const size_t scratch = (size_t)L.ndep * c->n3 * c->rs;
+  const size_t scratch = (size_t)L.nout * L.spec_comp * 2 * c->rs;
   const int nblocks = pk_blocks(c->n, scratch);
   const int nb = c->n / 2 + 1;
-  double* part = reinterpret_cast<double*>(dep);
+  double* part = reinterpret_cast<double*>(cnt);
   const double box3 = 1.0;  // box units: P in units of L^3, converted below
   launch_power_spectrum<T>(spec, c->n, L.nhp, box3 / ((double)c->np * (double)c->np), subtract ? box3 / (double)c->np : 0.0,
                            nblocks, part, c->st);
@@ -932,7 +934,6 @@ pm_status do_power_spectrum(pm_ctx* c, int subtract, double* k_out, double* p_ou
     p_out[b] = m > 0 ? h[nb + b] / m * Lb * Lb * Lb : 0.0;
     k_out[b] = m > 0 ? h[2 * nb + b] / m * kf : 0.0;
   }
-  c->deposited = false;
   return c->hip_check("power_spectrum");
 }
 }  // namespace
@@ -1114,7 +1115,32 @@ pm_status pm_set_state(pm_ctx* c, const void* blob, size_t bytes, int src_on_dev
   c->zero(c->L.cnt, c->n3 * 4);
   if (c->np2 > 0) c->zero(c->L.cnt2, c->n3 * 4);
   c->zero(c->L.err, 64);
-  if (!src_on_device) (void)hipStreamSynchronize(c->st);
+  // the body is not trusted: the kernels index LDS tiles and ranges by the cell offsets and the
+  // positions, so both are checked against each other before the context may run on them
+  int* err = c->at<int>(c->L.err);
+  if (c->cfg.precision == PM_FP64) {
+    launch_check_store<double>(c->parts<double>(0), c->np, c->n, c->at<uint32_t>(c->L.cell_start), err, c->st);
+    if (c->np2 > 0)
+      launch_check_store<double>(c->parts2<double>(0), c->np2, c->n, c->at<uint32_t>(c->L.cell_start2), err, c->st);
+  } else {
+    launch_check_store<float>(c->parts<float>(0), c->np, c->n, c->at<uint32_t>(c->L.cell_start), err, c->st);
+    if (c->np2 > 0)
+      launch_check_store<float>(c->parts2<float>(0), c->np2, c->n, c->at<uint32_t>(c->L.cell_start2), err, c->st);
+  }
+  int flag = 0;
+  if (hipMemcpyAsync(&flag, err, sizeof(int), hipMemcpyDeviceToHost, c->st) != hipSuccess ||
+      hipStreamSynchronize(c->st) != hipSuccess) {
+    c->have_particles = c->have_particles2 = false;
+    c->deposited = c->solved = false;
+    return c->fail(PM_EHIP, "checking the restored state failed");
+  }
+  if (flag & 4) {
+    // nothing of the blob may be used: the context has no particles until the next load or restore
+    c->zero(c->L.err, 64);
+    c->have_particles = c->have_particles2 = false;
+    c->deposited = c->solved = c->solved_once = false;
+    return c->fail(PM_EINVAL, "state blob body inconsistent (cell offsets, positions or identifiers)");
+  }
   c->cur = 0;
   c->cur2 = 0;
   c->have_particles2 = c->np2 > 0;
@@ -1168,10 +1194,13 @@ pm_status pm_closure_set_params(pm_ctx* c, const float* params, int src_on_devic
   const Layout& L = c->L;
   const float* src = params;
   if (!src_on_device) {
-    // stage through the unused half of the second FP64 position block
-    float* dst = reinterpret_cast<float*>(c->ws + L.pos[1 - c->cur]);
+    // stage through the closure's output buffer (3 n^3 floats >= 49152 bytes for n >= 16, more than
+    // the parameters need); its contents are stale afterwards, so a new forward pass is required
+    static_assert(3 * 16 * 16 * 16 >= PM_CLOSURE_NPARAM, "staging buffer too small");
+    float* dst = c->at<float>(L.cl_corr);
     (void)hipMemcpyAsync(dst, params, PM_CLOSURE_NPARAM * sizeof(float), hipMemcpyHostToDevice, c->st);
     src = dst;
+    c->cl_forwarded = false;
   }
   closure_pack(src, c->at<uint16_t>(L.cl_wf), c->at<uint16_t>(L.cl_wb), c->at<float>(L.cl_bias), c->st);
   if (!src_on_device) (void)hipStreamSynchronize(c->st);

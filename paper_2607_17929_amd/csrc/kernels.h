@@ -135,6 +135,10 @@ size_t scan_block_sums_count(long ncell);
 template <typename T>
 void launch_scatter(const Particles<T>& src, Particles<T> dst, long np, int nmesh, const uint32_t* rank,
                     const uint32_t* cell_start, hipStream_t st);
+// bit 4 of err unless the store and its cell offsets are consistent (used on restored checkpoints)
+template <typename T>
+void launch_check_store(const Particles<T>& p, long np, int nmesh, const uint32_t* cell_start, int* err,
+                        hipStream_t st);
 template <typename T>
 void launch_export(const Particles<T>& p, long np, double* pos_aos, T* u_aos, uint32_t* ids, hipStream_t st);
 template <typename T>

@@ -743,6 +743,49 @@ void launch_scatter(const Particles<T>& src, Particles<T> dst, long np, int nmes
 }
 
 // ---------------------------------------------------------------------------
+// consistency check of a restored store (checkpoint bodies are not trusted):
+// cell_start[0] = 0, cell_start[n^3] = np, non-decreasing; every particle has
+// finite momenta, a position in [0, 1), an identifier < np, and sits inside the
+// range of the cell its position falls in.  Any failure sets bit 4 of err.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void check_offsets_kernel(const uint32_t* cell_start, long ncell, long np, int* err) {
+  const long c = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c > ncell) return;
+  bool bad = false;
+  if (c == 0) bad = cell_start[0] != 0u;
+  if (c == ncell) bad = bad || (long)cell_start[ncell] != np;
+  if (c < ncell) bad = bad || cell_start[c] > cell_start[c + 1];
+  if (bad) atomicOr(err, 4);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void check_store_kernel(Particles<T> p, long np, int nmesh,
+                                                          const uint32_t* cell_start, int* err) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= np) return;
+  const double x = p.px[i], y = p.py[i], z = p.pz[i];
+  const T ux = p.ux[i], uy = p.uy[i], uz = p.uz[i];
+  bool ok = isfinite(ux) && isfinite(uy) && isfinite(uz);
+  ok = ok && x >= 0.0 && x < 1.0 && y >= 0.0 && y < 1.0 && z >= 0.0 && z < 1.0;  // false for NaN
+  ok = ok && (long)p.id[i] < np;
+  if (ok) {
+    const uint32_t k = cell_key(x, y, z, nmesh);
+    ok = (long)cell_start[k] <= i && i < (long)cell_start[k + 1];
+  }
+  if (!ok) atomicOr(err, 4);
+}
+
+template <typename T>
+void launch_check_store(const Particles<T>& p, long np, int nmesh, const uint32_t* cell_start, int* err,
+                        hipStream_t st) {
+  const long ncell = (long)nmesh * nmesh * nmesh;
+  hipLaunchKernelGGL(check_offsets_kernel, dim3((unsigned)((ncell + 1 + 255) / 256)), dim3(256), 0, st, cell_start,
+                     ncell, np, err);
+  hipLaunchKernelGGL((check_store_kernel<T>), dim3((unsigned)((np + 255) / 256)), dim3(256), 0, st, p, np, nmesh,
+                     cell_start, err);
+}
+
+// ---------------------------------------------------------------------------
 // export in identifier order as [n][3] arrays
 // ---------------------------------------------------------------------------
 template <typename T>
@@ -795,6 +838,7 @@ void launch_copy_unpad(const cplx<T>* spec, int n, int nhp, cplx<T>* out, bool t
   template void launch_scatter<T>(const Particles<T>&, Particles<T>, long, int, const uint32_t*, const uint32_t*,      \
                                   hipStream_t);                                                                        \
   template void launch_export<T>(const Particles<T>&, long, double*, T*, uint32_t*, hipStream_t);                      \
+  template void launch_check_store<T>(const Particles<T>&, long, int, const uint32_t*, int*, hipStream_t);            \
   template void launch_copy_unpad<T>(const cplx<T>*, int, int, cplx<T>*, bool, hipStream_t);
 GPM_INST(float)
 GPM_INST(double)

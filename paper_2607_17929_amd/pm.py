@@ -266,7 +266,14 @@ class PMContext:
         self._chk(self.lib.pm_gather_grad_phi(self.ctx, C.c_void_p(_ptr(out)), 1), "pm_gather_grad_phi")
         return out
 
-    def closure_set_params(self, params):
+    def closure_set_params(self, params, host: bool = False):
+        """Bind the network's FP32 parameter vector; `host` passes it from host memory (src_on_device 0)."""
+        if host:
+            a = np.ascontiguousarray(params.cpu().numpy() if isinstance(params, torch.Tensor) else params,
+                                     dtype=np.float32)
+            assert a.size == L.PM_CLOSURE_NPARAM
+            self._chk(self.lib.pm_closure_set_params(self.ctx, a.ctypes.data, 0), "pm_closure_set_params")
+            return
         t = torch.as_tensor(params, dtype=torch.float32).to(self.device).contiguous()
         assert t.numel() == L.PM_CLOSURE_NPARAM
         self._keep_params = t

@@ -103,3 +103,70 @@ def test_closure_training_beats_plain_force():
     print(f"held-out: plain 1x error {plain:.4e}, with closure {corr:.4e}", flush=True)
     assert np.mean(hist[-50:]) < np.mean(hist[:20])
     assert corr < 0.8 * plain
+
+
+def test_parameters_from_host_memory_leave_the_run_untouched():
+    """pm_closure_set_params from host memory stages the parameters inside the closure's own buffers:
+    on a small run (100 particles, 16^3 mesh) the particles and fields are bit for bit what they were,
+    and the network's output equals the one after binding the same parameters from device memory."""
+    from paper_2607_17929_amd import PMContext
+    print("closure parameters from host memory", flush=True)
+    r = np.random.default_rng(21)
+    pos = r.random((100, 3))
+    u = 1e-3 * r.standard_normal((100, 3))
+    ctx = PMContext(16, 100, 160.0, physics="scalar", precision="fp64", closure=True)
+    ctx.init_particles(pos, u, opm.Background(160.0).tau(0.1))
+    for _ in range(2):
+        ctx.step(0.5)
+    ctx.deposit()
+    ctx.solve_metric(0.5)
+    before = {k: ctx.get_field(k) for k in ("n00", "n0x", "nzz", "phi", "phi_prev", "chi")}
+    pb, ub = ctx.get_particles()
+    params = _params(4)
+    ctx.closure_set_params(params, host=True)
+    for k, v in before.items():
+        assert np.array_equal(ctx.get_field(k), v), k
+    pa, ua = ctx.get_particles()
+    assert np.array_equal(pa, pb) and np.array_equal(ua, ub)
+    ctx.closure_forward(False)
+    out_host = ctx.closure_gather().cpu().numpy()
+    ctx.closure_set_params(torch.tensor(params, dtype=torch.float32))
+    ctx.closure_forward(False)
+    assert np.array_equal(ctx.closure_gather().cpu().numpy(), out_host)
+    ctx.update_particles(0.5)
+    ctx.sync()
+
+
+def test_reading_h_and_spectrum_between_solve_and_update():
+    """With the closure on, reading h_ij or measuring P(k) between the solve and the update does not
+    change the update: both use scratch that holds nothing between solves, not the deposit the closure
+    reads its density feature from."""
+    from paper_2607_17929_amd import PMContext
+    print("h_ij and P(k) between solve and update", flush=True)
+    pos, u, tau0, dtau = config_particles("zeldovich_32_scalar_fp64")
+    params = _params(6)
+    runs = []
+    for probe in (False, True):
+        ctx = PMContext(32, pos.shape[0], 320.0, physics="full", precision="fp64", closure=True)
+        ctx.init_particles(pos, u, tau0)
+        ctx.closure_set_params(torch.tensor(params, dtype=torch.float32))
+        ctx.closure_enable(True)
+        for i in range(3):
+            ctx.deposit()
+            ctx.solve_metric(dtau if i else 0.0)
+            if probe:
+                ctx.get_field("hxy")
+                ctx.power_spectrum()
+                ctx.get_field("hzz", device=True)
+            ctx.update_particles(dtau)
+        runs.append((ctx.get_particles()[0], gpu_fields_of(ctx)))
+    (p0, f0), (p1, f1) = runs
+    d = p1 - p0
+    d -= np.round(d)
+    assert np.max(np.abs(d)) * 32 < 1e-10
+    for k in f0:
+        assert rel_l2(f1[k], f0[k]) < 1e-12, k
+
+
+def gpu_fields_of(ctx):
+    return {k: ctx.get_field(k).astype(np.float64) for k in ("phi", "chi", "bx", "hxx")}

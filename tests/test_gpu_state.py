@@ -187,3 +187,67 @@ def test_restore_clears_a_sticky_device_error():
     pa, _ = a.get_particles()
     pr, _ = ref.get_particles()
     assert periodic_max_dx(pa, pr, 32) < 1e-10
+
+
+def _header_sections(blob):
+    """(offset, bytes) of each section of a state blob, read from its header (magic, version,
+    section count, configuration, times, flags, total, then 32 offsets and 32 sizes as uint64)."""
+    nsec = int(np.frombuffer(blob[12:16].tobytes(), dtype=np.uint32)[0])
+    off = np.frombuffer(blob[112:112 + 8 * 32].tobytes(), dtype=np.uint64)[:nsec]
+    size = np.frombuffer(blob[368:368 + 8 * 32].tobytes(), dtype=np.uint64)[:nsec]
+    return [(int(o), int(b)) for o, b in zip(off, size)]
+
+
+def test_damaged_blob_bodies_are_rejected():
+    """The body of a checkpoint is checked on the device before the context runs on it: cell offsets
+    that do not end at the particle count or decrease, a position outside [0, 1), a particle moved
+    into another cell's range and an identifier out of range each give PM_EINVAL; the context then
+    holds no particles (the next deposit is out of order) until a good blob is restored."""
+    from paper_2607_17929_amd import PMError
+    _say("state blob body validation")
+    pos, u, tau0, dtau = config_particles("zeldovich_32_scalar_fp64")
+    n, n_p = 32, pos.shape[0]
+    a = _ctx(n, n_p, 320.0, "scalar", "fp64")
+    a.init_particles(pos, u, tau0)
+    a.step(dtau)
+    blob = a.get_state()
+    sec = _header_sections(blob)
+    (o_pos, _), (o_mom, _), (o_id, _), (o_cs, b_cs) = sec[:4]
+    assert b_cs == (n ** 3 + 1) * 4
+    cs = np.frombuffer(blob[o_cs:o_cs + b_cs].tobytes(), dtype=np.uint32).copy()
+    px = np.frombuffer(blob[o_pos:o_pos + 8 * n_p].tobytes(), dtype=np.float64).copy()
+
+    def with_cs(c):
+        b = blob.copy()
+        b[o_cs:o_cs + b_cs] = np.frombuffer(c.astype(np.uint32).tobytes(), dtype=np.uint8)
+        return b
+
+    def with_x(i, x):
+        b = blob.copy()
+        b[o_pos + 8 * i:o_pos + 8 * i + 8] = np.frombuffer(np.float64(x).tobytes(), dtype=np.uint8)
+        return b
+
+    damaged = {}
+    c = cs.copy(); c[-1] = n_p + 1; damaged["total"] = with_cs(c)
+    c = cs.copy(); k = int(np.argmax(np.diff(cs) > 0)); c[k + 1] = c[k] - 1 if c[k] > 0 else c[k + 2] + 5
+    damaged["decreasing"] = with_cs(c)
+    damaged["outside"] = with_x(0, 1.5)
+    damaged["nan"] = with_x(1, float("nan"))
+    damaged["other cell"] = with_x(2, (px[2] + 0.5) % 1.0)
+    b = blob.copy(); b[o_id:o_id + 4] = np.frombuffer(np.uint32(n_p).tobytes(), dtype=np.uint8)
+    damaged["identifier"] = b
+    target = _ctx(n, n_p, 320.0, "scalar", "fp64")
+    for name, bad in damaged.items():
+        _say(f"  damaged body: {name}")
+        with pytest.raises(PMError) as e:
+            target.set_state(bad)
+        assert e.value.status == -1, name
+        with pytest.raises(PMError) as e:
+            target.deposit()
+        assert e.value.status == -5, name
+    target.set_state(blob)
+    target.step(dtau)
+    a.step(dtau)
+    fa, ft = gpu_fields(a, "scalar"), gpu_fields(target, "scalar")
+    for k in fa:
+        assert rel_l2(ft[k], fa[k]) < 1e-12, k
