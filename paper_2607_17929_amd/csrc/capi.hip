@@ -278,15 +278,18 @@ void upload_tables(pm_ctx* c) {
 
 // one forward transform + solve + inverse transform
 // smode: the solve's mode (c->mode, or MODE_FULLP for a parabolic-B step); b_op as in SolveArgs
+// incr: solve for the increment phi_n - phi_{n-1} (phi1 = phi_{n-1}); phi_out then gets phi1 plus the
+// increment and delta_out the increment itself
 template <typename T>
-void solve_pass(pm_ctx* c, const T* phi1, const T* phi2, const T* chi1, double inv_dt, double inv_dtl, T* phi_out,
-                int tensor_op, double dtau, double hc_half, int smode, int b_op) {
+void solve_pass(pm_ctx* c, const T* phi1, const T* dphi1, const T* chi1, double inv_dt, double inv_dtl, T* phi_out,
+                int tensor_op, double dtau, double hc_half, int smode, int b_op, int incr = 0, T* delta_out = nullptr) {
   const Layout& L = c->L;
   const int nsrc = mode_nsrc(smode);
   const double a = c->a_of(c->tau), hc = c->hc_of(c->tau), eb = c->ebar(a);
   SrcArgsH<T> s;
   s.dep = c->at<T>(L.dep);
-  s.phi1 = phi1; s.phi2 = phi2; s.chi1 = chi1;
+  s.phi1 = phi1; s.dphi1 = dphi1; s.chi1 = chi1;
+  s.incr = incr;
   s.rowsum = c->mode == MODE_NEWTONIAN ? nullptr : c->at<double>(L.rowsum);
   s.kap = c->kappa() / (a * a);
   s.ebar = eb; s.hc = hc; s.inv_dt = inv_dt; s.inv_dtl = inv_dtl;
@@ -311,6 +314,7 @@ void solve_pass(pm_ctx* c, const T* phi1, const T* phi2, const T* chi1, double i
   sa.kap_a2 = c->kappa() / (a * a);
   sa.n3_ebar = (double)c->n3 * eb;
   sa.phibar_out = dc + 1;
+  sa.incr = incr;
   sa.hst = L.hst ? c->at<cplx<T>>(L.hst) : nullptr;
   sa.tensor_op = c->mode == MODE_FULL ? tensor_op : 0;
   sa.dtau = dtau; sa.hc_half = hc_half;
@@ -329,7 +333,7 @@ void solve_pass(pm_ctx* c, const T* phi1, const T* phi2, const T* chi1, double i
   fft_cols<T>(c->n, L.nhp * L.nout, spec_out, 1, true, false, tw, c->st);
   c->stage_end(PM_STAGE_FFT_Y_INV);
   c->stage_begin(PM_STAGE_FFT_X_INV);
-  fft_c2r_x<T>(c->n, L.nhp, spec_out, L.nout, outs, 1.0, tw, c->st);
+  fft_c2r_x<T>(c->n, L.nhp, spec_out, L.nout, outs, 1.0, tw, c->st, incr ? phi1 : nullptr, delta_out);
   c->stage_end(PM_STAGE_FFT_X_INV);
 }
 
@@ -344,22 +348,28 @@ pm_status do_solve(pm_ctx* c, double dtau_prev) {
     c->i_prev = c->i_phi;
     c->i_phi = i_new;
   } else if (dtau_prev <= 0) {
-    // quasi-static start: two passes from phi = chi = 0, no time derivatives
+    // quasi-static start: two passes from phi = chi = 0, no time derivatives; the slots end as
+    // latest = previous = the second pass's phi and a zero increment (the third slot)
     const int sa = 0, sb = 1, sc = 2;
     // (the parabolic B route starts from the momentum constraint's B of the second pass)
+    c->zero(L.phi[sc], c->n3 * sizeof(T));
     solve_pass<T>(c, nullptr, nullptr, nullptr, 0, 0, slot(sa), 1, 0, 0, c->mode, 0);
-    solve_pass<T>(c, slot(sa), slot(sa), chi, 0, 0, slot(sb), 1, 0, 0, c->mode, 1);
+    solve_pass<T>(c, slot(sa), slot(sc), chi, 0, 0, slot(sb), 1, 0, 0, c->mode, 1);
     hipMemcpyAsync(slot(sc), slot(sb), c->n3 * sizeof(T), hipMemcpyDeviceToDevice, c->st);
+    c->zero(L.phi[sa], c->n3 * sizeof(T));
     c->i_phi = sb;
     c->i_prev = sc;
     c->dtau_last = 0;
   } else {
-    const int i_new = 3 - c->i_phi - c->i_prev;
+    // semi-implicit step solved for the increment: phi_{n-2} is no longer needed, so phi_n takes
+    // its slot; the increment slot holds phi_{n-1} - phi_{n-2} (read by the source assembly for the
+    // lagged time derivative) and then phi_n - phi_{n-1}
+    const int i_new = c->i_prev, i_d = 3 - c->i_phi - c->i_prev;
     const double inv_dtl = c->dtau_last > 0 ? 1.0 / c->dtau_last : 0.0;
     const double hc_half = c->hc_of(c->tau - 0.5 * dtau_prev);
     const int smode = (c->mode == MODE_FULL && c->L.a2b) ? MODE_FULLP : c->mode;
-    solve_pass<T>(c, slot(c->i_phi), slot(c->i_prev), chi, 1.0 / dtau_prev, inv_dtl, slot(i_new), 2, dtau_prev,
-                  hc_half, smode, 2);
+    solve_pass<T>(c, slot(c->i_phi), slot(i_d), chi, 1.0 / dtau_prev, inv_dtl, slot(i_new), 2, dtau_prev,
+                  hc_half, smode, 2, 1, slot(i_d));
     c->i_prev = c->i_phi;
     c->i_phi = i_new;
     c->dtau_last = dtau_prev;
@@ -954,7 +964,7 @@ pm_status pm_power_spectrum(pm_ctx* c, int subtract_shot_noise, double* k_out, d
 namespace {
 
 constexpr uint64_t kStateMagic = 0x31455441545347ULL;  // "GSTATE1" (little-endian bytes)
-constexpr uint32_t kStateVersion = 2;
+constexpr uint32_t kStateVersion = 3;
 constexpr size_t kStateHeader = 1024;
 constexpr int kStateMaxSec = 32;
 
@@ -974,8 +984,9 @@ struct StateHeader {
 static_assert(sizeof(StateHeader) <= kStateHeader, "state header too large");
 
 // workspace regions that make up the state: the sorted particles (buffer `cur`), the cell offsets
-// of the sort, phi of the latest and the previous solve, chi, B, the tensor and parabolic-B
-// spectra, the FP64 scalars and, between a deposit and its solve, the deposit
+// of the sort, phi of the latest and the previous solve and the latest solve's increment, chi, B,
+// the tensor and parabolic-B spectra, the FP64 scalars and, between a deposit and its solve, the
+// deposit
 int state_sections(const pm_ctx* c, int cur, int cur2, int i_phi, int i_prev, bool with_dep, size_t* ws_off,
                    size_t* bytes) {
   const Layout& L = c->L;
@@ -996,6 +1007,7 @@ int state_sections(const pm_ctx* c, int cur, int cur2, int i_phi, int i_prev, bo
   }
   add(L.phi[i_phi], n3 * rs);
   add(L.phi[i_prev], n3 * rs);
+  if (c->mode != MODE_NEWTONIAN) add(L.phi[3 - i_phi - i_prev], n3 * rs);  // increment of the latest solve
   if (L.chi) add(L.chi, n3 * rs);
   for (int i = 0; i < 3; ++i)
     if (L.b[i]) add(L.b[i], n3 * rs);
@@ -1100,7 +1112,7 @@ pm_status pm_set_state(pm_ctx* c, const void* blob, size_t bytes, int src_on_dev
     return c->fail(PM_EINVAL, "state blob of another configuration");
   if (!(h.tau > 0) || !isfinite(h.tau) || h.steps < 0 || h.total > bytes)
     return c->fail(PM_EINVAL, "corrupt state header");
-  // restore into particle buffer 0 and phi slots 0 (latest) and 1 (previous)
+  // restore into particle buffer 0 and phi slots 0 (latest), 1 (previous) and 2 (increment)
   size_t ws_off[kStateMaxSec], sb[kStateMaxSec];
   uint64_t off[kStateMaxSec];
   const int nsec = state_sections(c, 0, 0, 0, 1, h.deposited != 0, ws_off, sb);

@@ -54,7 +54,7 @@ template <typename T>
 struct SrcArgs {
   const T* dep;    // deposit components, stride n^3
   const T* phi1;   // lagged phi_{n-1} (null: zero)
-  const T* phi2;   // phi_{n-2}
+  const T* dphi1;  // increment phi_{n-1} - phi_{n-2} of the lagged solve
   const T* chi1;   // lagged chi
   const T* raw;    // MODE_RAW: the field to transform
   double* rowsum;  // FP64 row sums [z][y] of the phi source without its E - ebar term (may be null)
@@ -64,6 +64,8 @@ struct SrcArgs {
   T inv_dt;        // 1 / (tau_n - tau_{n-1}), 0 for a quasi-static solve
   T inv_dtl;       // 1 / (tau_{n-1} - tau_{n-2}) for the lagged phi-dot, 0 if unknown
   T half_n;        // n / 2: centred difference factor
+  T n2;            // n^2: 7-point Laplacian factor
+  int incr;        // source of the increment phi_n - phi_{n-1}
 };
 
 // Writes the n_src sources of vertex (x, y, z) to out[c * cstride].
@@ -81,7 +83,7 @@ __device__ __forceinline__ T assemble_point(const SrcArgs<T>& a, int n, int x, i
   } else {
     const long n3 = nn * n;
     const T E = a.kap * a.dep[idx];
-    T p = 0, c = 0, pd = 0, gp[3] = {0, 0, 0}, gc[3] = {0, 0, 0};
+    T p = 0, c = 0, pd = 0, lap = 0, gp[3] = {0, 0, 0}, gc[3] = {0, 0, 0};
     if (a.phi1) {
       const int xm = wrapi(x - 1, n), xp = wrapi(x + 1, n);
       const int ym = wrapi(y - 1, n), yp = wrapi(y + 1, n);
@@ -92,12 +94,18 @@ __device__ __forceinline__ T assemble_point(const SrcArgs<T>& a, int n, int x, i
                              {(long)zp * nn + ry + x, (long)zm * nn + ry + x}};
       p = a.phi1[idx];
       c = a.chi1[idx];
-      pd = (p - a.phi2[idx]) * a.inv_dtl;
+      // lagged time derivative from the increment of the lagged solve (not from the difference of
+      // two stored solutions, which in FP32 would carry both solutions' rounding)
+      pd = a.dphi1[idx] * a.inv_dtl;
+      T nb = 0;
 #pragma unroll
       for (int d = 0; d < 3; ++d) {
-        gp[d] = (a.phi1[ix[d][0]] - a.phi1[ix[d][1]]) * a.half_n;
+        const T up = a.phi1[ix[d][0]], dn = a.phi1[ix[d][1]];
+        gp[d] = (up - dn) * a.half_n;
         gc[d] = (a.chi1[ix[d][0]] - a.chi1[ix[d][1]]) * a.half_n;
+        nb += up + dn;
       }
+      lap = (nb - (T)6 * p) * a.n2;
     }
     const T hc = a.hc, eb = a.ebar;
     // non-linear remainder of the Hamiltonian constraint (lagged fields)
@@ -106,8 +114,12 @@ __device__ __forceinline__ T assemble_point(const SrcArgs<T>& a, int n, int x, i
     const T hmd = hc - pd;
     const T R = (T)0.5 * g2 + (E - eb) * p + E * expm1_minus_x(p) -
                 (T)1.5 * (hmd * hmd * expm1_minus_x((T)-2 * w) + (T)2 * w * ((T)2 * hc * pd - pd * pd) + pd * pd);
-    // the mean of E - ebar is taken from an FP64 sum over particles; the rest is summed here
-    const T rest = R - (T)3 * hc * a.inv_dt * p - (T)3 * hc * hc * c;
+    // the mean of E - ebar is taken from an FP64 sum over particles; the rest is summed here.
+    // Semi-implicit form (L - 3H/dtau' - 6H^2 - ebar) phi_n = (E - ebar) - (3H/dtau') phi_{n-1}
+    // - 3H^2 chi_{n-1} + R with L the 7-point Laplacian; for the increment delta = phi_n - phi_{n-1}
+    // the same operator has the source (E - ebar) + R - 3H^2 chi_{n-1} - L phi_{n-1} + (6H^2 + ebar) phi_{n-1}
+    const T rest = a.incr ? R - (T)3 * hc * hc * c - lap + ((T)6 * hc * hc + eb) * p
+                          : R - (T)3 * hc * a.inv_dt * p - (T)3 * hc * hc * c;
     const T rhs = (E - eb) + rest;
     out[0] = rhs;
     // trace-free space-space source (symmetric, order xx xy xz yy yz zz)
@@ -212,6 +224,8 @@ __global__ __launch_bounds__(NT) void fft_x_r2c_kernel(SrcArgs<T> a, cplx<T>* sp
 template <typename T>
 struct OutPtrs {
   T* p[8];
+  const T* base0;  // non-null: component 0 is an increment added to base0 ...
+  T* delta0;       // ... and stored as it is here
 };
 
 template <typename T, int N, int NOUT, int RY, int NT>
@@ -268,7 +282,14 @@ __global__ __launch_bounds__(NT) void fft_x_c2r_kernel(const cplx<T>* spec, int 
   for (int job = tid; job < L * N; job += NT) {
     const int line = job / N, x = job % N;
     const int c = line / RY, r = line % RY;
-    out.p[c][((long)z * N + (y0 + r)) * N + x] = rs[((x >> 1) * L + line) * 2 + (x & 1)] * out_scale;
+    const long o = ((long)z * N + (y0 + r)) * N + x;
+    const T v = rs[((x >> 1) * L + line) * 2 + (x & 1)] * out_scale;
+    if (c == 0 && out.base0) {
+      out.delta0[o] = v;
+      out.p[0][o] = out.base0[o] + v;
+    } else {
+      out.p[c][o] = v;
+    }
   }
 }
 
@@ -350,9 +371,11 @@ static void launch_c2r(const cplx<T>* spec, int nhp, int nout, const OutPtrs<T>&
 template <typename T>
 void fft_r2c_x(const SrcArgsH<T>& ah, int mode, int n, int nhp, cplx<T>* spec, const cplx<T>* tw, hipStream_t st) {
   SrcArgs<T> a;
-  a.dep = ah.dep; a.phi1 = ah.phi1; a.phi2 = ah.phi2; a.chi1 = ah.chi1; a.raw = ah.raw; a.rowsum = ah.rowsum;
+  a.dep = ah.dep; a.phi1 = ah.phi1; a.dphi1 = ah.dphi1; a.chi1 = ah.chi1; a.raw = ah.raw; a.rowsum = ah.rowsum;
   a.kap = (T)ah.kap; a.ebar = (T)ah.ebar; a.hc = (T)ah.hc; a.inv_dt = (T)ah.inv_dt; a.inv_dtl = (T)ah.inv_dtl;
   a.half_n = (T)(0.5 * n);
+  a.n2 = (T)((double)n * n);
+  a.incr = ah.incr;
   switch (n) {
 #define X(NN) case NN: launch_r2c<T, NN>(a, mode, spec, nhp, tw, st); break;
     GPM_FOR_EACH_N(X)
@@ -371,9 +394,11 @@ void fft_cols(int n, int nhp, cplx<T>* spec, int ncomp, bool inv, bool along_z, 
 
 template <typename T>
 void fft_c2r_x(int n, int nhp, const cplx<T>* spec, int nout, T* const* outp, double out_scale, const cplx<T>* tw,
-               hipStream_t st) {
+               hipStream_t st, const T* base0, T* delta0) {
   OutPtrs<T> o;
   for (int i = 0; i < 8; ++i) o.p[i] = (i < nout) ? outp[i] : nullptr;
+  o.base0 = base0;
+  o.delta0 = base0 ? delta0 : nullptr;
   switch (n) {
 #define X(NN) case NN: launch_c2r<T, NN>(spec, nhp, nout, o, (T)out_scale, tw, st); break;
     GPM_FOR_EACH_N(X)
@@ -400,7 +425,8 @@ void fft_inverse(int n, int nhp, cplx<T>* spec, int nout, T* const* outp, double
 #define GPM_FFT_INST(T)                                                                                          \
   template void fft_r2c_x<T>(const SrcArgsH<T>&, int, int, int, cplx<T>*, const cplx<T>*, hipStream_t);          \
   template void fft_cols<T>(int, int, cplx<T>*, int, bool, bool, const cplx<T>*, hipStream_t);                   \
-  template void fft_c2r_x<T>(int, int, const cplx<T>*, int, T* const*, double, const cplx<T>*, hipStream_t);      \
+  template void fft_c2r_x<T>(int, int, const cplx<T>*, int, T* const*, double, const cplx<T>*, hipStream_t,       \
+                             const T*, T*);                                                                      \
   template void fft_forward<T>(const SrcArgsH<T>&, int, int, int, cplx<T>*, int, const cplx<T>*, hipStream_t);    \
   template void fft_inverse<T>(int, int, cplx<T>*, int, T* const*, double, const cplx<T>*, hipStream_t);
 GPM_FFT_INST(float)

@@ -20,11 +20,12 @@ template <typename T>
 struct SrcArgsH {
   const T* dep = nullptr;
   const T* phi1 = nullptr;
-  const T* phi2 = nullptr;
+  const T* dphi1 = nullptr;  // increment phi_{n-1} - phi_{n-2} of the lagged solve
   const T* chi1 = nullptr;
   const T* raw = nullptr;
   double* rowsum = nullptr;
   double kap = 0, ebar = 0, hc = 0, inv_dt = 0, inv_dtl = 0;
+  int incr = 0;              // source of the increment phi_n - phi_{n-1} instead of phi_n
 };
 
 // ---- fft.hip ----
@@ -36,10 +37,11 @@ void fft_r2c_x(const SrcArgsH<T>& a, int mode, int n, int nhp, cplx<T>* spec, co
 // of c components is one array with rows of c * nhp values)
 template <typename T>
 void fft_cols(int n, int nhp, cplx<T>* spec, int ncomp, bool inv, bool along_z, const cplx<T>* tw, hipStream_t st);
-// pass X inverse of nout interleaved components into separate real arrays
+// pass X inverse of nout interleaved components into separate real arrays; with base0 non-null,
+// component 0 is an increment: outp[0] = base0 + value, and the value itself goes to delta0
 template <typename T>
 void fft_c2r_x(int n, int nhp, const cplx<T>* spec, int nout, T* const* outp, double out_scale, const cplx<T>* tw,
-               hipStream_t st);
+               hipStream_t st, const T* base0 = nullptr, T* delta0 = nullptr);
 template <typename T>
 void fft_forward(const SrcArgsH<T>& a, int mode, int n, int nhp, cplx<T>* spec, int ncomp, const cplx<T>* tw,
                  hipStream_t st);
@@ -73,6 +75,8 @@ struct SolveArgs {
   const double* dc;
   double kap_a2, n3_ebar;
   double* phibar_out; // FP64 mean of the new phi (may be null)
+  int incr;           // the phi source is that of the increment phi_n - phi_{n-1}: the FP64 mean
+                      // of the solution is added to the previous mean in phibar_out
   // tensor state: records (h+, hx, pi+, pix) of the polarisation amplitudes and their
   // time derivatives at state_index
   cplx<T>* hst;

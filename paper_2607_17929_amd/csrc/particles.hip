@@ -173,12 +173,20 @@ __global__ __launch_bounds__(DEP_NT, DEP_MIN_WAVES) void deposit_kernel(Particle
   }
   __syncthreads();
   const uint32_t total = row_off[ROWS];
-  // 2. accumulate chunk by chunk
-  T acc[DEP_VPT][NC];
+  // 2. accumulate chunk by chunk.  n00 and n0i are summed in FP64 (each product w q in T): they
+  //    feed phi and B, and the lagged time derivative of phi is the difference of two successive
+  //    solutions, which would carry the rounding of two independent FP32 sums over a crowded cell
+  //    amplified by |phi| / |phi_n - phi_{n-1}|; the stresses are summed in T.
+  constexpr int N4 = NC < 4 ? NC : 4, N6 = NC > 4 ? NC - 4 : 1;
+  double accd[DEP_VPT][N4];
+  T acc[DEP_VPT][N6];
 #pragma unroll
-  for (int k = 0; k < DEP_VPT; ++k)
+  for (int k = 0; k < DEP_VPT; ++k) {
 #pragma unroll
-    for (int c = 0; c < NC; ++c) acc[k][c] = (T)0;
+    for (int c = 0; c < N4; ++c) accd[k][c] = 0.0;
+#pragma unroll
+    for (int c = 0; c < N6; ++c) acc[k][c] = (T)0;
+  }
   const double ad = a64;  // the FP64 energy sum takes the scale factor in FP64
   double e_own = 0.0;
   for (uint32_t c0 = 0; c0 < total; c0 += CAP) {
@@ -261,14 +269,15 @@ __global__ __launch_bounds__(DEP_NT, DEP_MIN_WAVES) void deposit_kernel(Particle
             const T wz = dz == 0 ? fr.z : (T)1 - fr.z;
             const T w = wx * wy * wz;
             if constexpr (NC == 1) {
-              acc[k][0] += w * a;
+              accd[k][0] += (double)(w * a);
             } else {
               const V4<T> mo = smo[l];
               const T wi = w * fr.w;
               const T wux = wi * mo.y, wuy = wi * mo.z, wuz = wi * mo.w;
-              acc[k][0] += w * mo.x; acc[k][1] += w * mo.y; acc[k][2] += w * mo.z; acc[k][3] += w * mo.w;
-              acc[k][4] += wux * mo.y; acc[k][5] += wux * mo.z; acc[k][6] += wux * mo.w;
-              acc[k][7] += wuy * mo.z; acc[k][8] += wuy * mo.w; acc[k][9] += wuz * mo.w;
+              accd[k][0] += (double)(w * mo.x); accd[k][1] += (double)(w * mo.y);
+              accd[k][2] += (double)(w * mo.z); accd[k][3] += (double)(w * mo.w);
+              acc[k][0] += wux * mo.y; acc[k][1] += wux * mo.z; acc[k][2] += wux * mo.w;
+              acc[k][3] += wuy * mo.z; acc[k][4] += wuy * mo.w; acc[k][5] += wuz * mo.w;
             }
           }
         }
@@ -286,10 +295,14 @@ __global__ __launch_bounds__(DEP_NT, DEP_MIN_WAVES) void deposit_kernel(Particle
     if (accumulate) {
       // a further species: its sums, weighted by its particle mass over the first species', are added
 #pragma unroll
-      for (int c = 0; c < NC; ++c) dep[c * n3 + o] += w * acc[k][c];
+      for (int c = 0; c < N4; ++c) dep[c * n3 + o] = (T)((double)dep[c * n3 + o] + wd * accd[k][c]);
+#pragma unroll
+      for (int c = 4; c < NC; ++c) dep[c * n3 + o] += w * acc[k][c - 4];
     } else {
 #pragma unroll
-      for (int c = 0; c < NC; ++c) dep[c * n3 + o] = acc[k][c];
+      for (int c = 0; c < N4; ++c) dep[c * n3 + o] = (T)accd[k][c];
+#pragma unroll
+      for (int c = 4; c < NC; ++c) dep[c * n3 + o] = acc[k][c - 4];
     }
   }
   if (esum) {

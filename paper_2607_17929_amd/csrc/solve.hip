@@ -107,7 +107,7 @@ __device__ __forceinline__ void solve_mode(const SolveArgs<T>& a, int kx, int ky
       const double src0 = a.dc[0] + a.kap_a2 * a.dc[2] - a.n3_ebar;
       const double mean = src0 / d0 * a.inv_n3;
       phi = mk<T>((T)mean, 0);
-      if (a.phibar_out) a.phibar_out[0] = mean;
+      if (a.phibar_out) a.phibar_out[0] = a.incr ? a.phibar_out[0] + mean : mean;
     }
     // chi: scalar projection of Sigma
     const cplx<T>* sg = src + 1;
