@@ -68,38 +68,27 @@ void launch_ingest(const double* pos_aos, const T* u_aos, const uint32_t* ids, l
 }
 
 // ---------------------------------------------------------------------------
-// CIC deposit without atomics.  A workgroup owns a TX x TY x TZ block of
-// vertices; the particles of the (TX+1)(TY+1)(TZ+1) cells touching it form
-// (TY+1)(TZ+1) cell rows, each two contiguous ranges of the cell-sorted store
-// (the cell below the block in x, then the block's own x-range).  They are
-// streamed through LDS in chunks (cell fractions, momenta, energy).  Each
-// thread owns whole vertices and sums, in registers, the contributions of the
-// particles of the vertex's 8 adjacent cells -- 4 contiguous ranges, one per
-// cell row -- over all chunks, then stores the 10 components once.
+// CIC deposit without atomics, streamed along z.  A workgroup owns a column of
+// TX x TY vertices (x, y) over zb vertex planes and walks the cell planes
+// z0 - 1 .. z0 + zb - 1 in order.  The particles of one cell plane that touch
+// the column -- TY + 1 cell rows, each the halo cell x0 - 1 and the cells
+// x0 .. x0 + TX - 1, i.e. two contiguous ranges of the cell-sorted store -- are
+// staged in LDS (cell fractions, energy, momentum and the stresses u_i u_j / e),
+// and each thread, owning one vertex column, sums the contributions of the
+// particles of its 4 cells of the plane in one loop over both cell rows:
+// weight (1 - f_z) to the vertex on the plane's lower face, f_z to the one on
+// its upper face.  A vertex plane is complete after the cell planes below and
+// above it and is stored then, so every cell plane is read once per column.
+// While a plane is summed, the particles of the next plane are being loaded
+// into registers and the cell offsets of the plane after the next one too (row
+// offsets of the staged lists are scanned in LDS, three planes in flight).
+// Only cell_start and the particle arrays are read; each vertex is written once.
 // ---------------------------------------------------------------------------
-constexpr int DEP_TX = 16, DEP_TY = 4, DEP_TZ = 8, DEP_NT = 256;
-constexpr int DEP_ROWS = (DEP_TY + 1) * (DEP_TZ + 1);
-constexpr int DEP_CX = DEP_TX + 1;
-constexpr int DEP_NV = DEP_TX * DEP_TY * DEP_TZ;
-constexpr int DEP_VPT = DEP_NV / DEP_NT;  // vertices per thread
-static_assert(DEP_NV % DEP_NT == 0, "whole vertices per thread");
+constexpr int DEP_NT = 256;                  // one vertex column per thread
+template <typename T> constexpr int dep_cap() { return sizeof(T) == 4 ? 512 : 256; }  // staged particles per chunk
+constexpr int DEP_ZB = 16;                   // vertex planes per workgroup (fewer on small meshes)
 
-// Staged particles per chunk.  512 keeps the FP32 kernel's LDS at 23 KB, so that six workgroups
-// fit a CU, and the launch bound below asks for six waves per SIMD (80 VGPRs, 12 bytes per lane of
-// spills): measured at 512^3 it runs 7 % faster than 1024 records at four waves per SIMD.  The FP64
-// kernel stays at four waves (its 39 KB of LDS allow no more).
-template <typename T> constexpr int dep_capacity() { return 512; }
-constexpr int DEP_MIN_WAVES = 6;
-
-// largest r in [0, R) with off[r] <= i, for a non-decreasing off with off[0] = 0 <= i (R <= 64)
-template <int R>
-__device__ __forceinline__ int row_of(const uint32_t* off, uint32_t i) {
-  int lo = 0;
-#pragma unroll
-  for (int step = 32; step > 0; step >>= 1)
-    if (step < R && lo + step < R && off[lo + step] <= i) lo += step;
-  return lo;
-}
+__host__ __device__ constexpr int dep_tx(int n) { return n >= 32 ? 32 : 16; }
 
 // exclusive prefix of c over the first wave's lanes (R <= 64 rows): off[0] = 0, off[r + 1] = sum_{q <= r} c_q
 template <int R>
@@ -114,230 +103,329 @@ __device__ __forceinline__ void wave_row_offsets(uint32_t c, uint32_t* off) {
   if (lane == 0) off[0] = 0;
 }
 
-template <typename T, int NC, bool REL>
-__global__ __launch_bounds__(DEP_NT, DEP_MIN_WAVES) void deposit_kernel(Particles<T> p, const uint32_t* __restrict__ cell_start, int n,
-                                                         T a, double a64, T w, double wd, int accumulate,
+// largest r in [0, R) with off[r] <= i, for a non-decreasing off with off[0] = 0 <= i (R <= 64)
+template <int R>
+__device__ __forceinline__ int row_of(const uint32_t* off, uint32_t i) {
+  int lo = 0;
+#pragma unroll
+  for (int step = 32; step > 0; step >>= 1)
+    if (step < R && lo + step < R && off[lo + step] <= i) lo += step;
+  return lo;
+}
+
+// One particle in registers (loaded for the next plane while the current one is summed).
+template <typename T>
+struct DepPart {
+  double x, y, z;
+  T ux, uy, uz;
+};
+
+template <typename T, int NC, bool REL, int TX>
+__global__ __launch_bounds__(DEP_NT) void deposit_kernel(Particles<T> p, const uint32_t* __restrict__ cell_start, int n,
+                                                         int zb, T a, double a64, T w, double wd, int accumulate,
                                                          T* __restrict__ dep, double* __restrict__ esum) {
-  constexpr int CAP = dep_capacity<T>();
-  constexpr int TX = DEP_TX, TY = DEP_TY, CX = DEP_CX, ROWS = DEP_ROWS, GW = TX + 3;
-  constexpr int NQ = (ROWS * GW + DEP_NT - 1) / DEP_NT;  // cell_start reads per thread
-  constexpr int SPT = CAP / DEP_NT;                      // staged particles per thread and chunk
-  static_assert(ROWS <= 64 && CAP % DEP_NT == 0, "row scan in one wave, whole staging rounds");
-  // staged per particle: (cell fractions, 1/e) and (e, u), one 4-vector each
-  __shared__ V4<T> sfr[CAP], smo[NC > 1 ? CAP : 1];
-  __shared__ uint32_t cstart[ROWS * CX];  // row-relative staged start of local cell (row, lx); lx = 0 is cell x0 - 1
-  __shared__ uint32_t gcs[ROWS * GW];     // halo start/end, then starts of cells x0 .. x0 + TX
-  __shared__ uint32_t row_off[ROWS + 1];
+  constexpr int TY = DEP_NT / TX, ROWS = TY + 1, RW = TX + 3;  // raw offsets per row: halo start/end, x0 .. x0 + TX
+  constexpr int CAP = dep_cap<T>(), SPT = CAP / DEP_NT;
+  constexpr int NQ = (ROWS * RW + DEP_NT - 1) / DEP_NT;
+  constexpr int N4 = NC < 4 ? NC : 4, N6 = NC > 4 ? NC - 4 : 1;
+  constexpr int WX = TX >= 16 ? 16 : TX, WY = 64 / WX;         // a wave's vertex columns: WX x WY
+  static_assert(ROWS <= 64 && CAP % DEP_NT == 0 && TX % WX == 0 && TY % WY == 0, "tile shape");
+  constexpr int C4 = NC > 1 ? CAP : 1;
+  __shared__ V4<T> sfr[CAP];                  // f_x, f_y, f_z, -
+  __shared__ V4<T> sq[C4], ss[C4];            // (e, u_x, u_y, u_z), (u_x u_x, u_x u_y, u_x u_z, u_y u_y) / e
+  __shared__ T ss2[C4][2];                    // (u_y u_z, u_z u_z) / e
+  __shared__ uint32_t raw[3][ROWS][RW];       // cell offsets of the planes in flight (plane mod 3)
+  __shared__ uint32_t roff[3][ROWS + 1];      // staged offset of each row
   __shared__ double red[DEP_NT / 64];
   const int m = n - 1;
   int bx, by, bz;
   xcd_block3(bx, by, bz);
-  const int x0 = bx * TX, y0 = by * TY, z0 = bz * DEP_TZ;
-  const int tid = threadIdx.x;
-  // 1. cell_start values of every touching cell, all reads in flight at once.  Local cell (lx, ly, lz)
-  //    is global (x0 - 1 + lx, y0 - 1 + ly, z0 - 1 + lz); on a 16^3 mesh the block spans x and the
-  //    first and last local x-layers are the same cells, but each vertex reads each cell once.
-  {
-    uint32_t gv[NQ];
+  const int x0 = bx * TX, y0 = by * TY, zs = bz * zb;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  // waves of WX x WY vertex columns (the clustered occupancy is less uneven over squarer patches)
+  const int lvx = (wave % (TX / WX)) * WX + lane % WX, lvy = (wave / (TX / WX)) * WY + lane / WX;
+  const long nn = (long)n * n, n3 = nn * n;
+
+  // raw cell offsets of cell plane cz: row r is cell row y0 - 1 + r; entry 0/1 = start/end of the
+  // halo cell x0 - 1, entry 2 + j = start of cell x0 + j (j = 0 .. TX)
+  auto load_raw = [&](int cz, uint32_t* v) {
 #pragma unroll
     for (int k = 0; k < NQ; ++k) {
       const int q = tid + k * DEP_NT;
-      if (q < ROWS * GW) {
-        const int r = q / GW, j = q % GW;
-        const int ly = r % (TY + 1), lz = r / (TY + 1);
-        const int cy = (y0 - 1 + ly) & m, cz = (z0 - 1 + lz) & m;
-        const uint32_t rb = ((uint32_t)cz * n + cy) * (uint32_t)n;
-        const uint32_t hc = rb + ((x0 - 1) & m);
-        gv[k] = cell_start[j == 0 ? hc : (j == 1 ? hc + 1 : rb + x0 + (j - 2))];
+      if (q < ROWS * RW) {
+        const int r = q / RW, j = q - r * RW;
+        const uint32_t rb = ((uint32_t)(cz & m) * (uint32_t)n + (uint32_t)((y0 - 1 + r) & m)) * (uint32_t)n;
+        const uint32_t hc = rb + (uint32_t)((x0 - 1) & m);
+        v[k] = cell_start[j == 0 ? hc : (j == 1 ? hc + 1 : rb + x0 + (j - 2))];
       }
     }
+  };
+  auto store_raw = [&](int b, const uint32_t* v) {
 #pragma unroll
     for (int k = 0; k < NQ; ++k) {
       const int q = tid + k * DEP_NT;
-      if (q < ROWS * GW) gcs[q] = gv[k];
+      if (q < ROWS * RW) raw[b][q / RW][q % RW] = v[k];
     }
-  }
-  __syncthreads();
-  for (int q = tid; q < ROWS * CX; q += DEP_NT) {
-    const int r = q / CX, lx = q % CX;
-    const uint32_t* g = gcs + r * GW;
-    cstart[q] = (lx == 0) ? 0u : (g[1] - g[0]) + (g[lx + 1] - g[2]);
-  }
-  if (tid < 64) {
-    uint32_t c = 0;
-    if (tid < ROWS) {
-      const uint32_t* g = gcs + tid * GW;
-      c = (g[1] - g[0]) + (g[TX + 2] - g[2]);
+  };
+  // staged offsets of the rows of the plane in buffer b (first wave)
+  auto scan_rows = [&](int b) {
+    if (tid < 64) {
+      uint32_t c = 0;
+      if (tid < ROWS) c = (raw[b][tid][1] - raw[b][tid][0]) + (raw[b][tid][2 + TX] - raw[b][tid][2]);
+      wave_row_offsets<ROWS>(c, roff[b]);
     }
-    wave_row_offsets<ROWS>(c, row_off);
-  }
-  __syncthreads();
-  const uint32_t total = row_off[ROWS];
-  // 2. accumulate chunk by chunk.  n00 and n0i are summed in FP64 (each product w q in T): they
-  //    feed phi and B, and the lagged time derivative of phi is the difference of two successive
-  //    solutions, which would carry the rounding of two independent FP32 sums over a crowded cell
-  //    amplified by |phi| / |phi_n - phi_{n-1}|; the stresses are summed in T.
-  constexpr int N4 = NC < 4 ? NC : 4, N6 = NC > 4 ? NC - 4 : 1;
-  double accd[DEP_VPT][N4];
-  T acc[DEP_VPT][N6];
-#pragma unroll
-  for (int k = 0; k < DEP_VPT; ++k) {
-#pragma unroll
-    for (int c = 0; c < N4; ++c) accd[k][c] = 0.0;
-#pragma unroll
-    for (int c = 0; c < N6; ++c) acc[k][c] = (T)0;
-  }
-  const double ad = a64;  // the FP64 energy sum takes the scale factor in FP64
+  };
+  // global index of staged particle i of the plane in buffer b; own: in a cell of this column
+  auto source_of = [&](int b, uint32_t i, bool& own) {
+    const int r = row_of<ROWS + 1>(roff[b], i);
+    const uint32_t k = i - roff[b][r];
+    const uint32_t hs = raw[b][r][0], hn = raw[b][r][1] - hs;
+    own = r > 0 && k >= hn;
+    return k < hn ? hs + k : raw[b][r][2] + (k - hn);
+  };
+  auto load_part = [&](uint32_t g, DepPart<T>& d) {
+    d.x = p.px[g]; d.y = p.py[g]; d.z = p.pz[g];
+    if constexpr (NC > 1) { d.ux = p.ux[g]; d.uy = p.uy[g]; d.uz = p.uz[g]; }
+  };
   double e_own = 0.0;
-  for (uint32_t c0 = 0; c0 < total; c0 += CAP) {
-    const uint32_t c1 = min(total, c0 + (uint32_t)CAP);
-    // staging: locate, load (all loads of the thread in flight), then convert and store
-    uint32_t gi[SPT];
-    bool own[SPT];
-#pragma unroll
-    for (int s2 = 0; s2 < SPT; ++s2) {
-      const uint32_t i = c0 + tid + s2 * DEP_NT;
-      gi[s2] = 0;
-      own[s2] = false;
-      if (i < c1) {
-        const int r = row_of<ROWS>(row_off, i);
-        const uint32_t k = i - row_off[r];
-        const uint32_t* g = gcs + r * GW;
-        const uint32_t halo_n = g[1] - g[0];
-        gi[s2] = (k < halo_n) ? g[0] + k : g[2] + (k - halo_n);
-        // the block's own cells: not the halo layers below it in y, z or x
-        own[s2] = (r % (TY + 1)) > 0 && (r / (TY + 1)) > 0 && k >= halo_n;
+  auto stage = [&](uint32_t l, const DepPart<T>& d, bool own) {
+    const double sx = d.x * (double)n, sy = d.y * (double)n, sz = d.z * (double)n;
+    V4<T> fr;
+    fr.x = (T)(sx - floor(sx));
+    fr.y = (T)(sy - floor(sy));
+    fr.z = (T)(sz - floor(sz));
+    fr.w = (T)0;
+    sfr[l] = fr;
+    if constexpr (NC > 1) {
+      const T vx = d.ux, vy = d.uy, vz = d.uz;
+      const T u2 = vx * vx + vy * vy + vz * vz;
+      const T e = REL ? sqrt(a * a + u2) : a;
+      const T ie = rcp(e);
+      V4<T> q, t;
+      q.x = e; q.y = vx; q.z = vy; q.w = vz;
+      const T ix = vx * ie, iy = vy * ie;
+      t.x = ix * vx; t.y = ix * vy; t.z = ix * vz; t.w = iy * vy;
+      sq[l] = q;
+      ss[l] = t;
+      ss2[l][0] = iy * vz;
+      ss2[l][1] = vz * ie * vz;
+      // FP64 sum over the particles of this column's own cells (the homogeneous source of phi is its
+      // small difference from the background, so e is formed from the momenta in FP64 here)
+      if (own) {
+        const double dx = vx, dy = vy, dz = vz;
+        e_own += REL ? sqrt(a64 * a64 + dx * dx + dy * dy + dz * dz) : a64;
       }
     }
-    double px[SPT], py[SPT], pz[SPT];
-    T ux[SPT], uy[SPT], uz[SPT];
+  };
+
+  // sums of the vertex on the current plane's lower face (lo) and upper face (hi): n00 and n0i in FP64
+  // (each product w q in T), the stresses in T.  The lagged time derivative of phi is the change
+  // between two solves, which would otherwise carry the independent rounding of two FP32 sums over a
+  // crowded cell amplified by |phi| / |phi_n - phi_{n-1}|.
+  double lo4[N4], hi4[N4];
+  T lo6[N6], hi6[N6];
 #pragma unroll
-    for (int s2 = 0; s2 < SPT; ++s2) {
-      if (c0 + tid + s2 * DEP_NT < c1) {
-        px[s2] = p.px[gi[s2]]; py[s2] = p.py[gi[s2]]; pz[s2] = p.pz[gi[s2]];
-        if constexpr (NC > 1) { ux[s2] = p.ux[gi[s2]]; uy[s2] = p.uy[gi[s2]]; uz[s2] = p.uz[gi[s2]]; }
+  for (int c = 0; c < N4; ++c) lo4[c] = hi4[c] = 0.0;
+#pragma unroll
+  for (int c = 0; c < N6; ++c) lo6[c] = hi6[c] = (T)0;
+
+  // sum the staged particles [c0, c1) of the plane in buffer b: the thread's cells are, in the cell
+  // rows lvy (below the vertex: weight f_y) and lvy + 1 (1 - f_y), the local cells lvx (x0 + lvx - 1,
+  // weight f_x) and lvx + 1 (1 - f_x), one contiguous staged range per row
+  auto accumulate_chunk = [&](int b, uint32_t c0, uint32_t c1) {
+    uint32_t beg[2], spl[2], len[2];
+#pragma unroll
+    for (int dy = 0; dy < 2; ++dy) {
+      const int r = lvy + dy;
+      const uint32_t* rr = raw[b][r];
+      const uint32_t hn = rr[1] - rr[0], m0 = rr[2], ro = roff[b][r];
+      const uint32_t s0 = ro + (lvx == 0 ? 0u : hn + (rr[1 + lvx] - m0));
+      const uint32_t s1 = ro + hn + (rr[2 + lvx] - m0);
+      const uint32_t s2 = ro + hn + (rr[3 + lvx] - m0);
+      const uint32_t bb = max(s0, c0), ee = min(s2, c1);
+      beg[dy] = bb - c0;
+      spl[dy] = s1 > c0 ? s1 - c0 : 0u;
+      len[dy] = ee > bb ? ee - bb : 0u;
+    }
+    const uint32_t tot = len[0] + len[1];
+    for (uint32_t j = 0; j < tot; ++j) {
+      const bool r1 = j >= len[0];
+      const uint32_t l = r1 ? beg[1] + (j - len[0]) : beg[0] + j;
+      const V4<T> fr = sfr[l];
+      const T wx = l < (r1 ? spl[1] : spl[0]) ? fr.x : (T)1 - fr.x;
+      const T wy = r1 ? (T)1 - fr.y : fr.y;
+      const T wxy = wx * wy;
+      const T wh = wxy * fr.z, wl = wxy - wh;  // f_z and (1 - f_z) shares
+      if constexpr (NC == 1) {
+        lo4[0] += (double)(wl * a);
+        hi4[0] += (double)(wh * a);
+      } else {
+        const V4<T> q = sq[l], t = ss[l];
+        const T t4 = ss2[l][0], t5 = ss2[l][1];
+        const double dl = (double)wl, dh = (double)wh;
+        const double q0 = (double)q.x, q1 = (double)q.y, q2 = (double)q.z, q3 = (double)q.w;
+        lo4[0] = fma(dl, q0, lo4[0]); lo4[1] = fma(dl, q1, lo4[1]);
+        lo4[2] = fma(dl, q2, lo4[2]); lo4[3] = fma(dl, q3, lo4[3]);
+        hi4[0] = fma(dh, q0, hi4[0]); hi4[1] = fma(dh, q1, hi4[1]);
+        hi4[2] = fma(dh, q2, hi4[2]); hi4[3] = fma(dh, q3, hi4[3]);
+        lo6[0] += wl * t.x; lo6[1] += wl * t.y; lo6[2] += wl * t.z;
+        lo6[3] += wl * t.w; lo6[4] += wl * t4; lo6[5] += wl * t5;
+        hi6[0] += wh * t.x; hi6[1] += wh * t.y; hi6[2] += wh * t.z;
+        hi6[3] += wh * t.w; hi6[4] += wh * t4; hi6[5] += wh * t5;
       }
     }
+  };
+
+  // prologue: offsets of the first three planes, row offsets of the first two, the first plane's
+  // particles in flight
+  {
+    uint32_t v[NQ];
 #pragma unroll
-    for (int s2 = 0; s2 < SPT; ++s2) {
-      if (c0 + tid + s2 * DEP_NT < c1) {
-        const uint32_t l = tid + s2 * DEP_NT;
-        const double sx = px[s2] * (double)n, sy = py[s2] * (double)n, sz = pz[s2] * (double)n;
-        V4<T> fr;
-        fr.x = (T)(sx - floor(sx));
-        fr.y = (T)(sy - floor(sy));
-        fr.z = (T)(sz - floor(sz));
-        fr.w = (T)0;
-        if constexpr (NC > 1) {
-          const T vx = ux[s2], vy = uy[s2], vz = uz[s2];
-          const T e = REL ? sqrt(a * a + vx * vx + vy * vy + vz * vz) : a;
-          fr.w = rcp(e);
-          V4<T> mo;
-          mo.x = e; mo.y = vx; mo.z = vy; mo.w = vz;
-          smo[l] = mo;
-          // FP64 energy sum over the particles of the block's own cells
-          if (own[s2]) {
-            const double dx = vx, dy = vy, dz = vz;
-            e_own += REL ? sqrt(ad * ad + dx * dx + dy * dy + dz * dz) : ad;
-          }
-        }
-        sfr[l] = fr;
+    for (int q = 0; q < 3; ++q) {
+      if (q <= zb) {
+        load_raw(zs - 1 + q, v);
+        store_raw(q, v);
       }
     }
-    __syncthreads();
-#pragma unroll
-    for (int k = 0; k < DEP_VPT; ++k) {
-      const int v = tid + k * DEP_NT;
-      const int lvx = v % TX, lvy = (v / TX) % TY, lvz = v / (TX * TY);
-#pragma unroll
-      for (int dz = 0; dz < 2; ++dz) {
-#pragma unroll
-        for (int dy = 0; dy < 2; ++dy) {
-          // cell row (lvy + dy, lvz + dz); dy = 0 is the row below the vertex (vertex = upper y corner)
-          const int rr = (lvz + dz) * (TY + 1) + (lvy + dy);
-          const int cb = rr * CX + lvx;  // cell below the vertex in x (vertex = its upper x corner)
-          const uint32_t ro = row_off[rr];
-          const uint32_t s1 = ro + cstart[cb + 1];
-          const uint32_t s2 = ro + ((lvx + 2 <= TX) ? cstart[cb + 2] : row_off[rr + 1] - ro);
-          const uint32_t b = max(ro + cstart[cb], c0), e = min(s2, c1);
-          for (uint32_t i = b; i < e; ++i) {
-            const uint32_t l = i - c0;
-            const bool upper_x = i < s1;
-            const V4<T> fr = sfr[l];
-            const T wx = upper_x ? fr.x : (T)1 - fr.x;
-            const T wy = dy == 0 ? fr.y : (T)1 - fr.y;
-            const T wz = dz == 0 ? fr.z : (T)1 - fr.z;
-            const T w = wx * wy * wz;
-            if constexpr (NC == 1) {
-              accd[k][0] += (double)(w * a);
-            } else {
-              const V4<T> mo = smo[l];
-              const T wi = w * fr.w;
-              const T wux = wi * mo.y, wuy = wi * mo.z, wuz = wi * mo.w;
-              accd[k][0] += (double)(w * mo.x); accd[k][1] += (double)(w * mo.y);
-              accd[k][2] += (double)(w * mo.z); accd[k][3] += (double)(w * mo.w);
-              acc[k][0] += wux * mo.y; acc[k][1] += wux * mo.z; acc[k][2] += wux * mo.w;
-              acc[k][3] += wuy * mo.z; acc[k][4] += wuy * mo.w; acc[k][5] += wuz * mo.w;
-            }
-          }
-        }
-      }
-    }
-    __syncthreads();
   }
-  // 3. store the block's vertices (consecutive threads -> consecutive x)
-  const long n3 = (long)n * n * n;
+  __syncthreads();
+  scan_rows(0);
+  scan_rows(1);
+  __syncthreads();
+  DepPart<T> pr[SPT];
+  bool pown[SPT];
+  {
+    const uint32_t lim = min(roff[0][ROWS], (uint32_t)CAP);
 #pragma unroll
-  for (int k = 0; k < DEP_VPT; ++k) {
-    const int v = tid + k * DEP_NT;
-    const int lvx = v % TX, lvy = (v / TX) % TY, lvz = v / (TX * TY);
-    const long o = ((long)(z0 + lvz) * n + (y0 + lvy)) * n + (x0 + lvx);
-    if (accumulate) {
-      // a further species: its sums, weighted by its particle mass over the first species', are added
-#pragma unroll
-      for (int c = 0; c < N4; ++c) dep[c * n3 + o] = (T)((double)dep[c * n3 + o] + wd * accd[k][c]);
-#pragma unroll
-      for (int c = 4; c < NC; ++c) dep[c * n3 + o] += w * acc[k][c - 4];
-    } else {
-#pragma unroll
-      for (int c = 0; c < N4; ++c) dep[c * n3 + o] = (T)accd[k][c];
-#pragma unroll
-      for (int c = 4; c < NC; ++c) dep[c * n3 + o] = acc[k][c - 4];
+    for (int s2 = 0; s2 < SPT; ++s2) {
+      const uint32_t i = tid + s2 * DEP_NT;
+      if (i < lim) {
+        bool own;
+        load_part(source_of(0, i, own), pr[s2]);
+      }
+      pown[s2] = false;  // the first plane is below the column's own cells
     }
+  }
+  uint32_t rnext[NQ];
+  for (int P = 0; P <= zb; ++P) {
+    const int b = P % 3, b1 = (P + 1) % 3, b2 = (P + 2) % 3;
+    const int cz = zs - 1 + P;
+    const uint32_t total = roff[b][ROWS];
+    // 1. the prefetched first chunk of this plane into LDS
+    {
+      const uint32_t lim = min(total, (uint32_t)CAP);
+#pragma unroll
+      for (int s2 = 0; s2 < SPT; ++s2) {
+        const uint32_t i = tid + s2 * DEP_NT;
+        if (i < lim) stage(i, pr[s2], pown[s2]);
+      }
+    }
+    __syncthreads();
+    // 2. requests for the next planes: particles of plane P + 1, cell offsets of plane P + 3
+    if (P + 1 <= zb) {
+      const uint32_t lim = min(roff[b1][ROWS], (uint32_t)CAP);
+#pragma unroll
+      for (int s2 = 0; s2 < SPT; ++s2) {
+        const uint32_t i = tid + s2 * DEP_NT;
+        pown[s2] = false;
+        if (i < lim) load_part(source_of(b1, i, pown[s2]), pr[s2]);
+      }
+    }
+    if (P + 3 <= zb) load_raw(cz + 3, rnext);
+    // 3. sum this plane: (1 - f_z) to vertex plane cz, f_z to vertex plane cz + 1 (the first plane's
+    //    lower-face sums and the last plane's upper-face sums belong to other columns and are dropped)
+    accumulate_chunk(b, 0, min(total, (uint32_t)CAP));
+    for (uint32_t c0 = CAP; c0 < total; c0 += CAP) {
+      // a crowded plane: further chunks loaded and summed in turn
+      const uint32_t c1 = min(total, c0 + (uint32_t)CAP);
+      __syncthreads();
+#pragma unroll
+      for (int s2 = 0; s2 < SPT; ++s2) {
+        const uint32_t i = c0 + tid + s2 * DEP_NT;
+        if (i < c1) {
+          bool own;
+          DepPart<T> d;
+          load_part(source_of(b, i, own), d);
+          stage(i - c0, d, own && P > 0);
+        }
+      }
+      __syncthreads();
+      accumulate_chunk(b, c0, c1);
+    }
+    // 4. vertex plane cz is complete: store it and move the upper-face sums down
+    if (P > 0) {
+      const long o = ((long)cz * n + (y0 + lvy)) * n + (x0 + lvx);
+      if (accumulate) {
+        // a further species: its sums, weighted by its particle mass over the first species', are added
+#pragma unroll
+        for (int c = 0; c < N4; ++c) dep[c * n3 + o] = (T)((double)dep[c * n3 + o] + wd * lo4[c]);
+#pragma unroll
+        for (int c = 4; c < NC; ++c) dep[c * n3 + o] += w * lo6[c - 4];
+      } else {
+#pragma unroll
+        for (int c = 0; c < N4; ++c) dep[c * n3 + o] = (T)lo4[c];
+#pragma unroll
+        for (int c = 4; c < NC; ++c) dep[c * n3 + o] = lo6[c - 4];
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < N4; ++c) { lo4[c] = hi4[c]; hi4[c] = 0.0; }
+#pragma unroll
+    for (int c = 0; c < N6; ++c) { lo6[c] = hi6[c]; hi6[c] = (T)0; }
+    __syncthreads();
+    // 5. row offsets of plane P + 2; the cell offsets of plane P + 3 replace this plane's
+    if (P + 2 <= zb) scan_rows(b2);
+    if (P + 3 <= zb) store_raw(b, rnext);
   }
   if (esum) {
     // fixed-order reduction: within each wave, then the waves' sums in order
 #pragma unroll
     for (int d = 32; d > 0; d >>= 1) e_own += __shfl_down(e_own, d);
-    if ((tid & 63) == 0) red[tid >> 6] = e_own;
+    if (lane == 0) red[wave] = e_own;
     __syncthreads();
     if (tid == 0) {
       double t = 0.0;
 #pragma unroll
-      for (int w = 0; w < DEP_NT / 64; ++w) t += red[w];
+      for (int w2 = 0; w2 < DEP_NT / 64; ++w2) t += red[w2];
       esum[(bz * gridDim.y + by) * gridDim.x + bx] = wd * t;
     }
   }
 }
 
-int deposit_blocks(int n) { return (n / DEP_TX) * (n / DEP_TY) * (n / DEP_TZ); }
+static int dep_zb(int n) { return n < DEP_ZB ? n : DEP_ZB; }
+
+int deposit_blocks(int n) {
+  const int tx = dep_tx(n), ty = DEP_NT / tx;
+  return (n / tx) * (n / ty) * (n / dep_zb(n));
+}
+
+template <typename T, int TX>
+static void launch_deposit_tx(const Particles<T>& p, const uint32_t* cell_start, int n, int ncomp, bool relativistic,
+                              double a, double weight, bool accumulate, T* dep, double* esum_part, hipStream_t st) {
+  constexpr int TY = DEP_NT / TX;
+  const int zb = dep_zb(n);
+  dim3 grid(n / TX, n / TY, n / zb);
+  const int acc = accumulate ? 1 : 0;
+  if (ncomp == 1) {
+    hipLaunchKernelGGL((deposit_kernel<T, 1, false, TX>), grid, dim3(DEP_NT), 0, st, p, cell_start, n, zb, (T)a, a,
+                       (T)weight, weight, acc, dep, (double*)nullptr);
+    return;
+  }
+  if (relativistic)
+    hipLaunchKernelGGL((deposit_kernel<T, 10, true, TX>), grid, dim3(DEP_NT), 0, st, p, cell_start, n, zb, (T)a, a,
+                       (T)weight, weight, acc, dep, esum_part);
+  else
+    hipLaunchKernelGGL((deposit_kernel<T, 10, false, TX>), grid, dim3(DEP_NT), 0, st, p, cell_start, n, zb, (T)a, a,
+                       (T)weight, weight, acc, dep, esum_part);
+}
 
 template <typename T>
 void launch_deposit(const Particles<T>& p, const uint32_t* cell_start, int n, int ncomp, bool relativistic, double a,
                     double weight, bool accumulate, T* dep, double* esum_part, hipStream_t st) {
-  dim3 grid(n / DEP_TX, n / DEP_TY, n / DEP_TZ);  // n >= 16
-  const int acc = accumulate ? 1 : 0;
-  if (ncomp == 1) {
-    hipLaunchKernelGGL((deposit_kernel<T, 1, false>), grid, dim3(DEP_NT), 0, st, p, cell_start, n, (T)a, a, (T)weight,
-                       weight, acc, dep, (double*)nullptr);
-    return;
-  }
-  if (relativistic)
-    hipLaunchKernelGGL((deposit_kernel<T, 10, true>), grid, dim3(DEP_NT), 0, st, p, cell_start, n, (T)a, a, (T)weight,
-                       weight, acc, dep, esum_part);
+  if (dep_tx(n) == 32)
+    launch_deposit_tx<T, 32>(p, cell_start, n, ncomp, relativistic, a, weight, accumulate, dep, esum_part, st);
   else
-    hipLaunchKernelGGL((deposit_kernel<T, 10, false>), grid, dim3(DEP_NT), 0, st, p, cell_start, n, (T)a, a, (T)weight,
-                       weight, acc, dep, esum_part);
+    launch_deposit_tx<T, 16>(p, cell_start, n, ncomp, relativistic, a, weight, accumulate, dep, esum_part, st);
 }
 
 // ---------------------------------------------------------------------------
