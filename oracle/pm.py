@@ -195,6 +195,28 @@ def interpolate(fields, pos: np.ndarray, n: int) -> np.ndarray:
     return out
 
 
+def interpolate_with_gradients(fields, pos: np.ndarray, n: int) -> np.ndarray:
+    """CIC interpolation, at the given positions, of each field and of its centred-difference gradient
+    (f[v + e_d] - f[v - e_d]) / (2 dx), the differences evaluated only at the corner vertices the
+    particles need (the same quantities as interpolating the full arrays of grad(f), without forming
+    them).  Returns (len(fields), 4, N_p): value, d/dx, d/dy, d/dz."""
+    flat = [np.asarray(f).reshape(-1) for f in fields]
+    out = np.zeros((len(flat), 4, pos.shape[0]))
+    h = 0.5 * n
+    for idx, w in _corners(pos, n):
+        iz, iy, ix = idx // (n * n), (idx // n) % n, idx % n
+        nb = []
+        for d, (dz, dy, dx) in enumerate(((0, 0, 1), (0, 1, 0), (1, 0, 0))):
+            up = (((iz + dz) % n) * n + (iy + dy) % n) * n + (ix + dx) % n
+            dn = (((iz - dz) % n) * n + (iy - dy) % n) * n + (ix - dx) % n
+            nb.append((up, dn))
+        for c, f in enumerate(flat):
+            out[c, 0] += w * f[idx]
+            for d, (up, dn) in enumerate(nb):
+                out[c, 1 + d] += w * (f[up].astype(np.float64) - f[dn]) * h
+    return out
+
+
 def wrap_positions(x: np.ndarray) -> np.ndarray:
     """Periodic wrap into [0, 1); a result of exactly 1.0 maps to 0.0."""
     y = x - np.floor(x)
@@ -588,32 +610,7 @@ class OracleSim:
         self.tau += dtau
 
     def _kick_drift(self, pos, u_in, a, ah, dtau, extra_gphi):
-        g = self.gathered(pos)
-        phi_p, chi_p = g[0], g[1]
-        B_p = g[2:5]
-        gphi = g[5:8].copy()
-        gchi = g[8:11]
-        G = g[11:20].reshape(3, 3, -1)  # G[i][j] = d_i B_j
-        if extra_gphi is not None:
-            gphi = gphi + extra_gphi
-        u = u_in.T.copy()
-        if self.physics == NEWTONIAN:
-            u = u - dtau * a * gphi
-            x = pos.T + dtau * u / ah
-        else:
-            u2 = np.sum(u * u, axis=0)
-            e = np.sqrt(a * a + u2)
-            force = -((a * a + 2.0 * u2) / e) * gphi + e * gchi
-            if self.physics == FULL:
-                force = force - np.einsum("j...,ij...->i...", u, G)
-            u = u + dtau * force
-            u2 = np.sum(u * u, axis=0)
-            eh = np.sqrt(ah * ah + u2)
-            vel = (u / eh) * (1.0 + (3.0 - u2 / (eh * eh)) * phi_p - chi_p)
-            if self.physics == FULL:
-                vel = vel + B_p
-            x = pos.T + dtau * vel
-        return wrap_positions(x.T.copy()), u.T.copy()
+        return kick_drift(self.gathered(pos), pos, u_in, a, ah, dtau, self.physics, extra_gphi)
 
     # -- whole step ---------------------------------------------------------
     def step(self, dtau: float, dtau_prev: float | None = None):
@@ -634,3 +631,44 @@ class OracleSim:
     def species2(self):
         """Positions and momenta of the second species (in their given order)."""
         return self.pos2, self.u2
+
+
+def gathered_pointwise(phi, chi, B, pos: np.ndarray, n: int) -> np.ndarray:
+    """The rows of OracleSim.gathered (phi, chi, B (3), g_phi (3), g_chi (3), G_ij = d_i B_j (9)) with the
+    centred differences evaluated only at the vertices the particles need: the same quantities, for
+    meshes whose full gradient arrays would not fit in host memory."""
+    g = interpolate_with_gradients([phi, chi] + list(B), pos, n)
+    rows = [g[0, 0], g[1, 0], g[2, 0], g[3, 0], g[4, 0]]
+    rows += [g[0, 1], g[0, 2], g[0, 3], g[1, 1], g[1, 2], g[1, 3]]
+    rows += [g[2 + j, 1 + i] for i in range(3) for j in range(3)]
+    return np.stack(rows)
+
+
+def kick_drift(g, pos, u_in, a, ah, dtau, physics, extra_gphi=None):
+    """Kick and drift of particles from their gathered fields g (the rows of OracleSim.gathered); the
+    equations of OracleSim.update.  Returns (wrapped positions, momenta)."""
+    phi_p, chi_p = g[0], g[1]
+    B_p = g[2:5]
+    gphi = g[5:8].copy()
+    gchi = g[8:11]
+    G = g[11:20].reshape(3, 3, -1)  # G[i][j] = d_i B_j
+    if extra_gphi is not None:
+        gphi = gphi + extra_gphi
+    u = u_in.T.copy()
+    if physics == NEWTONIAN:
+        u = u - dtau * a * gphi
+        x = pos.T + dtau * u / ah
+    else:
+        u2 = np.sum(u * u, axis=0)
+        e = np.sqrt(a * a + u2)
+        force = -((a * a + 2.0 * u2) / e) * gphi + e * gchi
+        if physics == FULL:
+            force = force - np.einsum("j...,ij...->i...", u, G)
+        u = u + dtau * force
+        u2 = np.sum(u * u, axis=0)
+        eh = np.sqrt(ah * ah + u2)
+        vel = (u / eh) * (1.0 + (3.0 - u2 / (eh * eh)) * phi_p - chi_p)
+        if physics == FULL:
+            vel = vel + B_p
+        x = pos.T + dtau * vel
+    return wrap_positions(x.T.copy()), u.T.copy()

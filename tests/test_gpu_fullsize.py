@@ -29,7 +29,7 @@ import pytest
 from oracle import pm as opm
 from synth import lattice_positions, plane_wave_particles, spectrum_power_law_m2, zeldovich_particles
 from synth.ics import eds_a_of_tau
-from tests.helpers import periodic_max_dx, rel_l2
+from tests.helpers import assert_fields, field_errors, periodic_max_dx, rel_l2
 from tests.test_oracle_pins import _linear_recursion, _project_wave
 
 pytestmark = pytest.mark.gpu
@@ -83,17 +83,17 @@ def test_fft_512_sampled_modes(precision):
         assert err < (1e-12 if precision == "fp64" else 1e-5), ((kx, ky, kz), err)
 
 
-def _region_deposit(pos, u, a, z0, y0, x0, R):
+def _region_deposit(pos, u, a, z0, y0, x0, R, n=N):
     """Oracle CIC sums at the vertices [z0, z0+R) x [y0, y0+R) x [x0, x0+R) from the particles of
     the cells that touch them (cells z0-1 .. z0+R-1 in each axis, periodic)."""
-    base, _ = opm.cic_cells(pos, N)
-    rel = (base - np.array([x0 - 1, y0 - 1, z0 - 1])) % N
+    base, _ = opm.cic_cells(pos, n)
+    rel = (base - np.array([x0 - 1, y0 - 1, z0 - 1])) % n
     sel = np.all(rel < R + 1, axis=1)
     p, q = pos[sel], opm.deposit_quantities(u[sel], a)
     out = np.zeros((10, R, R, R))
-    for idx, w in opm._corners(p, N):
-        iz, iy, ix = idx // (N * N), (idx // N) % N, idx % N
-        lz, ly, lx = (iz - z0) % N, (iy - y0) % N, (ix - x0) % N
+    for idx, w in opm._corners(p, n):
+        iz, iy, ix = idx // (n * n), (idx // n) % n, idx % n
+        lz, ly, lx = (iz - z0) % n, (iy - y0) % n, (ix - x0) % n
         ok = (lz < R) & (ly < R) & (lx < R)
         for c in range(10):
             np.add.at(out[c], (lz[ok], ly[ok], lx[ok]), w[ok] * q[c, ok])
@@ -232,6 +232,61 @@ def test_solve_512_clustered_against_oracle(clustered, precision):
          f"energy sum - 1 {dep[0].sum() / sim_energy(pos.shape[0], u.astype(np.float32 if precision == 'fp32' else np.float64), tau) - 1:.2e}")
     for k, err in errs.items():
         assert err < (1e-10 if precision == "fp64" else 1e-5), (k, err)
+
+
+EVOLUTION_CASES = [("fp32", "elliptic"), ("fp32", "parabolic"), ("fp64", "elliptic")]
+
+
+@pytest.mark.parametrize("precision,b_route", EVOLUTION_CASES)
+def test_evolution_solves_512_clustered_against_oracle(clustered, precision, b_route):
+    """The semi-implicit solves the benchmark times, at full size, element by element: after the GPU's
+    start step (quasi-static solve, kick, drift) and the next deposit, the deposit, phi, chi and the
+    start state of B are read back and handed to the oracle, which makes the same solve (the implicit
+    time derivative, the lagged remainder, the first Crank-Nicolson step of h and, on the parabolic
+    route, the first step of a^2 B); after one more update and deposit the second solve (now with the
+    lagged time derivative of phi from phi_{n-1} - phi_{n-2}) is compared the same way, the oracle
+    carrying its own tensor and a^2 B state.  phi, chi, B and the six h_ij against the oracle."""
+    from paper_2607_17929_amd import PMContext
+    pos, u, tau, dtau = clustered
+    _say(f"evolution solves 512 clustered {precision} {b_route} against the oracle")
+    ctx = PMContext(N, pos.shape[0], BOX, physics="full", precision=precision, b_route=b_route)
+    u_in = u.astype(ctx.np_dtype)
+    ctx.init_particles(pos, u_in, tau)
+    ctx.deposit()
+    ctx.solve_metric(0.0)
+    a_start = opm.Background(BOX).a(ctx.time()[0])
+    b_start = [ctx.get_field(k).astype(np.float64) for k in ("bx", "by", "bz")]
+    sim = opm.OracleSim(n=N, box_mpch=BOX, physics=opm.FULL, pos=pos, u=u_in.astype(np.float64), tau=tau,
+                        b_route=b_route)
+    # the oracle's state after its own start: phi_prev = phi, no time derivative yet, h = h' = 0 and
+    # a^2 B from the start's momentum-constraint B (its spectrum is what the start's B transforms to)
+    sim.a2B_k = [a_start ** 2 * opm.fft3(b) * opm.nyquist_mask(N) for b in b_start]
+    del b_start
+    sim.dtau_last = 0.0
+    sim.solved_once = True
+    names = ("phi", "chi", "bx", "by", "bz", "hxx", "hxy", "hxz", "hyy", "hyz", "hzz")
+    for k_solve in range(2):
+        ctx.update_particles(dtau)
+        ctx.deposit()
+        sim.dep = np.stack([ctx.get_field(k).astype(np.float64) for k in DEP])
+        sim.phi = ctx.get_field("phi").astype(np.float64)
+        sim.phi_prev = ctx.get_field("phi_prev").astype(np.float64)
+        sim.chi = ctx.get_field("chi").astype(np.float64)
+        sim.tau = ctx.time()[0]
+        ctx.solve_metric(dtau)
+        gpu = {k: ctx.get_field(k).astype(np.float64) for k in names}
+        sim.solve(dtau)
+        ref = {"phi": sim.phi, "chi": sim.chi, "bx": sim.B[0], "by": sim.B[1], "bz": sim.B[2]}
+        ref.update(zip(names[5:], sim.h_real()))
+        errs = field_errors(gpu, ref)
+        _say(f"  solve {k_solve + 1}: " + ", ".join(f"{k} {a:.1e}/{b:.1e}" for k, (a, b) in errs.items()))
+        for k in names:
+            assert np.max(np.abs(ref[k])) > 0, k
+        assert_fields(errs, precision)
+        sim.dtau_last = dtau
+        del gpu, ref
+    del ctx
+    torch.cuda.empty_cache()
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])

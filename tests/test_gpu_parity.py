@@ -12,7 +12,7 @@ import pytest
 
 from oracle import pm as opm
 from synth import config_particles, lattice_positions
-from tests.helpers import gpu_fields, oracle_fields, periodic_max_dx, rel_l2
+from tests.helpers import FIELD_LINF, gpu_fields, oracle_fields, periodic_max_dx, rel_l2, rel_linf
 
 pytestmark = pytest.mark.gpu
 
@@ -112,7 +112,7 @@ def _run_both(n, box, physics, precision, pos, u, tau0, dtaus, check_every=False
     ctx.init_particles(pos, u_in, tau0)
     sim = opm.OracleSim(n=n, box_mpch=box, physics=physics, pos=pos, u=u_in.astype(np.float64), tau=tau0,
                         b_route=b_route)
-    worst = {}
+    worst, worst_max = {}, {}
     for i, dt in enumerate(dtaus):
         ctx.step(dt)
         sim.step(dt)
@@ -121,6 +121,10 @@ def _run_both(n, box, physics, precision, pos, u, tau0, dtaus, check_every=False
             of = oracle_fields(sim, physics)
             for k in gf:
                 worst[k] = max(worst.get(k, 0.0), rel_l2(gf[k], of[k]))
+                worst_max[k] = max(worst_max.get(k, 0.0), rel_linf(gf[k], of[k]))
+    _say("  rel-max", {k: f"{v:.1e}" for k, v in worst_max.items()})
+    for k, v in worst_max.items():
+        assert v < FIELD_LINF[precision], (k, "rel-max", v)
     gp, gu = ctx.get_particles()
     op, ou = sim.particles_by_id()
     return worst, periodic_max_dx(gp, op, n), rel_l2(gu, ou), ctx, sim

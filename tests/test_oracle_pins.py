@@ -1029,3 +1029,19 @@ def test_p21_schwarzschild_satisfies_the_hamiltonian_constraint():
     scale = np.abs(s["lap_phi"]).max()
     assert scale > 1e-4
     assert np.abs(s["lap_phi"] - R).max() <= 1e-12 * scale
+
+
+def test_pointwise_gather_equals_the_gather_of_full_gradient_arrays():
+    """The pointwise evaluation of the gathered values and centred-difference gradients (used where
+    the full gradient arrays do not fit in host memory) equals the CIC interpolation of the full
+    arrays of grad(f): the same sums, evaluated at the needed vertices only."""
+    n = 16
+    r = np.random.default_rng(3)
+    pos, u = _rand_particles(300, 4, 0.01)
+    sim = pm.OracleSim(n=n, box_mpch=160.0, physics=pm.FULL, pos=pos, u=u, tau=30.0)
+    sim.phi, sim.chi = r.standard_normal((n, n, n)), r.standard_normal((n, n, n))
+    sim.B = [r.standard_normal((n, n, n)) for _ in range(3)]
+    full = sim.gathered()
+    point = pm.gathered_pointwise(sim.phi, sim.chi, sim.B, sim.pos, n)
+    assert full.shape == point.shape
+    assert np.max(np.abs(full - point)) < 1e-12 * np.max(np.abs(full))
