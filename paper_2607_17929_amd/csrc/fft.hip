@@ -296,17 +296,13 @@ __global__ __launch_bounds__(NT) void fft_x_c2r_kernel(const cplx<T>* spec, int 
 // ---------------------------------------------------------------------------
 // host launchers
 // ---------------------------------------------------------------------------
-#ifndef GPM_XROW_BYTES
-#define GPM_XROW_BYTES 2048  // real row bytes per pass-X workgroup
-#endif
-#ifndef GPM_COL_BYTES
-#define GPM_COL_BYTES 128    // contiguous bytes of one column-tile row
-#endif
+constexpr int X_ROW_BYTES = 2048;  // real row bytes per pass-X workgroup
+constexpr int COL_BYTES = 128;     // contiguous bytes of one column-tile row
 template <typename T, int N> constexpr int rows_per_block() {
-  constexpr int r = GPM_XROW_BYTES / (N * (int)sizeof(T));
+  constexpr int r = X_ROW_BYTES / (N * (int)sizeof(T));
   return r < 1 ? 1 : (r > N ? N : r);
 }
-template <typename T> constexpr int col_tile() { return GPM_COL_BYTES / (int)sizeof(cplx<T>); }
+template <typename T> constexpr int col_tile() { return COL_BYTES / (int)sizeof(cplx<T>); }
 
 template <typename T, int N>
 static void launch_cols(cplx<T>* spec, int ncomp, bool inv, bool along_z, int nhp, const cplx<T>* tw, hipStream_t st) {

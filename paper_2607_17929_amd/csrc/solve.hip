@@ -212,10 +212,7 @@ __device__ __forceinline__ void solve_mode(const SolveArgs<T>& a, int kx, int ky
 // are transformed back along z and written to the output spectrum.  Each value of the source
 // and output spectra crosses HBM once.
 // grid: x = kx tile, y = ky.
-#ifndef GPM_KSPACE_TWPOW
-#define GPM_KSPACE_TWPOW 1     // twiddle powers by products (the table may live in global memory)
-#endif
-constexpr bool KS_TWPOW = GPM_KSPACE_TWPOW != 0;
+constexpr bool KS_TWPOW = true;  // twiddle powers by products (the table may live in global memory)
 
 template <typename T, int N, int MODE, int KXT, int NT, bool TW_LDS>
 __global__ __launch_bounds__(NT) void kspace_kernel(SolveArgs<T> a) {
@@ -273,23 +270,18 @@ __global__ __launch_bounds__(NT) void kspace_kernel(SolveArgs<T> a) {
 }
 
 // Tile shape (measured at 512^3, FP32 full physics: rows of 4 kx x 10 components = 320 B in a
-// 160 KB tile, one workgroup per CU, run faster than 160 B rows with two workgroups per CU)
-#ifndef GPM_KSPACE_BYTES
-#define GPM_KSPACE_BYTES 256   // contiguous bytes wanted per row of a tile
-#endif
-#ifndef GPM_KSPACE_LDS
-#define GPM_KSPACE_LDS 163840  // LDS budget of a tile
-#endif
-#ifndef GPM_KSPACE_NT
-#define GPM_KSPACE_NT 1024     // 16 waves on the CU's one tile (3.54 ms at 512^3 against 3.63 with 512 threads)
-#endif
-// kx values per workgroup: KXT * NS * sizeof(complex) >= GPM_KSPACE_BYTES contiguous bytes where the
+// 160 KB tile, one workgroup per CU, run faster than 160 B rows with two workgroups per CU; 1024
+// threads, 16 waves on the CU's one tile, 3.54 ms against 3.63 with 512)
+constexpr int KS_ROW_BYTES = 256;   // contiguous bytes wanted per row of a tile
+constexpr long KS_LDS = 163840;     // LDS budget of a tile
+constexpr int KS_NT = 1024;         // threads of a workgroup when the tile has that many modes
+// kx values per workgroup: KXT * NS * sizeof(complex) >= KS_ROW_BYTES contiguous bytes where the
 // LDS tile allows
 template <typename T, int N, int NS> constexpr int kspace_kxt() {
-  constexpr int want = (GPM_KSPACE_BYTES + NS * (int)sizeof(cplx<T>) - 1) / (NS * (int)sizeof(cplx<T>));
+  constexpr int want = (KS_ROW_BYTES + NS * (int)sizeof(cplx<T>) - 1) / (NS * (int)sizeof(cplx<T>));
   int k = 1;
   while (k < want) k *= 2;
-  while (k > 1 && (long)N * k * NS * (long)sizeof(cplx<T>) > GPM_KSPACE_LDS) k /= 2;
+  while (k > 1 && (long)N * k * NS * (long)sizeof(cplx<T>) > KS_LDS) k /= 2;
   return k;
 }
 
@@ -297,9 +289,8 @@ template <typename T, int N, int MODE>
 static void launch_kspace_n(const SolveArgs<T>& a, hipStream_t st) {
   constexpr int NS = mode_nsrc(MODE);
   constexpr int KXT = kspace_kxt<T, N, NS>();
-  constexpr int NT = N * KXT >= GPM_KSPACE_NT ? GPM_KSPACE_NT : (N * KXT >= 256 ? 256 : 64);
-  constexpr bool TW_LDS =
-      (long)N * KXT * NS * (long)sizeof(cplx<T>) + N * (long)sizeof(cplx<T>) <= GPM_KSPACE_LDS;
+  constexpr int NT = N * KXT >= KS_NT ? KS_NT : (N * KXT >= 256 ? 256 : 64);
+  constexpr bool TW_LDS = (long)N * KXT * NS * (long)sizeof(cplx<T>) + N * (long)sizeof(cplx<T>) <= KS_LDS;
   static_assert((long)N * KXT * NS * (long)sizeof(cplx<T>) + (TW_LDS ? N : 0) * (long)sizeof(cplx<T>) <= 160 * 1024,
                 "LDS tile too large");
   const int nh = N / 2 + 1;
