@@ -73,7 +73,12 @@ enum {
    * with a^2 at the midpoint of each step and started from the momentum constraint (Eq. 6) at the
    * quasi-static start.  Later steps need 7 forward and 5 inverse transforms instead of 10 and 5
    * (the paper's benchmark configuration, Sec. 4.1).  Ignored for other physics. */
-  PM_FLAG_B_PARABOLIC = 4u
+  PM_FLAG_B_PARABOLIC = 4u,
+  /* Deterministic runs: after every sort by cell, the particles of each cell are put in identifier
+   * order (one more pass over the particles), so that the order of the atomic counters the sort
+   * ranks with no longer reaches the sums over a cell; two runs from the same inputs, and a run
+   * restarted from pm_get_state / pm_set_state, then give bitwise identical particles and fields. */
+  PM_FLAG_DETERMINISTIC = 8u
 };
 
 /* field identifiers for pm_get_field / pm_set_field (real space, [z][y][x]) */
@@ -261,10 +266,10 @@ pm_status pm_power_spectrum(pm_ctx* ctx, int subtract_shot_noise, double* k_out,
  * in (PM_EINVAL otherwise, and the context then holds no particles until the next
  * pm_init_particles or successful pm_set_state; repeated identifiers are not
  * detected).  On success it clears a sticky device error and leaves the context as
- * it was when the blob was taken.  The run after a restore agrees
- * with the uninterrupted run to rounding: particles inside a cell are ordered by
- * the sort's atomic counters, so sums over a cell's particles may round
- * differently from run to run. */
+ * it was when the blob was taken.  The run after a restore agrees with the
+ * uninterrupted run bit for bit under PM_FLAG_DETERMINISTIC, otherwise to rounding
+ * (particles inside a cell are then ordered by the sort's atomic counters, so sums
+ * over a cell's particles may round differently from run to run). */
 pm_status pm_get_state(pm_ctx* ctx, void* blob, size_t* bytes, int dst_on_device);
 pm_status pm_set_state(pm_ctx* ctx, const void* blob, size_t bytes, int src_on_device);
 
@@ -301,6 +306,14 @@ pm_status pm_closure_backward(pm_ctx* ctx, const float* d_dpred, float* d_grad);
  * device vectors, then the context's bfloat16 weights are refreshed from d_params. */
 pm_status pm_closure_adam(pm_ctx* ctx, float* d_params, float* d_m, float* d_v, const float* d_grad, int step,
                           double lr);
+
+/* Measurement helper (Sec. 4 reports step times; the HBM rates of the kernels here are judged
+ * against the device's own sustainable rate): copies `bytes` (a multiple of 16, both pointers device
+ * memory aligned to 16 bytes) from d_src to d_dst with a plain copy kernel (one 16-byte element per
+ * thread, non-temporal loads and stores), once to warm
+ * up and then `reps` times on hip_stream, and writes the average milliseconds of one copy to
+ * ms_per_copy.  The copy moves 2 x bytes through HBM.  Synchronises the stream; needs no context. */
+pm_status pm_copy_probe(const void* d_src, void* d_dst, size_t bytes, int reps, void* hip_stream, double* ms_per_copy);
 
 const char* pm_status_string(pm_status s);
 /* Last error message recorded on this context (never NULL). */

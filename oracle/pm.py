@@ -36,7 +36,18 @@ from dataclasses import dataclass, field
 import numpy as np
 import scipy.fft as sfft
 
-_WORKERS = max(1, min(16, len(os.sched_getaffinity(0))))
+def _host_threads() -> int:
+    """Threads for the library FFTs: the cores this process may run on, capped by OMP_NUM_THREADS when
+    it is set (the share of the host's cores that belongs to this process)."""
+    n = len(os.sched_getaffinity(0))
+    try:
+        cap = int(os.environ.get("OMP_NUM_THREADS", "0"))
+    except ValueError:
+        cap = 0
+    return max(1, min(n, cap) if cap > 0 else n)
+
+
+_WORKERS = _host_threads()
 
 NEWTONIAN, SCALAR, FULL = "newtonian", "scalar", "full"
 

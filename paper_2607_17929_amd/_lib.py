@@ -13,6 +13,7 @@ PM_NEWTONIAN, PM_SCALAR, PM_FULL = 0, 1, 2
 PM_FLAG_TIMINGS = 1
 PM_FLAG_CLOSURE = 2
 PM_FLAG_B_PARABOLIC = 4
+PM_FLAG_DETERMINISTIC = 8
 PM_CLOSURE_NPARAM = 9971
 
 FIELDS = {
@@ -29,7 +30,7 @@ EXPORTS = (
     "pm_background", "pm_tau_of_a", "pm_get_timings", "pm_sync", "pm_debug_fft", "pm_status_string",
     "pm_last_error", "pm_gather_grad_phi", "pm_power_spectrum", "pm_closure_set_params", "pm_closure_enable", "pm_closure_forward",
     "pm_closure_gather", "pm_closure_backward", "pm_closure_adam", "pm_closure_scale", "pm_get_state", "pm_set_state",
-    "pm_init_particles_2", "pm_get_particles_2", "pm_diagnostics",
+    "pm_init_particles_2", "pm_get_particles_2", "pm_diagnostics", "pm_copy_probe",
 )
 
 
@@ -96,6 +97,7 @@ def load():
         "pm_closure_backward": [vp, vp, vp],
         "pm_closure_adam": [vp, vp, vp, vp, vp, C.c_int, C.c_double],
         "pm_closure_scale": [vp, C.POINTER(C.c_double)],
+        "pm_copy_probe": [vp, vp, C.c_size_t, C.c_int, vp, C.POINTER(C.c_double)],
     }
     for name, args in sig.items():
         f = getattr(lib, name)

@@ -377,6 +377,8 @@ pm_status do_solve(pm_ctx* c, double dtau_prev) {
   return c->hip_check("solve");
 }
 
+// counting sort by cell; with PM_FLAG_DETERMINISTIC the particles of each cell are then put in
+// identifier order, so that the store and every sum over it are the same from run to run
 template <typename T>
 void sort_particles(pm_ctx* c) {
   const Layout& L = c->L;
@@ -384,6 +386,11 @@ void sort_particles(pm_ctx* c) {
   launch_scatter<T>(c->parts<T>(c->cur), c->parts<T>(1 - c->cur), c->np, c->n, c->at<uint32_t>(L.rank),
                     c->at<uint32_t>(L.cell_start), c->st);
   c->cur = 1 - c->cur;
+  if (c->cfg.flags & PM_FLAG_DETERMINISTIC) {
+    launch_order_by_id<T>(c->parts<T>(c->cur), c->parts<T>(1 - c->cur), c->np, c->n, c->at<uint32_t>(L.cell_start),
+                          c->st);
+    c->cur = 1 - c->cur;
+  }
 }
 
 template <typename T>
@@ -393,6 +400,11 @@ void sort_particles2(pm_ctx* c) {
   launch_scatter<T>(c->parts2<T>(c->cur2), c->parts2<T>(1 - c->cur2), c->np2, c->n, c->at<uint32_t>(L.rank2),
                     c->at<uint32_t>(L.cell_start2), c->st);
   c->cur2 = 1 - c->cur2;
+  if (c->cfg.flags & PM_FLAG_DETERMINISTIC) {
+    launch_order_by_id<T>(c->parts2<T>(c->cur2), c->parts2<T>(1 - c->cur2), c->np2, c->n,
+                          c->at<uint32_t>(L.cell_start2), c->st);
+    c->cur2 = 1 - c->cur2;
+  }
 }
 
 template <typename T>

@@ -139,6 +139,11 @@ size_t scan_block_sums_count(long ncell);
 template <typename T>
 void launch_scatter(const Particles<T>& src, Particles<T> dst, long np, int nmesh, const uint32_t* rank,
                     const uint32_t* cell_start, hipStream_t st);
+// move each particle of the cell-sorted src to cell_start[cell] + (particles of its cell with a smaller
+// identifier) in dst: an in-cell order that does not depend on the order of the sort's atomic ranks
+template <typename T>
+void launch_order_by_id(const Particles<T>& src, Particles<T> dst, long np, int nmesh, const uint32_t* cell_start,
+                        hipStream_t st);
 // bit 4 of err unless the store and its cell offsets are consistent (used on restored checkpoints)
 template <typename T>
 void launch_check_store(const Particles<T>& p, long np, int nmesh, const uint32_t* cell_start, int* err,

@@ -844,6 +844,38 @@ void launch_scatter(const Particles<T>& src, Particles<T> dst, long np, int nmes
 }
 
 // ---------------------------------------------------------------------------
+// deterministic order inside each cell: after the counting sort the particles of
+// a cell sit in the order in which atomic counters handed out their ranks; this
+// pass moves each particle to cell_start[cell] + (number of particles of its cell
+// with a smaller identifier), so the store -- and every sum over it -- no longer
+// depends on that order (identifiers are unique)
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(256) void order_by_id_kernel(Particles<T> s, Particles<T> d, long np, int nmesh,
+                                                          const uint32_t* __restrict__ cell_start) {
+  const long i = (long)xcd_remap(blockIdx.x, gridDim.x) * 256 + threadIdx.x;
+  if (i >= np) return;
+  const double x = s.px[i], y = s.py[i], z = s.pz[i];
+  const T ux = s.ux[i], uy = s.uy[i], uz = s.uz[i];
+  const uint32_t id = s.id[i];
+  const uint32_t k = cell_key(x, y, z, nmesh);
+  const uint32_t b = cell_start[k], e = cell_start[k + 1];
+  uint32_t r = 0;
+  for (uint32_t j = b; j < e; ++j) r += s.id[j] < id ? 1u : 0u;
+  const long o = (long)b + r;
+  d.px[o] = x; d.py[o] = y; d.pz[o] = z;
+  d.ux[o] = ux; d.uy[o] = uy; d.uz[o] = uz;
+  d.id[o] = id;
+}
+
+template <typename T>
+void launch_order_by_id(const Particles<T>& src, Particles<T> dst, long np, int nmesh, const uint32_t* cell_start,
+                        hipStream_t st) {
+  hipLaunchKernelGGL((order_by_id_kernel<T>), dim3((unsigned)((np + 255) / 256)), dim3(256), 0, st, src, dst, np, nmesh,
+                     cell_start);
+}
+
+// ---------------------------------------------------------------------------
 // consistency check of a restored store (checkpoint bodies are not trusted):
 // cell_start[0] = 0, cell_start[n^3] = np, non-decreasing; every particle has
 // finite momenta, a position in [0, 1), an identifier < np, and sits inside the
@@ -940,6 +972,7 @@ void launch_copy_unpad(const cplx<T>* spec, int n, int nhp, cplx<T>* out, bool t
                                   hipStream_t);                                                                        \
   template void launch_export<T>(const Particles<T>&, long, double*, T*, uint32_t*, hipStream_t);                      \
   template void launch_check_store<T>(const Particles<T>&, long, int, const uint32_t*, int*, hipStream_t);            \
+  template void launch_order_by_id<T>(const Particles<T>&, Particles<T>, long, int, const uint32_t*, hipStream_t);     \
   template void launch_copy_unpad<T>(const cplx<T>*, int, int, cplx<T>*, bool, hipStream_t);
 GPM_INST(float)
 GPM_INST(double)

@@ -18,11 +18,12 @@ _PREC = {"fp32": L.PM_FP32, "fp64": L.PM_FP64}
 
 def make_config(n_mesh: int, n_particles: int, box_mpch: float, physics: str = "full", precision: str = "fp32",
                 timings: bool = False, closure: bool = False, b_route: str = "elliptic", n_particles_2: int = 0,
-                mass_fraction_2: float = 0.0) -> L.PMConfig:
+                mass_fraction_2: float = 0.0, deterministic: bool = False) -> L.PMConfig:
     if b_route not in ("elliptic", "parabolic"):
         raise ValueError("b_route must be 'elliptic' or 'parabolic'")
     flags = ((L.PM_FLAG_TIMINGS if timings else 0) | (L.PM_FLAG_CLOSURE if closure else 0)
-             | (L.PM_FLAG_B_PARABOLIC if b_route == "parabolic" else 0))
+             | (L.PM_FLAG_B_PARABOLIC if b_route == "parabolic" else 0)
+             | (L.PM_FLAG_DETERMINISTIC if deterministic else 0))
     return L.PMConfig(n_mesh=n_mesh, precision=_PREC[precision], n_particles=n_particles, box_mpch=box_mpch,
                       physics=_PHYS[physics], flags=flags, n_particles_2=n_particles_2,
                       mass_fraction_2=mass_fraction_2)
@@ -52,6 +53,21 @@ def tau_of_a(box_mpch: float, a: float) -> float:
     return t.value
 
 
+def copy_probe(nbytes: int = 2 ** 31, reps: int = 5, device: str | torch.device = "cuda:0") -> float:
+    """Sustainable device copy rate (read + write bytes per second) from the library's copy kernel
+    (pm_copy_probe) on two buffers of nbytes."""
+    lib = L.load()
+    src = torch.ones(nbytes // 4, dtype=torch.float32, device=device)
+    dst = torch.empty_like(src)
+    st = torch.cuda.current_stream(torch.device(device))
+    ms = C.c_double()
+    L.check(lib.pm_copy_probe(C.c_void_p(src.data_ptr()), C.c_void_p(dst.data_ptr()), nbytes, reps,
+                              C.c_void_p(st.cuda_stream), C.byref(ms)), what="pm_copy_probe")
+    if not torch.equal(src[:1024], dst[:1024]) or not torch.equal(src[-1024:], dst[-1024:]):
+        raise RuntimeError("pm_copy_probe did not copy")
+    return 2.0 * nbytes / (ms.value * 1e-3)
+
+
 def _ptr(t: torch.Tensor) -> int:
     return t.data_ptr()
 
@@ -62,10 +78,10 @@ class PMContext:
     def __init__(self, n_mesh: int, n_particles: int, box_mpch: float, physics: str = "full",
                  precision: str = "fp32", timings: bool = False, device: str | torch.device = "cuda:0",
                  stream: torch.cuda.Stream | None = None, closure: bool = False, b_route: str = "elliptic",
-                 n_particles_2: int = 0, mass_fraction_2: float = 0.0):
+                 n_particles_2: int = 0, mass_fraction_2: float = 0.0, deterministic: bool = False):
         self.lib = L.load()
         self.cfg = make_config(n_mesh, n_particles, box_mpch, physics, precision, timings, closure, b_route,
-                               n_particles_2, mass_fraction_2)
+                               n_particles_2, mass_fraction_2, deterministic)
         self.n = n_mesh
         self.np = n_particles
         self.np2 = n_particles_2

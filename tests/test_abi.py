@@ -70,7 +70,7 @@ def test_header_constants_match_the_binding():
     h = _header_constants()
     for name in ("PM_OK", "PM_EINVAL", "PM_EWORKSPACE", "PM_EHIP", "PM_ENAN", "PM_ESTATE", "PM_ERANGE",
                  "PM_EUNSUPPORTED", "PM_FP32", "PM_FP64", "PM_NEWTONIAN", "PM_SCALAR", "PM_FULL",
-                 "PM_FLAG_TIMINGS", "PM_FLAG_CLOSURE", "PM_FLAG_B_PARABOLIC", "PM_CLOSURE_NPARAM"):
+                 "PM_FLAG_TIMINGS", "PM_FLAG_CLOSURE", "PM_FLAG_B_PARABOLIC", "PM_FLAG_DETERMINISTIC", "PM_CLOSURE_NPARAM"):
         assert h[name] == getattr(L, name), name
     for name, fid in L.FIELDS.items():
         assert h["PM_FIELD_" + name.upper()] == fid, name

@@ -251,3 +251,69 @@ def test_damaged_blob_bodies_are_rejected():
     fa, ft = gpu_fields(a, "scalar"), gpu_fields(target, "scalar")
     for k in fa:
         assert rel_l2(ft[k], fa[k]) < 1e-12, k
+
+
+DET_CASES = [("fp32", "full", "elliptic", "zeldovich_32"), ("fp32", "full", "parabolic", "clustered_64"),
+             ("fp64", "scalar", "elliptic", "zeldovich_32")]
+
+
+def _det_inputs(kind):
+    if kind == "zeldovich_32":
+        pos, u, tau0, dtau = config_particles("zeldovich_32_scalar_fp64")
+        return 32, 320.0, pos, u, tau0, dtau
+    # many particles per cell: most of the sums over a cell have several terms
+    r = np.random.default_rng(61)
+    n = 64
+    centers = r.random((6, 3))
+    pos = (centers[r.integers(0, 6, 60000)] + 0.8 / n * r.standard_normal((60000, 3))) % 1.0
+    u = 2e-3 * r.standard_normal((60000, 3))
+    tau0 = opm.Background(640.0).tau(0.2)
+    return n, 640.0, pos, u, tau0, 0.01 * tau0
+
+
+def _det_state(ctx, physics):
+    f = {k: v.copy() for k, v in gpu_fields(ctx, physics).items()}
+    p, u = ctx.get_particles()
+    return f, p, u
+
+
+@pytest.mark.parametrize("precision,physics,b_route,kind", DET_CASES)
+def test_deterministic_runs_and_restart_are_bitwise_equal(precision, physics, b_route, kind):
+    """With PM_FLAG_DETERMINISTIC two runs from the same inputs give bitwise identical fields and
+    particles after ten steps, and so does a run restarted from a checkpoint taken after five steps in
+    a fresh context (the checkpoint holds the store in its deterministic order)."""
+    from paper_2607_17929_amd import PMContext
+    _say(f"deterministic {precision} {physics} {b_route} {kind}")
+    n, box, pos, u, tau0, dtau = _det_inputs(kind)
+    runs = []
+    blob = None
+    for k in range(2):
+        ctx = PMContext(n, pos.shape[0], box, physics=physics, precision=precision, b_route=b_route,
+                        deterministic=True)
+        ctx.init_particles(pos, u.astype(ctx.np_dtype), tau0)
+        for s in range(10):
+            ctx.step(dtau)
+            if k == 0 and s == 4:
+                blob = ctx.get_state()
+        runs.append(_det_state(ctx, physics))
+        del ctx
+    ctx = PMContext(n, pos.shape[0], box, physics=physics, precision=precision, b_route=b_route, deterministic=True)
+    ctx.set_state(blob)
+    for _ in range(5):
+        ctx.step(dtau)
+    runs.append(_det_state(ctx, physics))
+    ref = runs[0]
+    for other in runs[1:]:
+        for name in ref[0]:
+            assert np.array_equal(other[0][name], ref[0][name]), name
+        assert np.array_equal(other[1], ref[1]) and np.array_equal(other[2], ref[2])
+    # the same as an ordinary run up to rounding
+    ctx = PMContext(n, pos.shape[0], box, physics=physics, precision=precision, b_route=b_route)
+    ctx.init_particles(pos, u.astype(ctx.np_dtype), tau0)
+    for _ in range(10):
+        ctx.step(dtau)
+    plain = _det_state(ctx, physics)
+    tol = 1e-10 if precision == "fp64" else 1e-5
+    for name in ref[0]:
+        assert rel_l2(plain[0][name], ref[0][name]) < tol, name
+    assert periodic_max_dx(plain[1], ref[1], n) < (1e-9 if precision == "fp64" else 1e-4)
