@@ -315,6 +315,22 @@ pm_status pm_closure_adam(pm_ctx* ctx, float* d_params, float* d_m, float* d_v, 
  * ms_per_copy.  The copy moves 2 x bytes through HBM.  Synchronises the stream; needs no context. */
 pm_status pm_copy_probe(const void* d_src, void* d_dst, size_t bytes, int reps, void* hip_stream, double* ms_per_copy);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight serving loops):
+ * the 3D real-to-complex FFT of pm_debug_fft without a context.  Its scratch (the padded half spectrum
+ * and the twiddle table, pm_fft_noalloc_scratch_bytes) lives in one fixed device array of
+ * PM_FFT_NOALLOC_SCRATCH_BYTES that each GPU holds until the process ends: meshes up to 128^3 in either
+ * precision fit, larger ones return PM_ERANGE.  It calls no allocation routine; the array's device
+ * address is looked up once per device on the first call made with that device current.
+ * direction +1: d_in = real [z][y][x] (n^3 values), d_out = complex [z][y][kx] (n^2 (n/2+1) interleaved
+ * re, im), unnormalised; -1: d_in = that half spectrum, d_out = real, scaled by 1/n^3.  Both device
+ * pointers of the given precision (PM_FP32 / PM_FP64); enqueued on hip_stream, no synchronisation.
+ * Every call on one GPU uses that GPU's one array, so calls that overlap on a GPU (two streams, two
+ * threads) race and must be ordered by the caller.  PM_EINVAL for null pointers, a bad direction or a
+ * mesh that is not a power of two in 16 .. 1024; PM_EHIP if the array's address cannot be found. */
+enum { PM_FFT_NOALLOC_SCRATCH_BYTES = 24 << 20 };
+size_t pm_fft_noalloc_scratch_bytes(int n_mesh, int precision); /* 0 for an invalid mesh or precision */
+pm_status pm_fft_noalloc(const void* d_in, void* d_out, int n_mesh, int precision, int direction, void* hip_stream);
+
 const char* pm_status_string(pm_status s);
 /* Last error message recorded on this context (never NULL). */
 const char* pm_last_error(pm_ctx* ctx);

@@ -15,6 +15,7 @@ PM_FLAG_CLOSURE = 2
 PM_FLAG_B_PARABOLIC = 4
 PM_FLAG_DETERMINISTIC = 8
 PM_CLOSURE_NPARAM = 9971
+PM_FFT_NOALLOC_SCRATCH_BYTES = 24 << 20
 
 FIELDS = {
     "n00": 0, "n0x": 1, "n0y": 2, "n0z": 3, "nxx": 4, "nxy": 5, "nxz": 6, "nyy": 7, "nyz": 8, "nzz": 9,
@@ -30,7 +31,8 @@ EXPORTS = (
     "pm_background", "pm_tau_of_a", "pm_get_timings", "pm_sync", "pm_debug_fft", "pm_status_string",
     "pm_last_error", "pm_gather_grad_phi", "pm_power_spectrum", "pm_closure_set_params", "pm_closure_enable", "pm_closure_forward",
     "pm_closure_gather", "pm_closure_backward", "pm_closure_adam", "pm_closure_scale", "pm_get_state", "pm_set_state",
-    "pm_init_particles_2", "pm_get_particles_2", "pm_diagnostics", "pm_copy_probe",
+    "pm_init_particles_2", "pm_get_particles_2", "pm_diagnostics", "pm_copy_probe", "pm_fft_noalloc",
+    "pm_fft_noalloc_scratch_bytes",
 )
 
 
@@ -98,11 +100,14 @@ def load():
         "pm_closure_adam": [vp, vp, vp, vp, vp, C.c_int, C.c_double],
         "pm_closure_scale": [vp, C.POINTER(C.c_double)],
         "pm_copy_probe": [vp, vp, C.c_size_t, C.c_int, vp, C.POINTER(C.c_double)],
+        "pm_fft_noalloc": [vp, vp, C.c_int, C.c_int, C.c_int, vp],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
         f.argtypes = args
         f.restype = C.c_int
+    lib.pm_fft_noalloc_scratch_bytes.argtypes = [C.c_int, C.c_int]
+    lib.pm_fft_noalloc_scratch_bytes.restype = C.c_size_t
     lib.pm_status_string.argtypes = [C.c_int]
     lib.pm_status_string.restype = C.c_char_p
     lib.pm_last_error.argtypes = [vp]

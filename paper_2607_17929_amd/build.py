@@ -11,7 +11,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libgpm.so")
-SOURCES = ["fft.hip", "solve.hip", "particles.hip", "closure.hip", "pk.hip", "capi.hip", "probe.hip"]
+SOURCES = ["fft.hip", "solve.hip", "particles.hip", "closure.hip", "pk.hip", "capi.hip", "probe.hip", "noalloc.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17",

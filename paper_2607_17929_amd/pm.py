@@ -68,6 +68,24 @@ def copy_probe(nbytes: int = 2 ** 31, reps: int = 5, device: str | torch.device 
     return 2.0 * nbytes / (ms.value * 1e-3)
 
 
+def fft_noalloc(x: torch.Tensor, n: int, direction: int, precision: str = "fp32") -> torch.Tensor:
+    """pm_fft_noalloc: the context-free FFT of pm_debug_fft (scratch in the library's fixed device array);
+    the output tensor is allocated here, by the caller's side."""
+    lib = L.load()
+    rdt = torch.float64 if precision == "fp64" else torch.float32
+    cdt = torch.complex128 if precision == "fp64" else torch.complex64
+    if direction == 1:
+        x = x.to(dtype=rdt).contiguous()
+        out = torch.empty((n, n, n // 2 + 1), dtype=cdt, device=x.device)
+    else:
+        x = x.to(dtype=cdt).contiguous()
+        out = torch.empty((n, n, n), dtype=rdt, device=x.device)
+    st = torch.cuda.current_stream(x.device)
+    L.check(lib.pm_fft_noalloc(C.c_void_p(x.data_ptr()), C.c_void_p(out.data_ptr()), n, _PREC[precision], direction,
+                               C.c_void_p(st.cuda_stream)), what="pm_fft_noalloc")
+    return out
+
+
 def _ptr(t: torch.Tensor) -> int:
     return t.data_ptr()
 
