@@ -36,7 +36,7 @@ __global__ __launch_bounds__(NT) void fft_cols_kernel(cplx<T>* data, uint32_t es
   __shared__ cplx<T> stw[N];
   for (int j = threadIdx.x; j < N; j += NT) stw[j] = tw[j];
   cplx<T>* g = data + (long)blockIdx.z * comp_stride + (long)blockIdx.y * outer_stride + (long)blockIdx.x * C;
-  col_stages<T, N, C, NT, 0, INV, true, true, uint32_t>(sm, g, es, g, es, stw);
+  col_stages<T, N, C, NT, 0, INV, true, true, uint32_t, false, true>(sm, g, es, g, es, stw);
 }
 
 // ---------------------------------------------------------------------------
@@ -213,7 +213,7 @@ __global__ __launch_bounds__(NT) void fft_x_r2c_kernel(SrcArgs<T> a, cplx<T>* sp
     const cplx<T> wk = (k == M) ? mk<T>(-1, 0) : w;
     const cplx<T> o = mk(od.y, -od.x);
     const cplx<T> xk = ev + cmul(wk, o);
-    spec[(((long)z * N + (y0 + r)) * nhp + k) * NSRC + c] = xk;
+    store_nt(spec + ((((long)z * N + (y0 + r)) * nhp + k) * NSRC + c), xk);  // streamed to the column pass
   }
 }
 

@@ -19,6 +19,8 @@ namespace gpm {
 // IX: index type of the global offsets (32-bit unless the arrays exceed 2^32 elements).
 // TWPOW: read one twiddle W^k per butterfly and form W^(r k), r = 2 .. R-1, by products (for a
 // table in global memory: one load instead of R - 1; at most three roundings deep).
+// NTG: the global reads and writes carry the non-temporal hint (streamed data that is not read again
+// soon; measured faster for the plain column passes, slower for the fused Fourier-space kernel).
 template <typename T, int R, bool INV>
 __device__ __forceinline__ void twiddle_pow(cplx<T>* v, cplx<T> w1) {
   cplx<T> w[8];
@@ -29,7 +31,20 @@ __device__ __forceinline__ void twiddle_pow(cplx<T>* v, cplx<T> w1) {
   for (int r = 1; r < R; ++r) v[r] = INV ? cmulc(v[r], w[r]) : cmul(v[r], w[r]);
 }
 
-template <typename T, int N, int C, int NT, int S, bool INV, bool FROM_G, bool TO_G, typename IX, bool TWPOW = false>
+template <typename T>
+__device__ __forceinline__ cplx<T> load_nt(const cplx<T>* p) {
+  const T* q = reinterpret_cast<const T*>(p);
+  return mk<T>(__builtin_nontemporal_load(q), __builtin_nontemporal_load(q + 1));
+}
+template <typename T>
+__device__ __forceinline__ void store_nt(cplx<T>* p, cplx<T> v) {
+  T* q = reinterpret_cast<T*>(p);
+  __builtin_nontemporal_store(v.x, q);
+  __builtin_nontemporal_store(v.y, q + 1);
+}
+
+template <typename T, int N, int C, int NT, int S, bool INV, bool FROM_G, bool TO_G, typename IX, bool TWPOW = false,
+          bool NTG = false>
 __device__ __forceinline__ void col_stage(cplx<T>* sm, const cplx<T>* gin, IX esin, cplx<T>* gout, IX esout,
                                           const cplx<T>* stw) {
   constexpr int R = stage_radix(N, S);
@@ -47,7 +62,7 @@ __device__ __forceinline__ void col_stage(cplx<T>* sm, const cplx<T>* gin, IX es
       for (int r = 0; r < R; ++r) {
         const int e = i + r * (N / R);
         if (FROM_G) {
-          v[p][r] = gin[(IX)e * esin + (IX)col];
+          v[p][r] = NTG ? load_nt(gin + ((IX)e * esin + (IX)col)) : gin[(IX)e * esin + (IX)col];
         } else {
           v[p][r] = sm[e * C + col];
         }
@@ -78,7 +93,8 @@ __device__ __forceinline__ void col_stage(cplx<T>* sm, const cplx<T>* gin, IX es
       for (int r = 0; r < R; ++r) {
         const int e = j0 + r * NS;
         if (TO_G) {
-          gout[(IX)e * esout + (IX)col] = v[p][r];
+          if (NTG) store_nt(gout + ((IX)e * esout + (IX)col), v[p][r]);
+          else gout[(IX)e * esout + (IX)col] = v[p][r];
         } else {
           sm[e * C + col] = v[p][r];
         }
@@ -90,13 +106,15 @@ __device__ __forceinline__ void col_stage(cplx<T>* sm, const cplx<T>* gin, IX es
 
 // All stages of the transform; GIN / GOUT: the first stage reads global memory, the last
 // stage writes global memory (otherwise the tile starts / ends in LDS).
-template <typename T, int N, int C, int NT, int S, bool INV, bool GIN, bool GOUT, typename IX, bool TWPOW = false>
+template <typename T, int N, int C, int NT, int S, bool INV, bool GIN, bool GOUT, typename IX, bool TWPOW = false,
+          bool NTG = false>
 __device__ __forceinline__ void col_stages(cplx<T>* sm, const cplx<T>* gin, IX esin, cplx<T>* gout, IX esout,
                                            const cplx<T>* stw) {
   constexpr int NSTG = nstages(N);
   if constexpr (S < NSTG) {
-    col_stage<T, N, C, NT, S, INV, GIN && S == 0, GOUT && S == NSTG - 1, IX, TWPOW>(sm, gin, esin, gout, esout, stw);
-    col_stages<T, N, C, NT, S + 1, INV, GIN, GOUT, IX, TWPOW>(sm, gin, esin, gout, esout, stw);
+    col_stage<T, N, C, NT, S, INV, GIN && S == 0, GOUT && S == NSTG - 1, IX, TWPOW, NTG>(sm, gin, esin, gout, esout,
+                                                                                          stw);
+    col_stages<T, N, C, NT, S + 1, INV, GIN, GOUT, IX, TWPOW, NTG>(sm, gin, esin, gout, esout, stw);
   }
 }
 
