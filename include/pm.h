@@ -302,6 +302,21 @@ pm_status pm_closure_gather(pm_ctx* ctx, float* out, int dst_on_device);
  * d_dpred [n][3] in identifier order, d_grad [PM_CLOSURE_NPARAM], overwritten), using the
  * activations of the last pm_closure_forward. */
 pm_status pm_closure_backward(pm_ctx* ctx, const float* d_dpred, float* d_grad);
+/* Training residual of the last pm_closure_forward against d_target ([n][3] FP32, identifier
+ * order, device): r = out_p - target_p at every particle; writes d_dpred[n][3] = 2 r / (3 n),
+ * the gradient of the mean-squared error that pm_closure_backward takes (device, may not alias
+ * d_target), and, when loss is not NULL, loss[0] = mean |r|^2 and loss[1] = mean |target|^2 over
+ * the 3 n components (FP64, fixed summation order; synchronises).  PM_ESTATE before a forward
+ * pass or without particles. */
+pm_status pm_closure_loss(pm_ctx* ctx, const float* d_target, float* d_dpred, double* loss);
+/* Augmentation of training data by the 48 symmetries of the periodic cube (the mesh, CIC and the
+ * centred differences map onto themselves): for n particles, component d of the outputs is
+ * component perm[d] of the inputs ([n][3] device arrays: positions FP64 in [0,1), two FP32
+ * vector fields such as momenta and force differences), and where bit d of flip (0..7) is set
+ * the position is reflected (x -> 1 - x, wrapped into [0,1)) and both vectors negated.  Outputs
+ * may alias the inputs.  Runs on the context's stream; PM_EINVAL if perm is not a permutation. */
+pm_status pm_cube_symmetry(pm_ctx* ctx, long n, const int* perm, int flip, const double* d_pos, const float* d_u,
+                           const float* d_v, double* d_pos_out, float* d_u_out, float* d_v_out);
 /* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected, step >= 1) on FP32
  * device vectors, then the context's bfloat16 weights are refreshed from d_params. */
 pm_status pm_closure_adam(pm_ctx* ctx, float* d_params, float* d_m, float* d_v, const float* d_grad, int step,

@@ -13,7 +13,8 @@ hidden activations are rounded to bfloat16 (round to nearest, ties to even)
 where the GPU stores them; sums are exact (FP64).
 
 Also: CIC gather of a vector field at particles and its adjoint (the deposit),
-the closure's input features and the Adam update.
+the closure's input features, the particle MSE and its gradient, the cube
+symmetries used to augment training data and the Adam update.
 
 Fields are arrays [c][z][y][x]; parameters use one flat FP32 vector with the
 layout W1[16][4][27] b1[16] W2[16][16][27] b2[16] W3[3][16][27] b3[3], tap
@@ -150,6 +151,29 @@ def features(n00: np.ndarray, phi: np.ndarray):
     rms = float(np.sqrt(np.mean(g[0] ** 2 + g[1] ** 2 + g[2] ** 2)))
     x = np.stack([np.sign(delta) * np.log1p(np.abs(delta)), g[0] / rms, g[1] / rms, g[2] / rms])
     return x, rms
+
+
+def mse_loss(pred: np.ndarray, target: np.ndarray):
+    """Particle mean-squared error over all components and its gradient in pred:
+    (mean |pred - target|^2, mean |target|^2, 2 (pred - target) / numel)."""
+    r = np.asarray(pred, dtype=np.float64) - np.asarray(target, dtype=np.float64)
+    t = np.asarray(target, dtype=np.float64)
+    return float(np.mean(r * r)), float(np.mean(t * t)), 2.0 * r / r.size
+
+
+def cube_symmetry(pos: np.ndarray, u: np.ndarray, v: np.ndarray, perm, flip: int):
+    """One of the 48 symmetries of the periodic unit cube on particle data [n][3]: component d of the
+    result is component perm[d] of the input; where bit d of flip is set the position is reflected
+    (x -> 1 - x, taken back into [0, 1)) and the two vector fields are negated."""
+    perm = list(perm)
+    p, a, b = pos[:, perm].copy(), u[:, perm].copy(), v[:, perm].copy()
+    for d in range(3):
+        if (flip >> d) & 1:
+            x = 1.0 - p[:, d]
+            p[:, d] = np.where(x >= 1.0, x - 1.0, x)
+            a[:, d] = -a[:, d]
+            b[:, d] = -b[:, d]
+    return p, a, b
 
 
 def adam(params, m, v, g, step: int, lr: float = 1e-3, b1: float = 0.9, b2: float = 0.999, eps: float = 1e-8):

@@ -32,7 +32,7 @@ EXPORTS = (
     "pm_last_error", "pm_gather_grad_phi", "pm_power_spectrum", "pm_closure_set_params", "pm_closure_enable", "pm_closure_forward",
     "pm_closure_gather", "pm_closure_backward", "pm_closure_adam", "pm_closure_scale", "pm_get_state", "pm_set_state",
     "pm_init_particles_2", "pm_get_particles_2", "pm_diagnostics", "pm_copy_probe", "pm_fft_noalloc",
-    "pm_fft_noalloc_scratch_bytes",
+    "pm_fft_noalloc_scratch_bytes", "pm_closure_loss", "pm_cube_symmetry",
 )
 
 
@@ -98,6 +98,8 @@ def load():
         "pm_closure_gather": [vp, vp, C.c_int],
         "pm_closure_backward": [vp, vp, vp],
         "pm_closure_adam": [vp, vp, vp, vp, vp, C.c_int, C.c_double],
+        "pm_closure_loss": [vp, vp, vp, C.POINTER(C.c_double)],
+        "pm_cube_symmetry": [vp, C.c_long, C.POINTER(C.c_int), C.c_int, vp, vp, vp, vp, vp, vp],
         "pm_closure_scale": [vp, C.POINTER(C.c_double)],
         "pm_copy_probe": [vp, vp, C.c_size_t, C.c_int, vp, C.POINTER(C.c_double)],
         "pm_fft_noalloc": [vp, vp, C.c_int, C.c_int, C.c_int, vp],

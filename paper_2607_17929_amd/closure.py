@@ -1,8 +1,9 @@
 """Training and evaluation driver of the learned force closure.
 
 Everything numerical runs in the library's kernels (PM steps, the network's
-forward and backward passes, Adam); this module only orders the calls and
-forms the particle-level mean-squared-error gradient.
+forward and backward passes, the residual and its mean-squared-error
+gradient, the cube-symmetry augmentation, Adam); this module only orders the
+calls.
 
 Training pairs: each seeded box is evolved with the 2x mesh; at a set of
 snapshots both the 1x and the 2x mesh compute grad phi on the *same*
@@ -83,23 +84,12 @@ def make_pairs(seeds, n_p: int, n1: int, box: float, a_snaps, steps: int, spectr
     return out, c1
 
 
-def cube_symmetry(pos: torch.Tensor, u: torch.Tensor, target: torch.Tensor, perm, signs):
-    """One of the 48 symmetries of the periodic cube applied to a snapshot: axes permuted by perm, axis d
-    reflected (x -> 1 - x) where signs[d] < 0; momenta and force differences transform as vectors.  The
-    mesh, the CIC weights and the centred differences map onto themselves, so the 1x fields the library
-    computes from the transformed particles are the transformed fields."""
-    perm = list(perm)
-    sg = torch.tensor(signs, dtype=torch.float64, device=pos.device)
-    p = pos[:, perm]
-    p = torch.where(sg < 0, 1.0 - p, p)
-    return (p.contiguous(), (u[:, perm] * sg.to(u.dtype)).contiguous(),
-            (target[:, perm] * sg.to(target.dtype)).contiguous())
-
-
 def train(ctx1: PMContext, snaps, params: torch.Tensor, iters: int, lr: float = 1e-3, log=print, log_every=100,
           augment: bool = False, lr_final: float = 1.0):
     """Adam on the particle MSE; returns (params, loss history).  With `augment` every iteration applies a
-    random cube symmetry to its snapshot; the learning rate follows a cosine from lr to lr * lr_final."""
+    random symmetry of the periodic cube (pm_cube_symmetry) to its snapshot; the learning rate follows a cosine
+    from lr to lr * lr_final.  Every step is library calls: the PM solve, the forward pass, the residual and
+    its MSE gradient (pm_closure_loss), the backward pass and Adam."""
     dev = ctx1.device
     p = params.to(dev).float().contiguous().clone()
     m = torch.zeros_like(p)
@@ -107,19 +97,23 @@ def train(ctx1: PMContext, snaps, params: torch.Tensor, iters: int, lr: float = 
     ctx1.closure_set_params(p)
     hist = []
     r = np.random.default_rng(1)
+    dpred = torch.empty((ctx1.np, 3), dtype=torch.float32, device=dev)
+    aug = None
     for it in range(1, iters + 1):
         s = snaps[int(r.integers(len(snaps)))]
         pos, u, target = s.pos, s.u, s.target
         if augment:
-            pos, u, target = cube_symmetry(pos, u, target, r.permutation(3), r.choice([-1.0, 1.0], 3))
+            perm, signs = r.permutation(3), r.choice([-1.0, 1.0], 3)
+            if aug is None:
+                aug = (torch.empty_like(pos), torch.empty_like(u), torch.empty_like(target))
+            pos, u, target = ctx1.cube_symmetry(pos, u, target, perm, sum(1 << d for d in range(3) if signs[d] < 0),
+                                                out=aug)
         ctx1.init_particles(pos, u, s.tau)
         ctx1.deposit()
         ctx1.solve_metric(0.0)
         ctx1.closure_forward(False)
-        pred = ctx1.closure_gather()
-        diff = pred - target
-        loss = float((diff * diff).mean())
-        g = ctx1.closure_backward(diff * (2.0 / diff.numel()))
+        loss, _, _ = ctx1.closure_loss(target, dpred)
+        g = ctx1.closure_backward(dpred)
         lr_it = lr * (lr_final + (1.0 - lr_final) * 0.5 * (1.0 + math.cos(math.pi * (it - 1) / max(iters - 1, 1))))
         ctx1.closure_adam(p, m, v, g, it, lr_it)
         hist.append(loss)
@@ -132,14 +126,15 @@ def evaluate(ctx1: PMContext, snaps, params: torch.Tensor):
     """(mean |target|^2, mean |pred - target|^2) over snapshots: plain 1x error vs error with the closure."""
     ctx1.closure_set_params(params)
     plain, corr = [], []
+    dpred = torch.empty((ctx1.np, 3), dtype=torch.float32, device=ctx1.device)
     for s in snaps:
         ctx1.init_particles(s.pos, s.u, s.tau)
         ctx1.deposit()
         ctx1.solve_metric(0.0)
         ctx1.closure_forward(False)
-        pred = ctx1.closure_gather()
-        plain.append(float((s.target * s.target).mean()))
-        corr.append(float(((pred - s.target) ** 2).mean()))
+        e, t, _ = ctx1.closure_loss(s.target, dpred)
+        plain.append(t)
+        corr.append(e)
     return float(np.mean(plain)), float(np.mean(corr))
 
 

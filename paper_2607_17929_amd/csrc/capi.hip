@@ -98,13 +98,13 @@ Layout make_layout(const pm_config& c) {
     L.cl_wf = take(3 * 27 * 256 * 2);
     L.cl_wb = take(3 * 27 * 256 * 2);
     L.cl_bias = take(3 * 16 * 4);
-    L.cl_scal = take(1024 * 8);
-    // training buffers only on meshes up to 256^3 (weight-gradient partials grow with n^3)
+    L.cl_scal = take(2048 * 8);  // [0..528) features, [4..6) loss, [1024..2048) loss partials
+    // training buffers only on meshes up to 256^3 (the back-propagated activations grow with n^3)
     L.cl_train = n <= 256;
     if (L.cl_train) {
       for (int i = 0; i < 3; ++i) L.cl_dact[i] = take(n3 * 32);
       L.cl_dcorr = take(3 * n3 * 4);
-      L.cl_part = take((n3 / 512) * (27 * 256 + 16) * 4);
+      L.cl_part = take((size_t)closure_wgrad_part_bytes(n));
     }
   }
   L.err = take(64);
@@ -1310,6 +1310,44 @@ pm_status pm_closure_backward(pm_ctx* c, const float* d_dpred, float* d_grad) {
   closure_conv(d2, wb + 27 * 256, nullptr, n, 2, d1, a1, nullptr, c->st);
   closure_wgrad(a0, d1, n, part, 4, 16, d_grad, 0, c->st);
   return c->hip_check("closure_backward");
+}
+
+pm_status pm_closure_loss(pm_ctx* c, const float* d_target, float* d_dpred, double* loss) {
+  pm_status s = closure_ready(c, true);
+  if (s != PM_OK) return s;
+  if (!d_target || !d_dpred) return PM_EINVAL;
+  if (!c->cl_forwarded) return c->fail(PM_ESTATE, "closure_loss needs closure_forward");
+  if (c->np < 1) return c->fail(PM_ESTATE, "closure_loss needs particles");
+  const Layout& L = c->L;
+  double* cs = c->at<double>(L.cl_scal);
+  if (c->cfg.precision == PM_FP64)
+    closure_loss3<double>(c->parts<double>(c->cur), c->np, c->n, c->at<float>(L.cl_corr), d_target, d_dpred, cs + 1024,
+                          cs + 4, c->st);
+  else
+    closure_loss3<float>(c->parts<float>(c->cur), c->np, c->n, c->at<float>(L.cl_corr), d_target, d_dpred, cs + 1024,
+                         cs + 4, c->st);
+  if (loss) {
+    if (hipMemcpyAsync(loss, cs + 4, 2 * sizeof(double), hipMemcpyDeviceToHost, c->st) != hipSuccess ||
+        hipStreamSynchronize(c->st) != hipSuccess)
+      return c->fail(PM_EHIP, "reading the closure loss failed");
+  }
+  return c->hip_check("closure_loss");
+}
+
+pm_status pm_cube_symmetry(pm_ctx* c, long n, const int* perm, int flip, const double* d_pos, const float* d_u,
+                           const float* d_v, double* d_pos_out, float* d_u_out, float* d_v_out) {
+  if (!c) return PM_EINVAL;
+  if (!perm || n < 0 || flip < 0 || flip > 7) return c->fail(PM_EINVAL, "cube_symmetry: bad arguments");
+  bool seen[3] = {false, false, false};
+  for (int d = 0; d < 3; ++d) {
+    if (perm[d] < 0 || perm[d] > 2 || seen[perm[d]])
+      return c->fail(PM_EINVAL, "cube_symmetry: perm must be a permutation of 0, 1, 2");
+    seen[perm[d]] = true;
+  }
+  if (n == 0) return PM_OK;
+  if (!d_pos || !d_u || !d_v || !d_pos_out || !d_u_out || !d_v_out) return PM_EINVAL;
+  closure_cube_symmetry(n, perm, flip, d_pos, d_u, d_v, d_pos_out, d_u_out, d_v_out, c->st);
+  return c->hip_check("cube_symmetry");
 }
 
 pm_status pm_closure_adam(pm_ctx* c, float* d_params, float* d_m, float* d_v, const float* d_grad, int step,

@@ -14,7 +14,10 @@
 // computes a 16 x 8 x 4 block of points from an LDS copy of its input block
 // plus a one-point margin.  The backward pass with respect to the input is the
 // same kernel with flipped, transposed weights and a ReLU mask; the weight
-// gradients are accumulated in FP32 per block and reduced in a fixed order.
+// gradient is a second implicit GEMM on the matrix cores (K = points), its
+// per-workgroup FP32 partials reduced in FP64 in a fixed order.  The training
+// residual, its mean square and the augmentation by cube symmetries are
+// kernels here too, so a training step is library calls only.
 #include "kernels.h"
 
 namespace gpm {
@@ -110,54 +113,120 @@ __global__ __launch_bounds__(CV_NT) void conv16_kernel(const uint16_t* __restric
   }
 }
 
-// Weight gradient of one layer over one block: dW[t][co][ci] = sum_p x[p + d_t][ci] dy[p][co],
-// db[co] = sum_p dy[p][co]; thread (co, ci) = (tid % 16, tid / 16) accumulates its 27 taps.
+// Weight gradient of one layer on the matrix cores: for each tap t,
+// dW_t[co][ci] = sum_p dy[p][co] x[p + d_t][ci] is a 16 x 16 GEMM with K running over the
+// points.  One MFMA takes 32 points (two x-rows of a 16 x 8 x 4 tile): A[co][k] = dy[p_k][co],
+// B[k][ci] = x[p_k + d_t][ci].  Both operands need 8 consecutive points per lane for one
+// channel, so the tile is transposed into LDS channel-major ([ci][hz][hy][hx] with rows of
+// WG_ROW elements, [co][row][lx] for dy); the x-shift of a tap is then a funnel shift of
+// two aligned words.  Wave w owns taps w, w + 4, ..., and wave 3's spare slot accumulates the
+// bias gradient (B = ones).  A workgroup walks tiles blockIdx.x, + gridDim.x, ... and writes
+// one FP32 partial; the partials are summed in a fixed order in FP64.
+constexpr int WG_ROW = 24;                              // LDS row: 18 halo points + pad, 16-byte aligned
+constexpr int WG_CI = CV_HZ * CV_HY * WG_ROW + 8;       // channel stride (pad spreads the banks)
+constexpr int WG_CO = CV_TX * CV_TY * CV_TZ + 8;        // dy channel stride
+constexpr int WG_PART = 27 * 256 + 16;                  // one partial: [t][co][ci] then the bias [co]
+constexpr int WG_GRID = 512;                            // workgroups (partials) at most
+
 __global__ __launch_bounds__(CV_NT) void conv16_wgrad_kernel(const uint16_t* __restrict__ x,
-                                                             const uint16_t* __restrict__ dy, int n,
+                                                             const uint16_t* __restrict__ dy, int n, long ntiles,
                                                              float* __restrict__ part) {
-  __shared__ uint4 tile[CV_HP * 2];
-  __shared__ uint4 dyt[CV_TX * CV_TY * CV_TZ * 2];
-  const int x0 = blockIdx.x * CV_TX, y0 = blockIdx.y * CV_TY, z0 = blockIdx.z * CV_TZ;
-  load_halo(x, n, x0, y0, z0, tile);
-  for (int q = threadIdx.x; q < CV_TX * CV_TY * CV_TZ * 2; q += CV_NT) {
-    const int pt = q >> 1, half = q & 1;
-    const int lx = pt % CV_TX, ly = (pt / CV_TX) % CV_TY, lz = pt / (CV_TX * CV_TY);
-    const long g = ((long)(z0 + lz) * n + (y0 + ly)) * n + (x0 + lx);
-    dyt[q] = reinterpret_cast<const uint4*>(dy + g * 16)[half];
-  }
-  __syncthreads();
-  const int co = threadIdx.x & 15, ci = threadIdx.x >> 4;
-  const uint16_t* ts = reinterpret_cast<const uint16_t*>(tile);
-  const uint16_t* ds = reinterpret_cast<const uint16_t*>(dyt);
-  float acc[27];
+  __shared__ __align__(16) uint16_t xt[16 * WG_CI];
+  __shared__ __align__(16) uint16_t dyt[16 * WG_CO];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int col = lane & 15, grp = lane >> 4;
+  const int ntx = n / CV_TX, nty = n / CV_TY;
+  const int m = n - 1;
+  const long nn = (long)n * n;
+  v4f acc[7];
 #pragma unroll
-  for (int t = 0; t < 27; ++t) acc[t] = 0.f;
-  float db = 0.f;
-  for (int pt = 0; pt < CV_TX * CV_TY * CV_TZ; ++pt) {
-    const int lx = pt % CV_TX, ly = (pt / CV_TX) % CV_TY, lz = pt / (CV_TX * CV_TY);
-    const float g = bf2f(ds[pt * 16 + co]);
-    db += g;
+  for (int j = 0; j < 7; ++j) acc[j] = v4f{0.f, 0.f, 0.f, 0.f};
+  const v8bf ones = __builtin_bit_cast(v8bf, make_uint4(0x3f803f80u, 0x3f803f80u, 0x3f803f80u, 0x3f803f80u));
+  for (long tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    const int x0 = (int)(tile % ntx) * CV_TX, y0 = (int)((tile / ntx) % nty) * CV_TY;
+    const int z0 = (int)(tile / ((long)ntx * nty)) * CV_TZ;
+    __syncthreads();  // the previous tile's operands are consumed
+    for (int q = threadIdx.x; q < CV_HP * 2; q += CV_NT) {
+      const int pt = q >> 1, half = q & 1;
+      const int hx = pt % CV_HX, hy = (pt / CV_HX) % CV_HY, hz = pt / (CV_HX * CV_HY);
+      const long g = (long)((z0 - 1 + hz) & m) * nn + (long)((y0 - 1 + hy) & m) * n + ((x0 - 1 + hx) & m);
+      const uint4 v = reinterpret_cast<const uint4*>(x + g * 16)[half];
+      const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+      uint16_t* d = xt + (8 * half) * WG_CI + (hz * CV_HY + hy) * WG_ROW + hx;
 #pragma unroll
-    for (int t = 0; t < 27; ++t) {
-      const int hx = lx + 1 + tap_dx(t), hy = ly + 1 + tap_dy(t), hz = lz + 1 + tap_dz(t);
-      acc[t] += g * bf2f(ts[((hz * CV_HY + hy) * CV_HX + hx) * 16 + ci]);
+      for (int c = 0; c < 8; ++c) d[c * WG_CI] = (uint16_t)(w[c >> 1] >> (16 * (c & 1)));
+    }
+    for (int q = threadIdx.x; q < CV_TX * CV_TY * CV_TZ * 2; q += CV_NT) {
+      const int pt = q >> 1, half = q & 1;
+      const int lx = pt % CV_TX, row = pt / CV_TX;  // row = ly + 8 lz
+      const long g = ((long)(z0 + row / CV_TY) * n + (y0 + row % CV_TY)) * n + (x0 + lx);
+      const uint4 v = reinterpret_cast<const uint4*>(dy + g * 16)[half];
+      const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+      uint16_t* d = dyt + (8 * half) * WG_CO + pt;
+#pragma unroll
+      for (int c = 0; c < 8; ++c) d[c * WG_CO] = (uint16_t)(w[c >> 1] >> (16 * (c & 1)));
+    }
+    __syncthreads();
+    // lane (col, grp) of K-step s: points lx = 8 (grp & 1) + e, e < 8, of row 2 s + (grp >> 1)
+    const int xb = 8 * (grp & 1);
+    for (int s = 0; s < CV_TY * CV_TZ / 2; ++s) {
+      const int row = 2 * s + (grp >> 1);
+      const int ly = row % CV_TY, lz = row / CV_TY;
+      const v8bf a = __builtin_bit_cast(v8bf, *reinterpret_cast<const uint4*>(dyt + col * WG_CO + row * CV_TX + xb));
+#pragma unroll
+      for (int j = 0; j < 7; ++j) {
+        const int t = wave + 4 * j;
+        if (t < 27) {
+          const int hz = lz + 1 + tap_dz(t), hy = ly + 1 + tap_dy(t), dx = tap_dx(t);
+          const uint16_t* r = xt + col * WG_CI + (hz * CV_HY + hy) * WG_ROW + xb;
+          // halo points xb + 1 + dx + e: from the aligned words at xb .. xb + 9
+          const uint4 w = *reinterpret_cast<const uint4*>(r);
+          uint4 b;
+          if (dx < 0) {
+            b = w;
+          } else {
+            const uint32_t w4 = *reinterpret_cast<const uint32_t*>(r + 8);
+            if (dx > 0) b = make_uint4(w.y, w.z, w.w, w4);
+            else b = make_uint4(__builtin_amdgcn_alignbit(w.y, w.x, 16), __builtin_amdgcn_alignbit(w.z, w.y, 16),
+                                __builtin_amdgcn_alignbit(w.w, w.z, 16), __builtin_amdgcn_alignbit(w4, w.w, 16));
+          }
+          acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, __builtin_bit_cast(v8bf, b), acc[j], 0, 0, 0);
+        } else {
+          acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, ones, acc[j], 0, 0, 0);
+        }
+      }
     }
   }
-  const long blk = ((long)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
-  float* o = part + blk * (27 * 256 + 16);
+  // D: lane holds co = 4 grp + r of column ci = col
+  float* o = part + (long)blockIdx.x * WG_PART;
 #pragma unroll
-  for (int t = 0; t < 27; ++t) o[(t * 16 + co) * 16 + ci] = acc[t];
-  if (ci == 0) o[27 * 256 + co] = db;
+  for (int j = 0; j < 7; ++j) {
+    const int t = wave + 4 * j;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int co = 4 * grp + r;
+      if (t < 27) o[(t * 16 + co) * 16 + col] = acc[j][r];
+      else if (col == 0) o[27 * 256 + co] = acc[j][r];
+    }
+  }
 }
 
-// sum the per-block partials in a fixed order and scatter into the flat parameter-gradient layout
-// W[co][ci][27] b[co] of layer (ci_n -> co_n) at offset off
-__global__ __launch_bounds__(256) void wgrad_reduce_kernel(const float* __restrict__ part, long nblk, int ci_n, int co_n,
+// sum the partials in a fixed order (FP64) and scatter into the flat parameter-gradient layout
+// W[co][ci][27] b[co] of layer (ci_n -> co_n) at offset off; 64 entries per workgroup, each wave
+// adds a contiguous quarter of the partials and the quarters are combined in order
+__global__ __launch_bounds__(256) void wgrad_reduce_kernel(const float* __restrict__ part, int nblk, int ci_n, int co_n,
                                                            float* __restrict__ grad, long off) {
-  const int e = blockIdx.x * blockDim.x + threadIdx.x;  // entry of the (27*256 + 16) partial
-  if (e >= 27 * 256 + 16) return;
+  __shared__ double q[4][64];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int e = blockIdx.x * 64 + lane;
+  const int lo = wave * nblk / 4, hi = (wave + 1) * nblk / 4;
   double s = 0.0;
-  for (long b = 0; b < nblk; ++b) s += (double)part[b * (27 * 256 + 16) + e];
+  if (e < WG_PART)
+    for (int b = lo; b < hi; ++b) s += (double)part[(long)b * WG_PART + e];
+  q[wave][lane] = s;
+  __syncthreads();
+  if (wave != 0 || e >= WG_PART) return;
+  s = ((q[0][lane] + q[1][lane]) + q[2][lane]) + q[3][lane];
   if (e < 27 * 256) {
     const int t = e / 256, co = (e / 16) % 16, ci = e % 16;
     if (co < co_n && ci < ci_n) grad[off + ((long)co * ci_n + ci) * 27 + t] = (float)s;
@@ -284,25 +353,129 @@ __device__ __forceinline__ void cic(double x, int n, int& i0, int& i1, float& w0
   w1 = f;
 }
 
+// CIC interpolation of the 3-component FP32 SoA field f at particle i
 template <typename T>
-__global__ __launch_bounds__(256) void gather3_kernel(Particles<T> p, long np, int n, const float* __restrict__ f,
-                                                      float* __restrict__ out) {
-  const long i = (long)blockIdx.x * 256 + threadIdx.x;
-  if (i >= np) return;
+__device__ __forceinline__ void gather3_at(const Particles<T>& p, long i, int n, const float* __restrict__ f,
+                                           float v[3]) {
   int x0, x1, y0, y1, z0, z1;
   float wx0, wx1, wy0, wy1, wz0, wz1;
   cic(p.px[i], n, x0, x1, wx0, wx1);
   cic(p.py[i], n, y0, y1, wy0, wy1);
   cic(p.pz[i], n, z0, z1, wz0, wz1);
   const long nn = (long)n * n, n3 = nn * n;
-  const long id = p.id[i];
+#pragma unroll
   for (int c = 0; c < 3; ++c) {
     const float* g = f + c * n3;
-    const float v = wz0 * (wy0 * (wx0 * g[z0 * nn + y0 * n + x0] + wx1 * g[z0 * nn + y0 * n + x1]) +
-                           wy1 * (wx0 * g[z0 * nn + y1 * n + x0] + wx1 * g[z0 * nn + y1 * n + x1])) +
-                    wz1 * (wy0 * (wx0 * g[z1 * nn + y0 * n + x0] + wx1 * g[z1 * nn + y0 * n + x1]) +
-                           wy1 * (wx0 * g[z1 * nn + y1 * n + x0] + wx1 * g[z1 * nn + y1 * n + x1]));
-    out[3 * id + c] = v;
+    v[c] = wz0 * (wy0 * (wx0 * g[z0 * nn + y0 * n + x0] + wx1 * g[z0 * nn + y0 * n + x1]) +
+                  wy1 * (wx0 * g[z0 * nn + y1 * n + x0] + wx1 * g[z0 * nn + y1 * n + x1])) +
+           wz1 * (wy0 * (wx0 * g[z1 * nn + y0 * n + x0] + wx1 * g[z1 * nn + y0 * n + x1]) +
+                  wy1 * (wx0 * g[z1 * nn + y1 * n + x0] + wx1 * g[z1 * nn + y1 * n + x1]));
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void gather3_kernel(Particles<T> p, long np, int n, const float* __restrict__ f,
+                                                      float* __restrict__ out) {
+  const long i = (long)blockIdx.x * 256 + threadIdx.x;
+  if (i >= np) return;
+  float v[3];
+  gather3_at(p, i, n, f, v);
+  const long id = p.id[i];
+  for (int c = 0; c < 3; ++c) out[3 * id + c] = v[c];
+}
+
+// Training residual: pred = gathered network output, r = pred - target (FP32, identifier order),
+// dpred = gscale r, and FP64 per-workgroup sums of |r|^2 and |target|^2 (fixed grid, fixed order).
+constexpr int LOSS_BLOCKS = 512;
+template <typename T>
+__global__ __launch_bounds__(256) void loss3_kernel(Particles<T> p, long np, int n, const float* __restrict__ f,
+                                                    const float* __restrict__ target, float gscale,
+                                                    float* __restrict__ dpred, double* __restrict__ part) {
+  __shared__ double red[2][256];
+  double e2 = 0.0, t2 = 0.0;
+  for (long i = (long)blockIdx.x * 256 + threadIdx.x; i < np; i += (long)gridDim.x * 256) {
+    float v[3];
+    gather3_at(p, i, n, f, v);
+    const long id = p.id[i];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const float tg = target[3 * id + c];
+      const float r = v[c] - tg;
+      dpred[3 * id + c] = r * gscale;
+      e2 += (double)r * (double)r;
+      t2 += (double)tg * (double)tg;
+    }
+  }
+  red[0][threadIdx.x] = e2;
+  red[1][threadIdx.x] = t2;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) {
+      red[0][threadIdx.x] += red[0][threadIdx.x + s];
+      red[1][threadIdx.x] += red[1][threadIdx.x + s];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    part[2 * blockIdx.x] = red[0][0];
+    part[2 * blockIdx.x + 1] = red[1][0];
+  }
+}
+
+// out[0] = mean |r|^2, out[1] = mean |target|^2 over the 3 np components
+__global__ __launch_bounds__(256) void loss3_final_kernel(const double* __restrict__ part, int nb, double inv_count,
+                                                          double* __restrict__ out) {
+  __shared__ double red[2][256];
+  double e2 = 0.0, t2 = 0.0;
+  for (int b = threadIdx.x; b < nb; b += 256) {
+    e2 += part[2 * b];
+    t2 += part[2 * b + 1];
+  }
+  red[0][threadIdx.x] = e2;
+  red[1][threadIdx.x] = t2;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) {
+      red[0][threadIdx.x] += red[0][threadIdx.x + s];
+      red[1][threadIdx.x] += red[1][threadIdx.x + s];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    out[0] = red[0][0] * inv_count;
+    out[1] = red[1][0] * inv_count;
+  }
+}
+
+// One of the 48 symmetries of the periodic unit cube on particle data: component d of the result
+// is component perm[d] of the input, reflected (x -> 1 - x, wrapped into [0, 1)) for positions and
+// negated for the two vector fields where flip bit d is set.  Each thread reads its particle before
+// writing it, so the outputs may alias the inputs.
+__global__ __launch_bounds__(256) void cube_symmetry_kernel(long np, int p0, int p1, int p2, int flip,
+                                                            const double* pos, const float* u, const float* v,
+                                                            double* pos_out, float* u_out, float* v_out) {
+  const long i = (long)blockIdx.x * 256 + threadIdx.x;
+  if (i >= np) return;
+  const int perm[3] = {p0, p1, p2};
+  double x[3];
+  float a[3], b[3];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    x[d] = pos[3 * i + perm[d]];
+    a[d] = u[3 * i + perm[d]];
+    b[d] = v[3 * i + perm[d]];
+  }
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    const bool f = (flip >> d) & 1;
+    double y = x[d];
+    if (f) {
+      y = 1.0 - y;
+      if (y >= 1.0) y -= 1.0;
+    }
+    pos_out[3 * i + d] = y;
+    u_out[3 * i + d] = f ? -a[d] : a[d];
+    v_out[3 * i + d] = f ? -b[d] : b[d];
   }
 }
 
@@ -391,14 +564,22 @@ void closure_conv(const uint16_t* in, const uint16_t* w, const float* bias, int 
     hipLaunchKernelGGL((conv16_kernel<2>), grid, dim3(CV_NT), 0, st, in, w, bias, n, out, mask, scale);
 }
 
-long closure_wgrad_blocks(int n) { return (long)(n / CV_TX) * (n / CV_TY) * (n / CV_TZ); }
+static long closure_wgrad_tiles(int n) { return (long)(n / CV_TX) * (n / CV_TY) * (n / CV_TZ); }
+// workgroups of the weight-gradient kernel: every workgroup takes at least two tiles (so that the
+// tile walk runs at every size), at most WG_GRID workgroups
+static int closure_wgrad_grid(int n) {
+  const long h = closure_wgrad_tiles(n) / 2;
+  return (int)(h < 1 ? 1 : (h < WG_GRID ? h : WG_GRID));
+}
+long closure_wgrad_part_bytes(int n) { return (long)closure_wgrad_grid(n) * WG_PART * 4; }
 
 void closure_wgrad(const uint16_t* x, const uint16_t* dy, int n, float* part, int ci_n, int co_n, float* grad,
                    long off, hipStream_t st) {
-  dim3 grid(n / CV_TX, n / CV_TY, n / CV_TZ);
-  hipLaunchKernelGGL(conv16_wgrad_kernel, grid, dim3(CV_NT), 0, st, x, dy, n, part);
-  hipLaunchKernelGGL(wgrad_reduce_kernel, dim3((27 * 256 + 16 + 255) / 256), dim3(256), 0, st, part,
-                     closure_wgrad_blocks(n), ci_n, co_n, grad, off);
+  const long tiles = closure_wgrad_tiles(n);
+  const int grid = closure_wgrad_grid(n);
+  hipLaunchKernelGGL(conv16_wgrad_kernel, dim3(grid), dim3(CV_NT), 0, st, x, dy, n, tiles, part);
+  hipLaunchKernelGGL(wgrad_reduce_kernel, dim3((WG_PART + 63) / 64), dim3(256), 0, st, part, grid, ci_n, co_n, grad,
+                     off);
 }
 
 void closure_adam(float* p, float* m, float* v, const float* g, int np, double lr, int step, hipStream_t st) {
@@ -425,6 +606,22 @@ void closure_gather3(const Particles<T>& p, long np, int n, const float* f, floa
 }
 
 template <typename T>
+void closure_loss3(const Particles<T>& p, long np, int n, const float* f, const float* target, float* dpred,
+                   double* part, double* out, hipStream_t st) {
+  const long want = (np + 255) / 256;
+  const int nb = (int)(want < LOSS_BLOCKS ? (want > 0 ? want : 1) : LOSS_BLOCKS);
+  const float gscale = (float)(2.0 / (3.0 * (double)np));
+  hipLaunchKernelGGL((loss3_kernel<T>), dim3(nb), dim3(256), 0, st, p, np, n, f, target, gscale, dpred, part);
+  hipLaunchKernelGGL(loss3_final_kernel, dim3(1), dim3(256), 0, st, part, nb, 1.0 / (3.0 * (double)np), out);
+}
+
+void closure_cube_symmetry(long np, const int perm[3], int flip, const double* pos, const float* u, const float* v,
+                           double* pos_out, float* u_out, float* v_out, hipStream_t st) {
+  hipLaunchKernelGGL(cube_symmetry_kernel, dim3((unsigned)((np + 255) / 256)), dim3(256), 0, st, np, perm[0], perm[1],
+                     perm[2], flip, pos, u, v, pos_out, u_out, v_out);
+}
+
+template <typename T>
 void closure_gather3_adjoint(const Particles<T>& p, long np, int n, const float* vals, float* f, hipStream_t st) {
   hipLaunchKernelGGL((gather3_adjoint_kernel<T>), dim3((unsigned)((np + 255) / 256)), dim3(256), 0, st, p, np, n, vals,
                      f);
@@ -444,6 +641,8 @@ void gather_grad_phi(const Particles<T>& p, long np, int n, const T* phi, T* out
   template void closure_features<T>(const T*, const T*, int, const double*, double*, float*, uint16_t*, hipStream_t); \
   template void closure_gather3<T>(const Particles<T>&, long, int, const float*, float*, hipStream_t);          \
   template void closure_gather3_adjoint<T>(const Particles<T>&, long, int, const float*, float*, hipStream_t);  \
+  template void closure_loss3<T>(const Particles<T>&, long, int, const float*, const float*, float*, double*,     \
+                                 double*, hipStream_t);                                                          \
   template void gather_grad_phi<T>(const Particles<T>&, long, int, const T*, T*, hipStream_t);
 GPM_CL_INST(float)
 GPM_CL_INST(double)

@@ -157,7 +157,7 @@ void launch_copy_unpad(const cplx<T>* spec, int n, int nhp, cplx<T>* out, bool t
 void closure_pack(const float* params, uint16_t* wf, uint16_t* wb, float* bias, hipStream_t st);
 void closure_conv(const uint16_t* in, const uint16_t* w, const float* bias, int n, int mode, void* out,
                   const uint16_t* mask, const float* scale, hipStream_t st);
-long closure_wgrad_blocks(int n);
+long closure_wgrad_part_bytes(int n);  // weight-gradient partials of one layer (bytes)
 void closure_wgrad(const uint16_t* x, const uint16_t* dy, int n, float* part, int ci_n, int co_n, float* grad,
                    long off, hipStream_t st);
 void closure_adam(float* p, float* m, float* v, const float* g, int np, double lr, int step, hipStream_t st);
@@ -168,6 +168,13 @@ template <typename T>
 void closure_gather3(const Particles<T>& p, long np, int n, const float* f, float* out, hipStream_t st);
 template <typename T>
 void closure_gather3_adjoint(const Particles<T>& p, long np, int n, const float* vals, float* f, hipStream_t st);
+// pred - target at the particles: dpred = 2 (pred - target) / (3 np), out[0] = mean |pred - target|^2,
+// out[1] = mean |target|^2 (FP64); part holds 2 x 512 doubles of scratch
+template <typename T>
+void closure_loss3(const Particles<T>& p, long np, int n, const float* f, const float* target, float* dpred,
+                   double* part, double* out, hipStream_t st);
+void closure_cube_symmetry(long np, const int perm[3], int flip, const double* pos, const float* u, const float* v,
+                           double* pos_out, float* u_out, float* v_out, hipStream_t st);
 void closure_soa3_to_bf16(const float* f, long n3, uint16_t* out, hipStream_t st);
 template <typename T>
 void gather_grad_phi(const Particles<T>& p, long np, int n, const T* phi, T* out, hipStream_t st);

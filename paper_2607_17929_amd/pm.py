@@ -331,6 +331,37 @@ class PMContext:
                   "pm_closure_backward")
         return g
 
+    def closure_loss(self, target: torch.Tensor, dpred: torch.Tensor | None = None, read: bool = True):
+        """Residual of the last forward pass against target ([n][3] FP32, identifier order): returns
+        (mean |pred - target|^2, mean |target|^2, dpred) with dpred the MSE gradient that
+        closure_backward takes (written into `dpred` when given); with read=False the two means stay on
+        the device and are returned as None (no synchronisation)."""
+        t = target.to(device=self.device, dtype=torch.float32).contiguous()
+        assert t.shape == (self.np, 3)
+        if dpred is None:
+            dpred = torch.empty((self.np, 3), dtype=torch.float32, device=self.device)
+        assert dpred.is_cuda and dpred.dtype == torch.float32 and dpred.is_contiguous() and dpred.shape == (self.np, 3)
+        out = (C.c_double * 2)()
+        self._chk(self.lib.pm_closure_loss(self.ctx, C.c_void_p(_ptr(t)), C.c_void_p(_ptr(dpred)),
+                                           out if read else None), "pm_closure_loss")
+        return (out[0], out[1], dpred) if read else (None, None, dpred)
+
+    def cube_symmetry(self, pos: torch.Tensor, u: torch.Tensor, v: torch.Tensor, perm, flip: int, out=None):
+        """One of the 48 symmetries of the periodic cube on [n][3] device arrays (positions FP64, two FP32 vector
+        fields): component d of the result is component perm[d] of the input; where bit d of flip is set the
+        position is reflected (x -> 1 - x) and both vectors are negated.  Returns (pos, u, v); `out` may be the
+        inputs themselves."""
+        for t, dt in ((pos, torch.float64), (u, torch.float32), (v, torch.float32)):
+            assert t.is_cuda and t.dtype == dt and t.is_contiguous() and t.dim() == 2 and t.shape[1] == 3
+        n = pos.shape[0]
+        assert u.shape[0] == n and v.shape[0] == n
+        if out is None:
+            out = (torch.empty_like(pos), torch.empty_like(u), torch.empty_like(v))
+        p3 = (C.c_int * 3)(*[int(q) for q in perm])
+        self._chk(self.lib.pm_cube_symmetry(self.ctx, n, p3, int(flip), *(C.c_void_p(_ptr(t)) for t in (pos, u, v)),
+                                            *(C.c_void_p(_ptr(t)) for t in out)), "pm_cube_symmetry")
+        return out
+
     def closure_adam(self, params: torch.Tensor, m: torch.Tensor, v: torch.Tensor, grad: torch.Tensor, step: int,
                      lr: float):
         for t in (params, m, v, grad):

@@ -2,7 +2,7 @@
 and a small training run that must beat the plain 1x force on held-out data.
 
 Tolerances: the forward output and the weight
-gradients are compared in relative L2; bfloat16 has a unit roundoff of 2^-9,
+gradients (two tiles per workgroup of the weight-gradient kernel at 32^3) are compared in relative L2; bfloat16 has a unit roundoff of 2^-9,
 and an occasional one-ulp difference in a rounded activation (FP32 versus FP64
 accumulation right at a rounding boundary) perturbs the output by about that
 much at a handful of points, so 2e-3 bounds the output and 2e-2 the gradients
@@ -65,6 +65,53 @@ def test_closure_forward_and_backward_parity():
         ek = rel_l2(g[offs[k]:offs[k + 1]], gref[offs[k]:offs[k + 1]])
         print(f"layer {k + 1} gradient rel-L2 {ek:.3e}", flush=True)
         assert ek < 2e-2
+
+
+def test_closure_loss_against_oracle():
+    """pm_closure_loss: the residual of the gathered output against a target, its MSE gradient and the two
+    FP64 means, against the oracle's MSE on the same prediction (the GPU forms the residual in FP32)."""
+    print("closure loss", flush=True)
+    ctx, sim, n00, pos, n = _setup()
+    ctx.closure_set_params(torch.tensor(_params(), dtype=torch.float32))
+    ctx.closure_forward(False)
+    pred = ctx.closure_gather().cpu().numpy()
+    target = np.random.default_rng(11).standard_normal(pred.shape).astype(np.float32)
+    loss, tms, dpred = ctx.closure_loss(torch.tensor(target))
+    ref_loss, ref_tms, ref_d = cnn.mse_loss(pred, target)
+    assert abs(loss - ref_loss) < 1e-6 * ref_loss
+    assert abs(tms - ref_tms) < 1e-12 * ref_tms
+    assert rel_l2(dpred.cpu().numpy(), ref_d) < 1e-6
+    # read=False leaves the means on the device and still writes the gradient
+    d2 = torch.zeros_like(dpred)
+    assert ctx.closure_loss(torch.tensor(target), d2, read=False)[:2] == (None, None)
+    assert torch.equal(d2, dpred)
+
+
+def test_cube_symmetry_against_oracle():
+    """pm_cube_symmetry for all 48 maps against the oracle's, bit for bit (including x = 0 and outputs that
+    alias the inputs)."""
+    import itertools
+    from paper_2607_17929_amd import PMContext
+    print("cube symmetry", flush=True)
+    r = np.random.default_rng(12)
+    m = 1000
+    pos = r.random((m, 3))
+    pos[0] = (0.0, 0.5, 0.999999)
+    u = r.standard_normal((m, 3)).astype(np.float32)
+    v = r.standard_normal((m, 3)).astype(np.float32)
+    ctx = PMContext(16, 8, 160.0, physics="scalar", precision="fp32")
+    tp, tu, tv = (torch.tensor(a, device="cuda") for a in (pos, u, v))
+    for perm in itertools.permutations(range(3)):
+        for flip in range(8):
+            gp, gu, gv = ctx.cube_symmetry(tp, tu, tv, perm, flip)
+            rp, ru, rv = cnn.cube_symmetry(pos, u, v, perm, flip)
+            assert np.array_equal(gp.cpu().numpy(), rp) and np.array_equal(gu.cpu().numpy(), ru)
+            assert np.array_equal(gv.cpu().numpy(), rv)
+    ap, au, av = (t.clone() for t in (tp, tu, tv))
+    ctx.cube_symmetry(ap, au, av, (2, 0, 1), 5, out=(ap, au, av))
+    rp, ru, rv = cnn.cube_symmetry(pos, u, v, (2, 0, 1), 5)
+    assert np.array_equal(ap.cpu().numpy(), rp) and np.array_equal(au.cpu().numpy(), ru)
+    assert np.array_equal(av.cpu().numpy(), rv)
 
 
 def test_closure_adam_step_parity():

@@ -16,6 +16,8 @@ properties that hold at any size.
   particles' state before the update, against the GPU's updated particles (both precisions).
 * A linear plane wave on the 512^3 lattice follows the scalar recursion of the discrete
   equations (Newtonian and relativistic scalar).
+* The learned closure's network at 512^3: gathered output on the particles of two 16^3 regions
+  against the oracle's network on the GPU's own fields.
 
 Input: a seeded Zel'dovich set with the benchmark's spectrum and amplitude rule, displaced to
 a = 0.5 (shell-crossed, strongly clustered) -- a synthetic stand-in for the clustered snapshot
@@ -322,6 +324,50 @@ def test_kick_drift_512_sampled_particles(clustered, precision):
         assert dx < 1e-9 and du < 1e-10
     else:
         assert dx < 1e-4 and du < 1e-5
+
+
+def test_closure_forward_512_sampled_regions(clustered):
+    """The closure network at 512^3 (the mesh it is applied on), on the clustered input: its output gathered at
+    every particle of two 16^3 regions (the densest cell's and a random one) against the oracle's network
+    (bfloat16 emulation) on the GPU's own FP32 n00 and phi.  The oracle forms the input features on the whole
+    mesh and runs the three convolutions on the region plus a 3-vertex margin, the network's reach, so the
+    region's values are exact.  Bar as at 32^3: 2e-3 relative L2."""
+    from oracle import cnn
+    from paper_2607_17929_amd import PMContext
+    pos, u, tau, _ = clustered
+    _say("closure forward 512")
+    ctx = PMContext(N, pos.shape[0], BOX, physics="scalar", precision="fp32", closure=True)
+    ctx.init_particles(pos, u.astype(np.float32), tau)
+    ctx.deposit()
+    ctx.solve_metric(0.0)
+    params = (0.15 * np.random.default_rng(3).standard_normal(cnn.N_PARAMS)).astype(np.float32).astype(np.float64)
+    ctx.closure_set_params(torch.tensor(params, dtype=torch.float32))
+    ctx.closure_forward(False)
+    out = ctx.closure_gather().cpu().numpy().astype(np.float64)
+    p_gpu, _ = ctx.get_particles()
+    x, rms = cnn.features(ctx.get_field("n00").astype(np.float64), ctx.get_field("phi").astype(np.float64))
+    assert abs(ctx.closure_scale() - rms) < 1e-6 * rms
+    del ctx
+    torch.cuda.empty_cache()
+    base, _ = opm.cic_cells(p_gpu, N)
+    key = (base[:, 2] * N + base[:, 1]) * N + base[:, 0]
+    dense = int(np.argmax(np.bincount(key, minlength=N ** 3)))
+    del key
+    R, M = 16, 3
+    c = (dense // (N * N), (dense // N) % N, dense % N)
+    r = np.random.default_rng(13)
+    for z0, y0, x0 in [tuple((v - R // 2) % N for v in c), tuple(int(v) for v in r.integers(0, N, 3))]:
+        zi, yi, xi = ((np.arange(-M, R + M) + o) % N for o in (z0, y0, x0))
+        y, _ = cnn.forward(params, x[:, zi][:, :, yi][:, :, :, xi])
+        core = y[:, M:M + R, M:M + R, M:M + R]
+        # particles whose eight CIC vertices are in the region, in region coordinates
+        rel = (base - np.array([x0, y0, z0])) % N
+        sel = np.all(rel <= R - 2, axis=1)
+        local = ((p_gpu[sel] * N - np.array([x0, y0, z0])) % N) / R
+        ref = cnn.gather(core, local)
+        e = rel_l2(out[sel], ref)
+        _say(f"  region {(z0, y0, x0)}: {int(sel.sum())} particles, rel-L2 {e:.2e}")
+        assert sel.sum() > 100 and e < 2e-3
 
 
 @pytest.mark.parametrize("physics", ["newtonian", "scalar"])
