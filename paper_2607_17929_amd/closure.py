@@ -44,8 +44,12 @@ def init_params(seed: int = 0) -> torch.Tensor:
 
 
 def make_pairs(seeds, n_p: int, n1: int, box: float, a_snaps, steps: int, spectrum, rms_cells: float = 0.2,
-               a0: float = 0.02, a1: float = 0.5, physics: str = "scalar", log=print):
-    """Evolve each box on the 2x mesh and collect (particles, normalised force difference) snapshots."""
+               a0: float = 0.02, a1: float = 0.5, physics: str = "scalar", log=print, closure_params=None, c1=None):
+    """Evolve each box and collect (particles, normalised force difference) snapshots.
+
+    Without closure_params the boxes are evolved on the 2x mesh; with them, on the 1x mesh with the closure
+    switched on (on-policy data: the particle states the corrected 1x run actually visits, each labelled with
+    the 2x - 1x force difference on those same particles).  c1 reuses a training context."""
     from synth import zeldovich_particles
     from synth.ics import eds_a_of_tau
 
@@ -53,21 +57,27 @@ def make_pairs(seeds, n_p: int, n1: int, box: float, a_snaps, steps: int, spectr
     tau0, tau1 = tau_of_a(box, a0), tau_of_a(box, a1)
     dtau = (tau1 - tau0) / steps
     snap_taus = sorted(tau_of_a(box, a) for a in a_snaps)
-    c2 = PMContext(n2, n_p, box, physics=physics, precision="fp32")
+    if closure_params is None:
+        ce = PMContext(n2, n_p, box, physics=physics, precision="fp32")
+    else:
+        ce = PMContext(n1, n_p, box, physics=physics, precision="fp32", closure=True)
+        ce.closure_set_params(closure_params)
+        ce.closure_enable(True)
     c2s = PMContext(n2, n_p, box, physics=physics, precision="fp32")
-    c1 = PMContext(n1, n_p, box, physics=physics, precision="fp32", closure=True)
+    if c1 is None:
+        c1 = PMContext(n1, n_p, box, physics=physics, precision="fp32", closure=True)
     out = []
     for seed in seeds:
         t0 = time.time()
         pos, u = zeldovich_particles(round(n_p ** (1 / 3)), seed, spectrum, box, rms_cells, 0.02, a0,
                                      eds_a_of_tau(tau0 - 0.5 * dtau, box))
-        c2.init_particles(pos, u.astype(np.float32), tau0)
+        ce.init_particles(pos, u.astype(np.float32), tau0)
         k = 0
         for i in range(steps):
-            c2.step(dtau)
-            tau = c2.time()[0]
+            ce.step(dtau)
+            tau = ce.time()[0]
             while k < len(snap_taus) and tau >= snap_taus[k] - 1e-9 * tau:
-                p, uu = c2.get_particles(device=True)
+                p, uu = ce.get_particles(device=True)
                 g = []
                 for ctx in (c1, c2s):
                     ctx.init_particles(p, uu, tau)
@@ -226,121 +236,234 @@ def calibrate_amplitude(params, n_p1: int, box: float, rms_cells: float, seeds, 
 
 # P(k) at half the Nyquist frequency moves by about 2 % per 1 % of output amplitude, so the grid is fine
 CAL_SCALES = tuple(round(1.0 + 0.005 * i, 3) for i in range(31))
-VALIDATION_SEEDS = (7, 8)  # the application runs seed 3
+# realizations of the application configuration the closure is judged on: seed 3 is the application run,
+# seeds 7 and 8 are two more realizations of the same configuration; none is used for training or tuning
+EVAL_SEEDS = (3, 7, 8)
+
+
+def _app_setup(n_app: int):
+    app_box = 2048.0 * n_app / 512
+    tau0, tau1 = tau_of_a(app_box, 0.02), tau_of_a(app_box, 0.5)
+    return app_box, tau0, tau1, 100
+
+
+_APP_ICS = {}
+
+
+def _app_particles(n_app: int, seed: int, rms: float = 0.2):
+    """Initial particles of one realization (n_app^3 particles, box 4 n_app Mpc/h, rms displacement `rms` cells at
+    a = 0.02; 0.2 is the application configuration), kept on the device."""
+    from synth import spectrum_power_law_m2, zeldovich_particles
+    from synth.ics import eds_a_of_tau
+    if (n_app, seed, rms) not in _APP_ICS:
+        app_box, tau0, tau1, steps = _app_setup(n_app)
+        dtau = (tau1 - tau0) / steps
+        pos, u = zeldovich_particles(n_app, seed, spectrum_power_law_m2, app_box, rms, 0.02, 0.02,
+                                     eds_a_of_tau(tau0 - 0.5 * dtau, app_box))
+        _APP_ICS[(n_app, seed, rms)] = (torch.tensor(pos, device="cuda"),
+                                        torch.tensor(u, device="cuda", dtype=torch.float32))
+    return _APP_ICS[(n_app, seed, rms)]
+
+
+def reference_runs(n_app: int, seeds, log=print, rms: float = 0.2):
+    """Per realization: P(k) of the plain 2x-mesh run (the reference) and of the plain 1x run, with wall times."""
+    app_box, tau0, tau1, steps = _app_setup(n_app)
+    kmax = math.pi / (2.0 * app_box / n_app)  # half the 1x Nyquist frequency
+    out = {}
+    for seed in seeds:
+        pos_d, u_d = _app_particles(n_app, seed, rms)
+        p2, w2 = run_pm(2 * n_app, pos_d, u_d, tau0, tau1, steps, app_box, None, log=None)
+        k, pk2, _ = power_spectrum(p2, n_app, app_box)
+        del p2
+        p1, w1 = run_pm(n_app, pos_d, u_d, tau0, tau1, steps, app_box, None, log=None)
+        pk1 = power_spectrum(p1, n_app, app_box)[1]
+        del p1
+        torch.cuda.empty_cache()
+        sel = k <= kmax
+        out[seed] = {"k": k, "pk2": pk2, "sel": sel, "plain_2x_wall_s": w2, "plain_1x_wall_s": w1, "rms": rms,
+                     "plain_1x_ratio": pk1[sel] / pk2[sel] - 1.0}
+        out[seed]["plain_1x_maxdev"] = float(np.max(np.abs(out[seed]["plain_1x_ratio"])))
+        if log:
+            log(f"reference seed {seed}: 2x run {w2:.1f} s, plain 1x run {w1:.1f} s, plain 1x max deviation "
+                f"{out[seed]['plain_1x_maxdev']:.4f}")
+    return out
+
+
+def closure_runs(params, n_app: int, refs, log=print):
+    """Per realization: the 1x run with the closure, its P(k) ratio to the 2x run (k up to half the 1x Nyquist
+    frequency), its maximum deviation and its wall time."""
+    app_box, tau0, tau1, steps = _app_setup(n_app)
+    out = {}
+    for seed, ref in refs.items():
+        pos_d, u_d = _app_particles(n_app, seed, ref["rms"])
+        p, wall = run_pm(n_app, pos_d, u_d, tau0, tau1, steps, app_box, params, log=None)
+        pk = power_spectrum(p, n_app, app_box)[1]
+        del p
+        torch.cuda.empty_cache()
+        ratio = pk[ref["sel"]] / ref["pk2"][ref["sel"]] - 1.0
+        out[seed] = {"maxdev": float(np.max(np.abs(ratio))), "wall_s": wall, "ratio": [float(v) for v in ratio]}
+        if log:
+            log(f"  closure on seed {seed}: max deviation {out[seed]['maxdev']:.4f} ({wall:.1f} s)")
+    return out
 
 
 def experiment(n_app: int = 512, n_train_p: int = 128, train_box: float = 512.0, n_boxes: int = 64,
-               iters: int = 12000, lr: float = 1e-3, augment: bool = True, calibrate: str = "validation", log=print):
-    """Train on seeded boxes (1x and 2x meshes), apply to n_app^3 particles on an n_app^3 mesh and compare
-    P(k) and cost with the plain n_app^3 and 2 n_app^3 meshes at a = 0.5.
+               iters: int = 12000, lr: float = 1e-3, augment: bool = True, rounds: int = 2, round_boxes: int = 32,
+               round_iters: int = 6000, calibrate: str = "none", train_rms: float | None = None,
+               eval_seeds=None, probe=(), log=print):
+    """Train on seeded boxes (1x and 2x meshes), apply to n_app^3 particles on an n_app^3 mesh and compare P(k)
+    and cost with the plain n_app^3 and 2 n_app^3 meshes at a = 0.5, on the realizations EVAL_SEEDS.
 
-    calibrate: "validation" scales the output by the amplitude that best matches the 2x spectrum, averaged
-    over other realizations of the application (same box, mesh and recipe, seeds VALIDATION_SEEDS; the
-    application's own seed is never used to choose it); "train" chooses it on 4 training boxes; "none" keeps the trained
-    output."""
-    from synth import spectrum_power_law_m2, zeldovich_particles
-    from synth.ics import eds_a_of_tau
+    Round 0 trains on snapshots of 2x-mesh runs.  Each further round (on-policy data) evolves round_boxes new
+    training boxes on the 1x mesh with the current closure, labels their snapshots with the 2x - 1x force
+    difference on the same particles, adds them to the training set and continues training for round_iters
+    iterations.  The closure's output is used as trained (calibrate "none"), or scaled by the amplitude whose
+    P(k) ratio matches best on 4 training boxes (calibrate "train"); no 2x run of the application
+    configuration is ever used to choose anything.
 
-    res = {}
+    train_rms: rms displacement of the training boxes at a = 0.02 in cells; None gives them the application's
+    physical spectrum amplitude (for P ~ k^-2 about half the application's displacement in cells).
+    probe: (n_app, rms) cases on which the final network is also evaluated (seeds 3, 7, 8, 9, 10; boxes of
+    4 n_app Mpc/h, i.e. the same 4 Mpc/h cell), to show how its error depends on box size and amplitude."""
+    from synth import spectrum_power_law_m2
+
+    if calibrate not in ("train", "none"):
+        raise ValueError("calibrate must be 'train' or 'none'")
+    seeds_eval = tuple(eval_seeds) if eval_seeds else EVAL_SEEDS
+    res = {"eval_seeds": list(seeds_eval), "iters": iters, "augment": augment, "calibrate": calibrate}
     # the training boxes share the application's physical spectrum amplitude: for P ~ k^-2 the variance of
     # the displacement scales as (1/k_f - 1/k_Nyquist), so the rms in cells is rescaled accordingly
     app_box = 2048.0 * n_app / 512
     cell = app_box / n_app
     var = lambda L, N: (L / (2 * math.pi)) * (1 - 2.0 / N)  # noqa: E731
     rms_train = 0.2 * cell * math.sqrt(var(train_box, n_train_p) / var(app_box, n_app)) / (train_box / n_train_p)
+    if train_rms is not None:
+        rms_train = train_rms
+    res["train_rms_cells"] = rms_train
+    a_snaps = list(np.linspace(0.1, 0.5, 8))
+    kw = dict(n_p=n_train_p ** 3, n1=n_train_p, box=train_box, a_snaps=a_snaps, steps=100,
+              spectrum=spectrum_power_law_m2, rms_cells=rms_train)
     t0 = time.time()
-    snaps, c1 = make_pairs(seeds=range(1000, 1000 + n_boxes), n_p=n_train_p ** 3, n1=n_train_p, box=train_box,
-                           a_snaps=list(np.linspace(0.1, 0.5, 8)), steps=100, spectrum=spectrum_power_law_m2,
-                           rms_cells=rms_train, log=log if n_boxes <= 8 else None)
-    res["pairs_s"] = time.time() - t0
-    log(f"{len(snaps)} training snapshots in {res['pairs_s']:.1f} s (rms displacement {rms_train:.3f} cells)")
+    refs = reference_runs(n_app, seeds_eval, log=log)
+    res["reference_s"] = time.time() - t0
+    res["k"] = [float(v) for v in refs[seeds_eval[0]]["k"][refs[seeds_eval[0]]["sel"]]]
+    res["kmax_half_nyquist"] = math.pi / (2.0 * cell)
+    res["ref"] = {str(sd): {"plain_1x_maxdev": r["plain_1x_maxdev"], "plain_1x_wall_s": r["plain_1x_wall_s"],
+                            "plain_2x_wall_s": r["plain_2x_wall_s"],
+                            "plain_1x_ratio": [float(v) for v in r["plain_1x_ratio"]]} for sd, r in refs.items()}
+    t0 = time.time()
+    snaps, c1 = make_pairs(seeds=range(1000, 1000 + n_boxes), log=None, **kw)
     hold = snaps[-8:]
-    t0 = time.time()
-    params, hist = train(c1, snaps[:-8], init_params(0), iters=iters, lr=lr, log=log, log_every=1000,
-                         augment=augment, lr_final=0.05)
-    res["train_s"] = time.time() - t0
-    res["heldout_plain"], res["heldout_closure"] = evaluate(c1, hold, params)
-    log(f"trained in {res['train_s']:.1f} s; held-out force error: plain {res['heldout_plain']:.4e}, "
-        f"closure {res['heldout_closure']:.4e}")
-    del c1, snaps
-    torch.cuda.empty_cache()
-    if calibrate not in ("validation", "train", "none"):
-        raise ValueError("calibrate must be 'validation', 'train' or 'none'")
-    if calibrate != "none":
+    train_set = snaps[:-8]
+    res["rounds"] = []
+    params = init_params(0)
+    cost = time.time() - t0
+    for rnd in range(rounds + 1):
         t0 = time.time()
-        if calibrate == "train":
-            s, table = calibrate_amplitude(params, n_train_p, train_box, rms_train, seeds=range(1000, 1000 + 4),
-                                           scales=CAL_SCALES, log=log)
-        else:
-            s, table = calibrate_amplitude(params, n_app, app_box, 0.2, seeds=VALIDATION_SEEDS, scales=CAL_SCALES,
-                                           log=log)
-        params = scaled_output(params, s)
-        res["amplitude"], res["calibration"], res["calibration_s"] = s, table, time.time() - t0
-        res["calibration_on"] = calibrate
-        log(f"output amplitude {s:.2f} chosen on the {calibrate} runs ({res['calibration_s']:.1f} s)")
-    # application
-    tau0, tau1 = tau_of_a(app_box, 0.02), tau_of_a(app_box, 0.5)
-    steps = 100
-    dtau = (tau1 - tau0) / steps
-    pos, u = zeldovich_particles(n_app, 3, spectrum_power_law_m2, app_box, 0.2, 0.02, 0.02,
-                                 eds_a_of_tau(tau0 - 0.5 * dtau, app_box))
-    pos_d = torch.tensor(pos, device="cuda")
-    u_d = torch.tensor(u, device="cuda", dtype=torch.float32)
-    del pos, u
-    out = {}
-    for label, mesh, prm in (("plain_1x", n_app, None), ("closure_1x", n_app, params), ("plain_2x", 2 * n_app, None)):
-        p, wall = run_pm(mesh, pos_d, u_d, tau0, tau1, steps, app_box, prm, log=log)
-        k, pk, cnt = power_spectrum(p, n_app, app_box)
-        out[label] = (k, pk, wall)
-        log(f"{label}: {wall:.1f} s for {steps} steps")
-        del p
-        torch.cuda.empty_cache()
-    k = out["plain_2x"][0]
-    kmax = math.pi / (2.0 * cell)  # half the 1x Nyquist frequency
-    sel = k <= kmax
-    ref = out["plain_2x"][1]
-    for label in ("plain_1x", "closure_1x"):
-        r = out[label][1][sel] / ref[sel] - 1.0
-        res[f"{label}_maxdev"] = float(np.max(np.abs(r)))
-        res[f"{label}_ratio"] = [float(v) for v in r]
-    res["k"] = [float(v) for v in k[sel]]
-    res["kmax_half_nyquist"] = kmax
-    for label in out:
-        res[f"{label}_wall_s"] = out[label][2]
-    res["loss_first"], res["loss_last"] = float(np.mean(hist[:50])), float(np.mean(hist[-50:]))
-    res["iters"], res["augment"] = iters, augment
-    res["pass_2pct"] = res["closure_1x_maxdev"] <= 0.02
-    res["gain"] = res["closure_1x_maxdev"] < res["plain_1x_maxdev"]
-    res["cheaper_than_2x"] = out["closure_1x"][2] < out["plain_2x"][2]
+        if rnd > 0:
+            seeds = range(2000 + 1000 * rnd, 2000 + 1000 * rnd + round_boxes)
+            new = make_pairs(seeds=seeds, log=None, closure_params=params, c1=c1, **kw)[0]
+            hold_new, new = new[-8:], new[:-8]
+            hold = hold + hold_new
+            train_set = train_set + new
+        pairs_s = time.time() - t0 + (cost if rnd == 0 else 0.0)
+        t0 = time.time()
+        params, hist = train(c1, train_set, params, iters=iters if rnd == 0 else round_iters,
+                             lr=lr, log=None, augment=augment, lr_final=0.05)
+        train_s = time.time() - t0
+        plain, corr = evaluate(c1, hold, params)
+        r = {"round": rnd, "snapshots": len(train_set), "pairs_s": pairs_s, "train_s": train_s,
+             "heldout_plain": plain, "heldout_closure": corr, "loss_first": float(np.mean(hist[:50])),
+             "loss_last": float(np.mean(hist[-50:]))}
+        log(f"round {rnd}: {len(train_set)} snapshots, pairs {pairs_s:.1f} s, training {train_s:.1f} s; held-out "
+            f"force error plain {plain:.4e}, closure {corr:.4e}")
+        r["eval"] = {str(sd): v for sd, v in closure_runs(params, n_app, refs, log=log).items()}
+        r["maxdev"] = max(v["maxdev"] for v in r["eval"].values())
+        res["rounds"].append(r)
+    if calibrate == "train":
+        t0 = time.time()
+        sc, table = calibrate_amplitude(params, n_train_p, train_box, rms_train, seeds=range(1000, 1000 + 4),
+                                        scales=CAL_SCALES, log=log)
+        params = scaled_output(params, sc)
+        res["amplitude"], res["calibration"], res["calibration_s"] = sc, table, time.time() - t0
+        res["calibrated_eval"] = {str(sd): v for sd, v in closure_runs(params, n_app, refs, log=log).items()}
+        log(f"output amplitude {sc:.3f} chosen on training boxes ({res['calibration_s']:.1f} s)")
+    res["probe"] = []
+    for n_p, rms in probe:
+        t0 = time.time()
+        pr = reference_runs(n_p, (3, 7, 8, 9, 10), log=None, rms=rms)
+        ev = closure_runs(params, n_p, pr, log=None)
+        res["probe"].append({"n_app": n_p, "box": 4.0 * n_p, "rms_cells": rms,
+                             "plain_1x_maxdev": [pr[sd]["plain_1x_maxdev"] for sd in pr],
+                             "closure_maxdev": [ev[sd]["maxdev"] for sd in ev]})
+        log(f"probe {n_p}^3 (box {4 * n_p} Mpc/h, rms {rms:.4f} cells): closure max deviation "
+            + ", ".join(f"{ev[sd]['maxdev']:.4f}" for sd in ev) + f" ({time.time() - t0:.1f} s)")
+    final = res["rounds"][-1] if calibrate == "none" else {"eval": res["calibrated_eval"]}
+    ev = final["eval"]
+    res["final_maxdev"] = {sd: v["maxdev"] for sd, v in ev.items()}
+    res["pass_2pct_all"] = all(v["maxdev"] <= 0.02 for v in ev.values())
+    res["gain_all"] = all(ev[str(sd)]["maxdev"] < refs[sd]["plain_1x_maxdev"] for sd in seeds_eval)
+    res["closure_wall_s"] = float(np.mean([v["wall_s"] for v in ev.values()]))
+    res["plain_2x_wall_s"] = float(np.mean([refs[sd]["plain_2x_wall_s"] for sd in seeds_eval]))
+    res["plain_1x_wall_s"] = float(np.mean([refs[sd]["plain_1x_wall_s"] for sd in seeds_eval]))
+    res["training_cost_s"] = sum(r["pairs_s"] + r["train_s"] for r in res["rounds"]) + res.get("calibration_s", 0.0)
     return res, params
 
 
 def summary_md(res: dict, command: str) -> str:
     """Markdown summary of an experiment result (the committed profile of the closure experiment)."""
+    seeds = [str(s) for s in res["eval_seeds"]]
     lines = ["# Learned closure experiment: 512^3 particles, 512^3 mesh + closure vs plain 1024^3 mesh", "",
              "Command (repository root, on the MI355X machine):", "", f"    {command}", "",
-             f"Training: {res.get('iters')} Adam iterations (cosine decay), cube-symmetry augmentation "
-             f"{'on' if res.get('augment') else 'off'}; pairs {res['pairs_s']:.1f} s, training {res['train_s']:.1f} s.",
-             f"Held-out particle force error (units of rms|grad phi|^2): plain 1x {res['heldout_plain']:.3e}, "
-             f"with closure {res['heldout_closure']:.3e}."]
+             f"Three realizations of the application configuration (seeds {', '.join(seeds)}; seed {seeds[0]} is the "
+             "application run), none used for training or for choosing anything.  Round 0 trains on snapshots of "
+             "2x-mesh runs of 512 Mpc/h training boxes; each later round adds snapshots of training boxes evolved on "
+             "the 1x mesh with the current closure (on-policy data), labelled with the 2x - 1x force on the same "
+             f"particles, and trains on.  Cube-symmetry augmentation {'on' if res.get('augment') else 'off'}; "
+             f"training boxes at rms displacement {res.get('train_rms_cells', 0.0994):.4f} cells at a = 0.02 "
+             "(the application: 0.2 cells in a 2048 Mpc/h box).", ""]
     if "amplitude" in res:
-        where = ("two other realizations of the application (seeds 7 and 8; the application is seed 3)"
-                 if res.get("calibration_on", "train") == "validation" else "4 training boxes")
-        lines.append(f"Output amplitude chosen on {where}: s = {res['amplitude']:.3f} "
-                     f"({res['calibration_s']:.1f} s; per realization one 2x run and {len(res['calibration'])} 1x runs); "
-                     f"max deviation per s there: "
-                     + ", ".join(f"{float(k):.3f}: {v:.4f}" for k, v in res["calibration"].items()) + ".")
-    lines += ["", "| run | wall time, 100 steps | max abs(P/P_2x - 1), k <= k_Ny/2 |", "|---|---|---|",
-              f"| plain 512^3 mesh | {res['plain_1x_wall_s']:.1f} s | {res['plain_1x_maxdev']:.4f} |",
-              f"| 512^3 mesh + closure | {res['closure_1x_wall_s']:.1f} s | {res['closure_1x_maxdev']:.4f} |",
+        lines.append(f"Output amplitude chosen on 4 training boxes: s = {res['amplitude']:.3f} "
+                     f"({res['calibration_s']:.1f} s).")
+    else:
+        lines.append("Output used as trained (s = 1): no amplitude tuning.")
+    lines += ["", "| round | training snapshots | pairs + training | held-out force error, plain -> closure | "
+              + " | ".join(f"max dev. seed {s}" for s in seeds) + " |",
+              "|---|---|---|---|" + "---|" * len(seeds)]
+    for r in res["rounds"]:
+        lines.append(f"| {r['round']} | {r['snapshots']} | {r['pairs_s'] + r['train_s']:.1f} s | "
+                     f"{r['heldout_plain']:.3e} -> {r['heldout_closure']:.3e} | "
+                     + " | ".join(f"{r['eval'][s]['maxdev']:.4f}" for s in seeds) + " |")
+    if "calibrated_eval" in res:
+        lines.append(f"| s = {res['amplitude']:.3f} | | | | "
+                     + " | ".join(f"{res['calibrated_eval'][s]['maxdev']:.4f}" for s in seeds) + " |")
+    lines += ["", "| run | wall time, 100 steps (mean) | max abs(P/P_2x - 1), k <= k_Ny/2, per realization |",
+              "|---|---|---|",
+              f"| plain 512^3 mesh | {res['plain_1x_wall_s']:.1f} s | "
+              + ", ".join(f"{res['ref'][s]['plain_1x_maxdev']:.4f}" for s in seeds) + " |",
+              f"| 512^3 mesh + closure | {res['closure_wall_s']:.1f} s | "
+              + ", ".join(f"{res['final_maxdev'][s]:.4f}" for s in seeds) + " |",
               f"| plain 1024^3 mesh | {res['plain_2x_wall_s']:.1f} s | (reference) |", "",
-              f"2% target: {'met' if res['pass_2pct'] else 'not met'}; gain over the plain mesh: "
-              f"{'yes' if res['gain'] else 'no'}; cheaper than the 2x mesh: "
-              f"{'yes' if res['cheaper_than_2x'] else 'no'} "
-              f"({res['closure_1x_wall_s'] / res['plain_2x_wall_s']:.2f}x of its time).", "",
-              "P(k) ratio minus one (every 6th bin):", "", "| k [h/Mpc] | plain 1x | 1x + closure |", "|---|---|---|"]
+              f"2% target on every realization: {'met' if res['pass_2pct_all'] else 'not met'}; gain over the plain "
+              f"mesh on every realization: {'yes' if res['gain_all'] else 'no'}.  Closure run "
+              f"{res['closure_wall_s'] / res['plain_2x_wall_s']:.2f}x the 2x run's time; one-off training cost "
+              f"{res['training_cost_s']:.1f} s (pairs, training{', calibration' if 'amplitude' in res else ''}).", "",
+              ]
+    if res.get("probe"):
+        lines += ["The final network on other boxes with the same 4 Mpc/h cell (seeds 3, 7, 8, 9, 10; s = 1):", "",
+                  "| particles = mesh | box | rms displacement at a = 0.02 | plain 1x max dev. | closure max dev. |",
+                  "|---|---|---|---|---|"]
+        for pr in res["probe"]:
+            lines.append(f"| {pr['n_app']}^3 | {pr['box']:.0f} Mpc/h | {pr['rms_cells']:.4f} cells | "
+                         + ", ".join(f"{v:.3f}" for v in pr["plain_1x_maxdev"]) + " | "
+                         + ", ".join(f"{v:.4f}" for v in pr["closure_maxdev"]) + " |")
+        lines.append("")
+    lines += [f"P(k) ratio minus one, seed {seeds[0]} (every 6th bin):", "",
+              "| k [h/Mpc] | plain 1x | 1x + closure |", "|---|---|---|"]
+    final = res["rounds"][-1]["eval"][seeds[0]] if "calibrated_eval" not in res else res["calibrated_eval"][seeds[0]]
     for i in range(0, len(res["k"]), 6):
-        lines.append(f"| {res['k'][i]:.4f} | {res['plain_1x_ratio'][i]:+.4f} | {res['closure_1x_ratio'][i]:+.4f} |")
+        lines.append(f"| {res['k'][i]:.4f} | {res['ref'][seeds[0]]['plain_1x_ratio'][i]:+.4f} | "
+                     f"{final['ratio'][i]:+.4f} |")
     return "\n".join(lines) + "\n"
 
 
@@ -353,10 +476,18 @@ if __name__ == "__main__":
     ap.add_argument("--n-app", type=int, default=512)
     ap.add_argument("--boxes", type=int, default=64)
     ap.add_argument("--iters", type=int, default=12000)
+    ap.add_argument("--rounds", type=int, default=2, help="on-policy rounds after the first training")
+    ap.add_argument("--round-boxes", type=int, default=32)
+    ap.add_argument("--round-iters", type=int, default=6000)
     ap.add_argument("--no-augment", action="store_true")
-    ap.add_argument("--calibrate", choices=("validation", "train", "none"), default="validation",
-                    help="choose the output amplitude on another realization of the application (default), on "
-                         "training boxes, or keep the trained output")
+    ap.add_argument("--train-rms", type=float, default=None,
+                    help="rms displacement of the training boxes at a = 0.02 in cells (default: the application's "
+                         "physical amplitude)")
+    ap.add_argument("--eval-seeds", default=None, help="comma-separated realizations to evaluate on")
+    ap.add_argument("--probe", default="128:0.0994,128:0.2,256:0.1411,256:0.2",
+                    help="n_app:rms cases the final network is also evaluated on ('' for none)")
+    ap.add_argument("--calibrate", choices=("train", "none"), default="none",
+                    help="keep the trained output (default) or scale it by the amplitude chosen on training boxes")
     ap.add_argument("--out", default="gpurun_out/closure_experiment.json")
     ap.add_argument("--summarize", metavar="RESULT_JSON", help="print the markdown summary of a stored result")
     ap.add_argument("--command", default="python -u -m paper_2607_17929_amd.closure --out gpurun_out/closure_experiment.json")
@@ -366,9 +497,13 @@ if __name__ == "__main__":
             print(summary_md(json.load(f), a.command), end="")
         raise SystemExit(0)
     res, params = experiment(n_app=a.n_app, n_boxes=a.boxes, iters=a.iters, augment=not a.no_augment,
-                             calibrate=a.calibrate, log=lambda s: print(s, flush=True))
+                             rounds=a.rounds, round_boxes=a.round_boxes, round_iters=a.round_iters,
+                             calibrate=a.calibrate, train_rms=a.train_rms,
+                             eval_seeds=[int(v) for v in a.eval_seeds.split(",")] if a.eval_seeds else None,
+                             probe=[(int(c.split(":")[0]), float(c.split(":")[1])) for c in a.probe.split(",") if c],
+                             log=lambda s: print(s, flush=True))
     os.makedirs(os.path.dirname(a.out) or ".", exist_ok=True)
     with open(a.out, "w") as f:
         json.dump(res, f, indent=1)
     np.save(os.path.splitext(a.out)[0] + "_params.npy", params.cpu().numpy())
-    print(json.dumps({k: v for k, v in res.items() if not isinstance(v, list)}), flush=True)
+    print(json.dumps({k: v for k, v in res.items() if not isinstance(v, (list, dict))}), flush=True)
