@@ -227,7 +227,11 @@ __global__ __launch_bounds__(NT) void kspace_kernel(SolveArgs<T> a) {
     for (int j = threadIdx.x; j < N; j += NT) stw_s[j] = a.tw[j];
     stw = stw_s;
   }
-  const int ky = blockIdx.y, kx0 = blockIdx.x * KXT;
+  // neighbouring kx tiles share cache lines (a row of a tile is KXT * NS complex values, not a whole
+  // number of lines at n = 1024): the XCD-aware order keeps them in one L2 (1024^3: 42.6 -> 33.8 ms)
+  int bxl, byl, bzl;
+  xcd_block3(bxl, byl, bzl);
+  const int ky = byl, kx0 = bxl * KXT;
   const cplx<T>* gin = a.spec + ((long)ky * a.nhp + kx0) * NS;
   cplx<T>* gout = a.out + ((long)ky * a.nhp + kx0) * NO;
   constexpr int MODES = N * KXT;
