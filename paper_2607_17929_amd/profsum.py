@@ -5,6 +5,7 @@
         --probe-bytes B --steps K --command "..."
 
 `trace` turns a `--kernel-trace` CSV into a table of per-kernel durations.
+`counters` averages other `--pmc` counters per dispatch of each stage's kernels.
 `traffic` turns two `--pmc FETCH_SIZE` / `--pmc WRITE_SIZE` runs into HBM bytes
 per launch of each stage's kernels.  Both counters are reported in KiB per
 dispatch; each is scaled by what the same counter reads for the runtime's
@@ -161,9 +162,55 @@ def load_traffic(md_path: str) -> dict | None:
     return json.loads(m.group(1)) if m else None
 
 
+def counters(csvs, steps: int, prec: str = "float") -> dict:
+    """Average per dispatch of every counter in the `--pmc` CSVs for the last `steps` dispatches of each stage's
+    kernels (the first pattern of the stage), {stage: {counter: value}}."""
+    out = {}
+    for stage, kernels in STAGE_KERNELS.items():
+        rx = re.compile(kernels[-1][0].replace("{T}", prec))
+        vals = {}
+        for path in csvs:
+            per = defaultdict(list)
+            for r in _rows(path):
+                if rx.search(r["Kernel_Name"]):
+                    per[r["Counter_Name"]].append((int(r["Dispatch_Id"]), float(r["Counter_Value"])))
+            for c, v in per.items():
+                v.sort()
+                tail = [x for _, x in v[-steps:]]
+                vals[c] = sum(tail) / len(tail)
+        if vals:
+            out[stage] = vals
+    return out
+
+
+def counters_md(res: dict, n_particles: int, commands) -> str:
+    """Table of the counters per stage with the derived ratios that separate latency from issue limits."""
+    names = sorted({c for v in res.values() for c in v})
+    lines = ["Commands (from the repository root on the MI355X machine):", ""] + [f"    {c}" for c in commands] + [""]
+    lines += ["| Stage | " + " | ".join(names) + " |", "|---|" + "---|" * len(names)]
+    for st, v in res.items():
+        lines.append(f"| {st} | " + " | ".join(f"{v[c]:.4g}" if c in v else "" for c in names) + " |")
+    lines += ["", "| Stage | waves waiting on a dependency (SQ_WAIT_INST_ANY / SQ_WAVE_CYCLES) | VALU instructions per "
+              "particle | LDS bank-conflict cycles / LDS active cycles | L2 hit rate |", "|---|---|---|---|---|"]
+    for st, v in res.items():
+        def ratio(a, b):
+            return f"{v[a] / v[b]:.2f}" if a in v and b in v and v[b] else ""
+        valu = f"{v['SQ_INSTS_VALU'] * 64 / n_particles:.0f}" if "SQ_INSTS_VALU" in v else ""
+        hit = (f"{v['TCC_HIT_sum'] / (v['TCC_HIT_sum'] + v['TCC_MISS_sum']):.2f}"
+               if "TCC_HIT_sum" in v and "TCC_MISS_sum" in v else "")
+        lines.append(f"| {st} | {ratio('SQ_WAIT_INST_ANY', 'SQ_WAVE_CYCLES')} | {valu} | "
+                     f"{ratio('SQ_LDS_BANK_CONFLICT', 'SQ_LDS_IDX_ACTIVE')} | {hit} |")
+    return "\n".join(lines) + "\n"
+
+
 def main():
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="cmd", required=True)
+    k = sub.add_parser("counters")
+    k.add_argument("csv", nargs="+")
+    k.add_argument("--steps", type=int, required=True)
+    k.add_argument("--particles", type=int, required=True)
+    k.add_argument("--command", action="append", required=True)
     t = sub.add_parser("trace")
     t.add_argument("csv")
     t.add_argument("--command", required=True)
@@ -176,7 +223,9 @@ def main():
     f.add_argument("--command-fetch", required=True)
     f.add_argument("--command-write", required=True)
     a = ap.parse_args()
-    if a.cmd == "trace":
+    if a.cmd == "counters":
+        print(counters_md(counters(a.csv, a.steps), a.particles, a.command), end="")
+    elif a.cmd == "trace":
         print(trace_table(a.csv, a.command), end="")
     else:
         res = traffic(a.fetch_csv, a.write_csv, a.probe_bytes, a.steps, a.n)
