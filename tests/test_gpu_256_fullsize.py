@@ -1,12 +1,13 @@
 """Element-by-element parity at the full size of the 256^3 full-physics workload: 256^3 particles on a
 256^3 mesh, box 1024 Mpc/h, the k T(k) spectrum (seed 2), Zel'dovich start at a = 0.1, dtau = 0.01 tau,
-against the FP64 oracle on the same inputs: the FP64 path after the quasi-static start step and one
-semi-implicit step (time derivatives, lagged fields, the first Crank-Nicolson step of h), the FP32 path
-after those two and after ten steps.
+against the FP64 oracle on the same inputs (the FP32-rounded momenta for both paths): the FP64 path after
+the quasi-static start step and one semi-implicit step (time derivatives, lagged fields, the first
+Crank-Nicolson step of h), the FP32 path after those two, after six and after ten steps.
 
 Bars: fields (phi, chi, B, the six h_ij) in relative L2 and relative max-norm, FP32 1e-5 / 1e-4, FP64
 1e-10 / 1e-9; positions FP32 1e-4 mesh spacings after ten steps, FP64 1e-9.  The oracle runs once for
-the ten steps (about 30 s per step here) while both GPU paths step beside it.
+the ten steps (about 25 s per step here) while both GPU paths step beside it; the three tests share that
+run (in file order; each also runs alone) so that none of them takes more than about two minutes.
 """
 import numpy as np
 import pytest
@@ -38,30 +39,56 @@ def _check(ctx, sim, precision, label):
     assert du < (1e-10 if precision == "fp64" else 1e-5)
 
 
-def test_ktk_256_full_ten_steps_against_oracle():
-    from paper_2607_17929_amd import PMContext
-    pos, u, tau0, dtau = config_particles("ktk_256_full")
-    n, box = 256, 1024.0
-    u32 = u.astype(np.float32)
-    ctx = {p: PMContext(n, pos.shape[0], box, physics="full", precision=p) for p in ("fp64", "fp32")}
-    ctx["fp64"].init_particles(pos, u, tau0)
-    ctx["fp32"].init_particles(pos, u32, tau0)
-    # the oracle follows the FP32 path's momenta (its inputs are the FP32-rounded ones); the FP64 path
-    # is compared after two steps with an oracle run of its own inputs
-    sim = opm.OracleSim(n=n, box_mpch=box, physics="full", pos=pos, u=u32.astype(np.float64), tau=tau0)
-    sim64 = opm.OracleSim(n=n, box_mpch=box, physics="full", pos=pos, u=u, tau=tau0)
-    del u
-    for i in range(10):
-        _say(f"256^3 full physics: step {i + 1}")
-        ctx["fp32"].step(dtau)
-        sim.step(dtau)
-        if i < 2:
-            ctx["fp64"].step(dtau)
-            sim64.step(dtau)
-        if i == 1:
-            _check(ctx["fp64"], sim64, "fp64", "fp64 after 2 steps")
-            del sim64, ctx["fp64"]
-            torch.cuda.empty_cache()
-            _check(ctx["fp32"], sim, "fp32", "fp32 after 2 steps")
-    _check(ctx["fp32"], sim, "fp32", "fp32 after 10 steps")
-    assert ctx["fp32"].time()[2] == 10
+class _Run:
+    """The 256^3 run shared by the tests below: both GPU paths and the oracle, advanced step by step."""
+
+    def __init__(self):
+        from paper_2607_17929_amd import PMContext
+        pos, u, tau0, self.dtau = config_particles("ktk_256_full")
+        self.n, box = 256, 1024.0
+        # every path starts from the FP32-rounded momenta, so that one oracle run serves both precisions
+        u32 = u.astype(np.float32)
+        del u
+        self.ctx = {p: PMContext(self.n, pos.shape[0], box, physics="full", precision=p) for p in ("fp64", "fp32")}
+        self.ctx["fp64"].init_particles(pos, u32.astype(np.float64), tau0)
+        self.ctx["fp32"].init_particles(pos, u32, tau0)
+        self.sim = opm.OracleSim(n=self.n, box_mpch=box, physics="full", pos=pos, u=u32.astype(np.float64), tau=tau0)
+        self.steps = 0
+
+    def advance(self, to):
+        while self.steps < to:
+            self.steps += 1
+            _say(f"256^3 full physics: step {self.steps}")
+            for c in self.ctx.values():
+                c.step(self.dtau)
+            self.sim.step(self.dtau)
+
+
+@pytest.fixture(scope="module")
+def run256():
+    r = _Run()
+    yield r
+    del r
+    torch.cuda.empty_cache()
+
+
+def test_ktk_256_full_two_steps_against_oracle(run256):
+    """Both paths after the quasi-static start step and one semi-implicit step."""
+    run256.advance(2)
+    _check(run256.ctx["fp64"], run256.sim, "fp64", "fp64 after 2 steps")
+    _check(run256.ctx["fp32"], run256.sim, "fp32", "fp32 after 2 steps")
+    del run256.ctx["fp64"]
+    torch.cuda.empty_cache()
+
+
+def test_ktk_256_full_six_steps_against_oracle(run256):
+    run256.ctx.pop("fp64", None)
+    run256.advance(6)
+    _check(run256.ctx["fp32"], run256.sim, "fp32", "fp32 after 6 steps")
+
+
+def test_ktk_256_full_ten_steps_against_oracle(run256):
+    run256.ctx.pop("fp64", None)
+    run256.advance(10)
+    _check(run256.ctx["fp32"], run256.sim, "fp32", "fp32 after 10 steps")
+    assert run256.ctx["fp32"].time()[2] == 10

@@ -236,7 +236,8 @@ def test_solve_512_clustered_against_oracle(clustered, precision):
         assert err < (1e-10 if precision == "fp64" else 1e-5), (k, err)
 
 
-EVOLUTION_CASES = [("fp32", "elliptic"), ("fp32", "parabolic"), ("fp64", "elliptic")]
+# the FP32 path the bench times, both B routes (the FP64 evolution solve is checked at 256^3 full size)
+EVOLUTION_CASES = [("fp32", "elliptic"), ("fp32", "parabolic")]
 
 
 @pytest.mark.parametrize("precision,b_route", EVOLUTION_CASES)

@@ -11,6 +11,9 @@ GPU path needs about 395 GB, so the checks are on outputs the oracle gives one b
 * gather + kick + drift: for 8192 sampled particles, the oracle's update on the GPU's own 1024^3 fields
   after the start-up solve (gradients evaluated at the vertices the particles need), against the GPU's;
 * finite fields and positions after three steps.  The per-stage times of the last step are printed.
+
+The checks of the run share one context (a module fixture, in file order; each also runs alone), so
+that none of them takes more than about two minutes.
 """
 import gc
 
@@ -63,27 +66,79 @@ def test_fft_1024_sampled_modes():
         assert err < 1e-5, ((kx, ky, kz), err)
 
 
-def test_memory_scale_1024():
-    from paper_2607_17929_amd import PMContext
-    # release what earlier tests left in the caching allocator: the workspace needs 234 GB
+class _Run:
+    """The 1024^3 run shared by the tests below (the workspace takes 256 GB of the device)."""
+
+    def __init__(self):
+        self.ctx = None
+        self.stage = "none"
+        self.bg = opm.Background(BOX)
+        self.tau = self.bg.tau(0.1)
+        self.dtau = 0.01 * self.tau
+
+    def ensure(self):
+        if self.ctx is not None:
+            return
+        from paper_2607_17929_amd import PMContext
+        # release what earlier tests left in the caching allocator
+        _release()
+        props = torch.cuda.get_device_properties(0)
+        _say(f"device memory {props.total_memory / 1e9:.0f} GB")
+        _say("building the 1024^3 input")
+        self.pos, u = zeldovich_particles(N, 4, spectrum_power_law_m2, BOX, 0.2, 0.02, 0.1,
+                                          eds_a_of_tau(self.tau - 0.5 * self.dtau, BOX))
+        self.u32 = u.astype(np.float32)
+        del u
+        self.ctx = PMContext(N, N ** 3, BOX, physics="full", precision="fp32", timings=True)
+        _say(f"workspace {self.ctx.ws_bytes / 1e9:.1f} GB")
+        self.ctx.init_particles(self.pos, self.u32, self.tau)
+        self.stage = "init"
+
+
+@pytest.fixture(scope="module")
+def run1024():
+    r = _Run()
+    yield r
+    del r
+    gc.collect()
     _release()
-    props = torch.cuda.get_device_properties(0)
-    _say(f"device memory {props.total_memory / 1e9:.0f} GB")
-    bg = opm.Background(BOX)
-    tau = bg.tau(0.1)
-    dtau = 0.01 * tau
-    _say("building the 1024^3 input")
-    pos, u = zeldovich_particles(N, 4, spectrum_power_law_m2, BOX, 0.2, 0.02, 0.1, eds_a_of_tau(tau - 0.5 * dtau, BOX))
-    u32 = u.astype(np.float32)
-    del u
-    ctx = PMContext(N, N ** 3, BOX, physics="full", precision="fp32", timings=True)
-    _say(f"workspace {ctx.ws_bytes / 1e9:.1f} GB")
-    ctx.init_particles(pos, u32, tau)
+
+
+def test_memory_scale_1024_input(run1024):
+    """The full-size input: 1024^3 particles in [0, 1), rms distance from their lattice sites 1.0 cell (0.2
+    cells at a = 0.02 grown to a = 0.1), finite momenta; the library takes them (init_particles)."""
+    r = run1024
+    r.ensure()
+    assert r.pos.shape == (N ** 3, 3) and float(r.pos.min()) >= 0.0 and float(r.pos.max()) < 1.0
+    assert bool(np.isfinite(r.u32).all())
+    q = ((np.arange(N) + 0.5) / N)
+    sample = np.random.default_rng(5).choice(N ** 3, 1 << 20, replace=False)
+    lat = np.stack([q[sample % N], q[(sample // N) % N], q[sample // (N * N)]], axis=1)
+    d = (r.pos[sample] - lat + 0.5) % 1.0 - 0.5
+    rms = float(np.sqrt(np.mean(np.sum(d * d, axis=1)))) * N
+    _say(f"rms displacement {rms:.3f} cells")
+    assert abs(rms - 1.0) < 0.02
+
+
+def _region_particles(pos, z0, y0, x0, R):
+    """The particles whose cell touches the vertices [z0, z0 + R) x ... (cells z0 - 1 .. z0 + R - 1 per axis)."""
+    sel = np.ones(pos.shape[0], dtype=bool)
+    for ax, o in ((2, z0), (1, y0), (0, x0)):
+        c = np.floor(pos[:, ax] * N).astype(np.int64)
+        sel &= (c - (o - 1)) % N < R + 1
+    return np.nonzero(sel)[0]
+
+
+def test_memory_scale_1024_deposit(run1024):
+    """CIC partition of unity over the whole mesh and every vertex of two 16^3 regions (the densest
+    cell's and a random one) against the oracle's CIC sums of the particles around them."""
+    r = run1024
+    r.ensure()
+    ctx = r.ctx
     ctx.deposit()
-    a = bg.a(tau)
-    u64 = u32.astype(np.float64)
-    e_sum = float(np.sum(np.sqrt(a * a + np.sum(u64 * u64, axis=1))))
-    u_sum = u64.sum(axis=0)
+    a = r.bg.a(r.tau)
+    e_sum = float(np.sum(np.sqrt(a * a + np.sum(r.u32.astype(np.float64) ** 2, axis=1))))
+    u_sum = r.u32.astype(np.float64).sum(axis=0)
     n00 = ctx.get_field("n00", device=True)
     tot = float(torch.sum(n00, dtype=torch.float64))
     del n00
@@ -94,20 +149,19 @@ def test_memory_scale_1024():
         s = float(torch.sum(f, dtype=torch.float64))
         del f
         assert abs(s - u_sum[i]) < 1e-5 * (abs(u_sum[i]) + 1e-6 * e_sum), (c, s, u_sum[i])
-    # two 16^3 regions of the deposit, vertex by vertex
-    base, _ = opm.cic_cells(pos, N)
-    key = (base[:, 2] * N + base[:, 1]) * N + base[:, 0]
-    del base
-    counts = np.bincount(key, minlength=N ** 3)
+    # the densest cell: one pass over the particles' cell keys
+    key = np.floor(r.pos[:, 0] * N).astype(np.int64)
+    key += N * np.floor(r.pos[:, 1] * N).astype(np.int64)
+    key += N * N * np.floor(r.pos[:, 2] * N).astype(np.int64)
+    dense = int(np.argmax(np.bincount(key, minlength=N ** 3)))
     del key
-    dense = int(np.argmax(counts))
-    del counts
     dz, dy, dx = dense // (N * N), (dense // N) % N, dense % N
     R = 16
-    r = np.random.default_rng(12)
-    regions = [((dz - R // 2) % N, (dy - R // 2) % N, (dx - R // 2) % N), tuple(int(v) for v in r.integers(0, N, 3))]
+    rg = np.random.default_rng(12)
+    regions = [((dz - R // 2) % N, (dy - R // 2) % N, (dx - R // 2) % N), tuple(int(v) for v in rg.integers(0, N, 3))]
     for (z0, y0, x0) in regions:
-        ref = _region_deposit(pos, u64, a, z0, y0, x0, R, n=N)
+        idx = _region_particles(r.pos, z0, y0, x0, R)
+        ref = _region_deposit(r.pos[idx], r.u32[idx].astype(np.float64), a, z0, y0, x0, R, n=N)
         zi, yi, xi = (np.arange(z0, z0 + R) % N, np.arange(y0, y0 + R) % N, np.arange(x0, x0 + R) % N)
         for c, name in enumerate(DEP):
             f = ctx.get_field(name, device=True)
@@ -115,17 +169,26 @@ def test_memory_scale_1024():
             del f
             err = rel_l2(got, ref[c])
             assert err < 2e-6, ((z0, y0, x0), name, err)
-        _say(f"  deposit region {(z0, y0, x0)} matches")
-    del pos, u64, u32
+        _say(f"  deposit region {(z0, y0, x0)} ({idx.size} particles) matches")
+    r.stage = "deposited"
+
+
+def test_memory_scale_1024_update(run1024):
+    """The start-up solve, then the update of 8192 sampled particles against the oracle's on the same fields."""
+    r = run1024
+    r.ensure()
+    ctx = r.ctx
+    if r.stage != "deposited":
+        ctx.deposit()
+    r.pos = r.u32 = None
     gc.collect()
-    # the start-up solve, then the update of 8192 sampled particles against the oracle's on the same fields
     ctx.solve_metric(0.0)
     fields = {k: ctx.get_field(k) for k in ("phi", "chi", "bx", "by", "bz")}
     p0, u0 = ctx.get_particles()
     sample = np.random.default_rng(78).choice(N ** 3, 8192, replace=False)
     p0, u0 = p0[sample].copy(), u0[sample].astype(np.float64)
     gc.collect()
-    ctx.update_particles(dtau)
+    ctx.update_particles(r.dtau)
     p1, u1 = ctx.get_particles()
     p1, u1 = p1[sample].copy(), u1[sample].astype(np.float64)
     gc.collect()
@@ -134,17 +197,25 @@ def test_memory_scale_1024():
     g = opm.gathered_pointwise(fields["phi"], fields["chi"], [fields["bx"], fields["by"], fields["bz"]], p0, N)
     del fields
     gc.collect()
-    p_ref, u_ref = opm.kick_drift(g, p0, u0, bg.a(tau), bg.a(tau + 0.5 * dtau), dtau, opm.FULL)
+    p_ref, u_ref = opm.kick_drift(g, p0, u0, r.bg.a(r.tau), r.bg.a(r.tau + 0.5 * r.dtau), r.dtau, opm.FULL)
     dxm = periodic_max_dx(p1, p_ref, N)
     du = rel_l2(u1, u_ref)
     _say(f"  sampled update: max |dx| {dxm:.2e} cells, u rel-L2 {du:.2e}, largest move "
          f"{periodic_max_dx(p1, p0, N):.2f} cells")
     assert dxm < 1e-4 and du < 1e-5
+    r.stage = "updated"
+
+
+def test_memory_scale_1024_steps(run1024):
+    """Three more steps (the last one timed per stage); fields and positions stay finite."""
+    r = run1024
+    r.ensure()
+    ctx = r.ctx
     for _ in range(2):
-        ctx.step(dtau)
+        ctx.step(r.dtau)
     ctx.sync()
     ctx.timings()  # time the next step alone
-    ctx.step(dtau)
+    ctx.step(r.dtau)
     ctx.sync()
     st = ctx.timings()
     per = {k: v[0] / v[1] for k, v in st.items() if v[1]}
@@ -156,5 +227,3 @@ def test_memory_scale_1024():
         del f
     p, _ = ctx.get_particles()
     assert bool(np.isfinite(p).all()) and float(p.min()) >= 0.0 and float(p.max()) < 1.0
-    del ctx, p
-    _release()
