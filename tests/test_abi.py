@@ -66,6 +66,21 @@ def _header_constants():
     return {k: int(v) for k, v in re.findall(r"\b(PM_[A-Z0-9_]+)\s*=\s*(-?\d+)u?\b", src)}
 
 
+def test_copy_probe_rejects_bad_arguments():
+    """pm_copy_probe validates its arguments on the host before any device call: sizes that are zero or not a
+    multiple of 16, pointers not aligned to 16 bytes, null pointers and reps < 1 give PM_EINVAL."""
+    lib = L.load()
+    ms = C.c_double()
+    a, b = C.c_void_p(1 << 20), C.c_void_p(2 << 20)  # never dereferenced: every call below is rejected first
+    assert lib.pm_copy_probe(a, b, 24, 1, None, C.byref(ms)) == L.PM_EINVAL
+    assert lib.pm_copy_probe(a, b, 0, 1, None, C.byref(ms)) == L.PM_EINVAL
+    assert lib.pm_copy_probe(C.c_void_p((1 << 20) + 8), b, 64, 1, None, C.byref(ms)) == L.PM_EINVAL
+    assert lib.pm_copy_probe(a, C.c_void_p((2 << 20) + 4), 64, 1, None, C.byref(ms)) == L.PM_EINVAL
+    assert lib.pm_copy_probe(None, b, 64, 1, None, C.byref(ms)) == L.PM_EINVAL
+    assert lib.pm_copy_probe(a, b, 64, 0, None, C.byref(ms)) == L.PM_EINVAL
+    assert lib.pm_copy_probe(a, b, 64, 1, None, None) == L.PM_EINVAL
+
+
 def test_header_constants_match_the_binding():
     h = _header_constants()
     for name in ("PM_OK", "PM_EINVAL", "PM_EWORKSPACE", "PM_EHIP", "PM_ENAN", "PM_ESTATE", "PM_ERANGE",

@@ -63,3 +63,20 @@ def test_energy_sum_and_two_species_momentum(precision):
     mom = ua.sum(axis=0) + w * ub.sum(axis=0)
     assert np.allclose(d["momentum"], mom, rtol=0, atol=1e-12 * (np.abs(ua).sum() + w * np.abs(ub).sum()))
     assert d["phi_mean"] != 0.0
+
+
+def test_copy_probe_copies_every_byte():
+    """The bandwidth probe is a copy: random bytes of a size that is no power of two (16 x 1000003) arrive
+    unchanged, and the reported time is positive."""
+    import ctypes as C
+
+    from paper_2607_17929_amd import _lib as L
+    lib = L.load()
+    nb = 16 * 1000003
+    src = torch.randint(0, 256, (nb,), dtype=torch.uint8, generator=torch.Generator().manual_seed(5)).cuda()
+    dst = torch.zeros_like(src)
+    ms = C.c_double()
+    st = torch.cuda.current_stream()
+    assert lib.pm_copy_probe(C.c_void_p(src.data_ptr()), C.c_void_p(dst.data_ptr()), nb, 3, C.c_void_p(st.cuda_stream),
+                             C.byref(ms)) == L.PM_OK
+    assert torch.equal(src, dst) and ms.value > 0
