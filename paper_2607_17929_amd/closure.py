@@ -308,15 +308,15 @@ def closure_runs(params, n_app: int, refs, log=print):
 
 
 def experiment(n_app: int = 512, n_train_p: int = 128, train_box: float = 512.0, n_boxes: int = 64,
-               iters: int = 12000, lr: float = 1e-3, augment: bool = True, rounds: int = 2, round_boxes: int = 32,
-               round_iters: int = 6000, calibrate: str = "none", train_rms: float | None = None,
+               iters: int = 12000, lr: float = 1e-3, augment: bool = True, phases: int = 2, phase_boxes: int = 32,
+               phase_iters: int = 6000, calibrate: str = "none", train_rms: float | None = None,
                eval_seeds=None, probe=(), log=print):
     """Train on seeded boxes (1x and 2x meshes), apply to n_app^3 particles on an n_app^3 mesh and compare P(k)
     and cost with the plain n_app^3 and 2 n_app^3 meshes at a = 0.5, on the realizations EVAL_SEEDS.
 
-    Round 0 trains on snapshots of 2x-mesh runs.  Each further round (on-policy data) evolves round_boxes new
+    Phase 0 trains on snapshots of 2x-mesh runs.  Each further phase (on-policy data) evolves phase_boxes new
     training boxes on the 1x mesh with the current closure, labels their snapshots with the 2x - 1x force
-    difference on the same particles, adds them to the training set and continues training for round_iters
+    difference on the same particles, adds them to the training set and continues training for phase_iters
     iterations.  The closure's output is used as trained (calibrate "none"), or scaled by the amplitude whose
     P(k) ratio matches best on 4 training boxes (calibrate "train"); no 2x run of the application
     configuration is ever used to choose anything.
@@ -355,31 +355,31 @@ def experiment(n_app: int = 512, n_train_p: int = 128, train_box: float = 512.0,
     snaps, c1 = make_pairs(seeds=range(1000, 1000 + n_boxes), log=None, **kw)
     hold = snaps[-8:]
     train_set = snaps[:-8]
-    res["rounds"] = []
+    res["phases"] = []
     params = init_params(0)
     cost = time.time() - t0
-    for rnd in range(rounds + 1):
+    for rnd in range(phases + 1):
         t0 = time.time()
         if rnd > 0:
-            seeds = range(2000 + 1000 * rnd, 2000 + 1000 * rnd + round_boxes)
+            seeds = range(2000 + 1000 * rnd, 2000 + 1000 * rnd + phase_boxes)
             new = make_pairs(seeds=seeds, log=None, closure_params=params, c1=c1, **kw)[0]
             hold_new, new = new[-8:], new[:-8]
             hold = hold + hold_new
             train_set = train_set + new
         pairs_s = time.time() - t0 + (cost if rnd == 0 else 0.0)
         t0 = time.time()
-        params, hist = train(c1, train_set, params, iters=iters if rnd == 0 else round_iters,
+        params, hist = train(c1, train_set, params, iters=iters if rnd == 0 else phase_iters,
                              lr=lr, log=None, augment=augment, lr_final=0.05)
         train_s = time.time() - t0
         plain, corr = evaluate(c1, hold, params)
-        r = {"round": rnd, "snapshots": len(train_set), "pairs_s": pairs_s, "train_s": train_s,
+        r = {"phase": rnd, "snapshots": len(train_set), "pairs_s": pairs_s, "train_s": train_s,
              "heldout_plain": plain, "heldout_closure": corr, "loss_first": float(np.mean(hist[:50])),
              "loss_last": float(np.mean(hist[-50:]))}
-        log(f"round {rnd}: {len(train_set)} snapshots, pairs {pairs_s:.1f} s, training {train_s:.1f} s; held-out "
+        log(f"phase {rnd}: {len(train_set)} snapshots, pairs {pairs_s:.1f} s, training {train_s:.1f} s; held-out "
             f"force error plain {plain:.4e}, closure {corr:.4e}")
         r["eval"] = {str(sd): v for sd, v in closure_runs(params, n_app, refs, log=log).items()}
         r["maxdev"] = max(v["maxdev"] for v in r["eval"].values())
-        res["rounds"].append(r)
+        res["phases"].append(r)
     if calibrate == "train":
         t0 = time.time()
         sc, table = calibrate_amplitude(params, n_train_p, train_box, rms_train, seeds=range(1000, 1000 + 4),
@@ -398,7 +398,7 @@ def experiment(n_app: int = 512, n_train_p: int = 128, train_box: float = 512.0,
                              "closure_maxdev": [ev[sd]["maxdev"] for sd in ev]})
         log(f"probe {n_p}^3 (box {4 * n_p} Mpc/h, rms {rms:.4f} cells): closure max deviation "
             + ", ".join(f"{ev[sd]['maxdev']:.4f}" for sd in ev) + f" ({time.time() - t0:.1f} s)")
-    final = res["rounds"][-1] if calibrate == "none" else {"eval": res["calibrated_eval"]}
+    final = res["phases"][-1] if calibrate == "none" else {"eval": res["calibrated_eval"]}
     ev = final["eval"]
     res["final_maxdev"] = {sd: v["maxdev"] for sd, v in ev.items()}
     res["pass_2pct_all"] = all(v["maxdev"] <= 0.02 for v in ev.values())
@@ -406,7 +406,7 @@ def experiment(n_app: int = 512, n_train_p: int = 128, train_box: float = 512.0,
     res["closure_wall_s"] = float(np.mean([v["wall_s"] for v in ev.values()]))
     res["plain_2x_wall_s"] = float(np.mean([refs[sd]["plain_2x_wall_s"] for sd in seeds_eval]))
     res["plain_1x_wall_s"] = float(np.mean([refs[sd]["plain_1x_wall_s"] for sd in seeds_eval]))
-    res["training_cost_s"] = sum(r["pairs_s"] + r["train_s"] for r in res["rounds"]) + res.get("calibration_s", 0.0)
+    res["training_cost_s"] = sum(r["pairs_s"] + r["train_s"] for r in res["phases"]) + res.get("calibration_s", 0.0)
     return res, params
 
 
@@ -416,8 +416,8 @@ def summary_md(res: dict, command: str) -> str:
     lines = ["# Learned closure experiment: 512^3 particles, 512^3 mesh + closure vs plain 1024^3 mesh", "",
              "Command (repository root, on the MI355X machine):", "", f"    {command}", "",
              f"Three realizations of the application configuration (seeds {', '.join(seeds)}; seed {seeds[0]} is the "
-             "application run), none used for training or for choosing anything.  Round 0 trains on snapshots of "
-             "2x-mesh runs of 512 Mpc/h training boxes; each later round adds snapshots of training boxes evolved on "
+             "application run), none used for training or for choosing anything.  Phase 0 trains on snapshots of "
+             "2x-mesh runs of 512 Mpc/h training boxes; each later phase adds snapshots of training boxes evolved on "
              "the 1x mesh with the current closure (on-policy data), labelled with the 2x - 1x force on the same "
              f"particles, and trains on.  Cube-symmetry augmentation {'on' if res.get('augment') else 'off'}; "
              f"training boxes at rms displacement {res.get('train_rms_cells', 0.0994):.4f} cells at a = 0.02 "
@@ -427,11 +427,11 @@ def summary_md(res: dict, command: str) -> str:
                      f"({res['calibration_s']:.1f} s).")
     else:
         lines.append("Output used as trained (s = 1): no amplitude tuning.")
-    lines += ["", "| round | training snapshots | pairs + training | held-out force error, plain -> closure | "
+    lines += ["", "| phase | training snapshots | pairs + training | held-out force error, plain -> closure | "
               + " | ".join(f"max dev. seed {s}" for s in seeds) + " |",
               "|---|---|---|---|" + "---|" * len(seeds)]
-    for r in res["rounds"]:
-        lines.append(f"| {r['round']} | {r['snapshots']} | {r['pairs_s'] + r['train_s']:.1f} s | "
+    for r in res["phases"]:
+        lines.append(f"| {r['phase']} | {r['snapshots']} | {r['pairs_s'] + r['train_s']:.1f} s | "
                      f"{r['heldout_plain']:.3e} -> {r['heldout_closure']:.3e} | "
                      + " | ".join(f"{r['eval'][s]['maxdev']:.4f}" for s in seeds) + " |")
     if "calibrated_eval" in res:
@@ -460,7 +460,7 @@ def summary_md(res: dict, command: str) -> str:
         lines.append("")
     lines += [f"P(k) ratio minus one, seed {seeds[0]} (every 6th bin):", "",
               "| k [h/Mpc] | plain 1x | 1x + closure |", "|---|---|---|"]
-    final = res["rounds"][-1]["eval"][seeds[0]] if "calibrated_eval" not in res else res["calibrated_eval"][seeds[0]]
+    final = res["phases"][-1]["eval"][seeds[0]] if "calibrated_eval" not in res else res["calibrated_eval"][seeds[0]]
     for i in range(0, len(res["k"]), 6):
         lines.append(f"| {res['k'][i]:.4f} | {res['ref'][seeds[0]]['plain_1x_ratio'][i]:+.4f} | "
                      f"{final['ratio'][i]:+.4f} |")
@@ -476,9 +476,9 @@ if __name__ == "__main__":
     ap.add_argument("--n-app", type=int, default=512)
     ap.add_argument("--boxes", type=int, default=64)
     ap.add_argument("--iters", type=int, default=12000)
-    ap.add_argument("--rounds", type=int, default=2, help="on-policy rounds after the first training")
-    ap.add_argument("--round-boxes", type=int, default=32)
-    ap.add_argument("--round-iters", type=int, default=6000)
+    ap.add_argument("--phases", type=int, default=2, help="on-policy phases after the first training")
+    ap.add_argument("--phase-boxes", type=int, default=32)
+    ap.add_argument("--phase-iters", type=int, default=6000)
     ap.add_argument("--no-augment", action="store_true")
     ap.add_argument("--train-rms", type=float, default=None,
                     help="rms displacement of the training boxes at a = 0.02 in cells (default: the application's "
@@ -488,16 +488,17 @@ if __name__ == "__main__":
                     help="n_app:rms cases the final network is also evaluated on ('' for none)")
     ap.add_argument("--calibrate", choices=("train", "none"), default="none",
                     help="keep the trained output (default) or scale it by the amplitude chosen on training boxes")
-    ap.add_argument("--out", default="gpurun_out/closure_experiment.json")
+    ap.add_argument("--out", default="closure_experiment.json")
     ap.add_argument("--summarize", metavar="RESULT_JSON", help="print the markdown summary of a stored result")
-    ap.add_argument("--command", default="python -u -m paper_2607_17929_amd.closure --out gpurun_out/closure_experiment.json")
+    ap.add_argument("--command", default="python -u -m paper_2607_17929_amd.closure",
+                    help="the command line recorded in the summary")
     a = ap.parse_args()
     if a.summarize:
         with open(a.summarize) as f:
             print(summary_md(json.load(f), a.command), end="")
         raise SystemExit(0)
     res, params = experiment(n_app=a.n_app, n_boxes=a.boxes, iters=a.iters, augment=not a.no_augment,
-                             rounds=a.rounds, round_boxes=a.round_boxes, round_iters=a.round_iters,
+                             phases=a.phases, phase_boxes=a.phase_boxes, phase_iters=a.phase_iters,
                              calibrate=a.calibrate, train_rms=a.train_rms,
                              eval_seeds=[int(v) for v in a.eval_seeds.split(",")] if a.eval_seeds else None,
                              probe=[(int(c.split(":")[0]), float(c.split(":")[1])) for c in a.probe.split(",") if c],
