@@ -87,6 +87,28 @@ def test_closure_loss_against_oracle():
     assert torch.equal(d2, dpred)
 
 
+def test_loss_and_symmetry_argument_errors():
+    """pm_closure_loss before a forward pass is a call-order error; pm_cube_symmetry rejects a perm that is not a
+    permutation of 0, 1, 2 and a flip outside 0..7, before touching the device arrays."""
+    import ctypes as C
+
+    from paper_2607_17929_amd import PMContext
+    from paper_2607_17929_amd import _lib as L
+    ctx = PMContext(16, 64, 160.0, physics="scalar", precision="fp32", closure=True)
+    r = np.random.default_rng(2)
+    ctx.init_particles(r.random((64, 3)), np.zeros((64, 3), dtype=np.float32), opm.Background(160.0).tau(0.1))
+    ctx.closure_set_params(torch.tensor(_params(), dtype=torch.float32))
+    with pytest.raises(L.PMError):
+        ctx.closure_loss(torch.zeros((64, 3)))
+    lib = L.load()
+    p = torch.zeros((4, 3), dtype=torch.float64, device="cuda")
+    v = torch.zeros((4, 3), dtype=torch.float32, device="cuda")
+    ptrs = [C.c_void_p(t.data_ptr()) for t in (p, v, v, p, v, v)]
+    for perm, flip in [((0, 0, 1), 0), ((0, 1, 3), 0), ((2, 1, 0), 8), ((2, 1, 0), -1)]:
+        assert lib.pm_cube_symmetry(ctx.ctx, 4, (C.c_int * 3)(*perm), flip, *ptrs) == L.PM_EINVAL
+    assert lib.pm_cube_symmetry(ctx.ctx, 4, (C.c_int * 3)(2, 1, 0), 7, *ptrs) == L.PM_OK
+
+
 def test_cube_symmetry_against_oracle():
     """pm_cube_symmetry for all 48 maps against the oracle's, bit for bit (including x = 0 and outputs that
     alias the inputs)."""
