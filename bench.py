@@ -212,6 +212,26 @@ def run_gpu(args):
     if not args.no_fp64:
         ms64, st64 = timed(ctx64, "fp64")
         res.update(ms64=ms64, st64=st64)
+    if not args.no_closure_cost:
+        # the closure's cost against the 2x mesh, measured here on the same particles (scalar physics, FP32,
+        # as in the closure experiment): a step on the n^3 mesh with the closure on (its cost does not depend
+        # on the trained values, so the initial parameters serve) and a plain step on the (2n)^3 mesh
+        from paper_2607_17929_amd import closure as cl
+        pos_d, u_d = ctx64.get_particles(device=True)
+        u_d = u_d.to(torch.float32)
+        ctxc = PMContext(n, n_p, box, physics="scalar", precision="fp32", closure=True, timings=True)
+        ctxc.init_particles(pos_d, u_d, tau_s)
+        ctxc.closure_set_params(cl.init_params(0))
+        ctxc.closure_enable(True)
+        res["ms_closure"], _ = timed(ctxc, "fp32 scalar + closure")
+        del ctxc
+        torch.cuda.empty_cache()
+        ctx2 = PMContext(2 * n, n_p, box, physics="scalar", precision="fp32", timings=True)
+        ctx2.init_particles(pos_d, u_d, tau_s)
+        del pos_d, u_d
+        res["ms_2x"], _ = timed(ctx2, f"fp32 scalar, {2 * n}^3 mesh")
+        del ctx2
+        torch.cuda.empty_cache()
     return res
 
 
@@ -252,6 +272,7 @@ def main():
     ap.add_argument("--no-parabolic", action="store_true", help="skip the parabolic-B FP32 leg")
     ap.add_argument("--no-deterministic", action="store_true", help="skip the deterministic FP32 leg")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-closure-cost", action="store_true", help="skip timing the closure against the 2x mesh")
     ap.add_argument("--cpu-n", type=int, default=256)
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="run one plain device copy of this many MiB before timing (a known-size dispatch that "
@@ -320,7 +341,12 @@ def main():
         out["fp64"] = {"value": n_p / r["ms64"] * 1e3, "ms_per_step": round(r["ms64"], 4),
                        "stages": {k: round(ms / calls / LAUNCHES.get(k, 1), 4) for k, (ms, calls) in r["st64"].items()
                                   if calls}}
-    cl = closure_result()
+    cl = closure_result() or {}
+    if "ms_closure" in r:
+        cl.update({"cost_vs_2x_measured": round(r["ms_closure"] / r["ms_2x"], 4),
+                   "closure_ms_per_step": round(r["ms_closure"], 4), "plain_2x_ms_per_step": round(r["ms_2x"], 4),
+                   "cost_measured": f"this run: FP32 scalar-physics steps on the {n}^3 mesh with the closure and on "
+                                    f"the {2 * n}^3 mesh, same particles"})
     if cl:
         out["closure_vs_2x_mesh"] = cl
     if not args.no_cpu_baseline:
