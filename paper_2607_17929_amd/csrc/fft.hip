@@ -158,12 +158,12 @@ __global__ __launch_bounds__(NT) void fft_x_r2c_kernel(SrcArgs<T> a, cplx<T>* sp
   constexpr int NSRC = mode_nsrc(MODE);
   constexpr int L = NSRC * RY;
   __shared__ cplx<T> cs[M * L];
-  __shared__ cplx<T> stw[N];   // W_N^j for the post-processing
+  __shared__ cplx<T> stw[M];   // W_N^j (j < M) for the post-processing
   __shared__ cplx<T> stwm[M];  // W_M^j = W_N^(2j) for the half-length transforms
   __shared__ double red[RY][NT / 64];
   const int y0 = blockIdx.x * RY, z = blockIdx.y;
   const int tid = threadIdx.x;
-  for (int j = tid; j < N; j += NT) stw[j] = tw[j];
+  for (int j = tid; j < M; j += NT) stw[j] = tw[j];
   for (int j = tid; j < M; j += NT) stwm[j] = tw[2 * j];
   // 1. assemble the sources of RY rows: real x of line (c, r) is element x / 2, real (x even) or
   //    imaginary (x odd) part
@@ -234,13 +234,14 @@ __global__ __launch_bounds__(NT) void fft_x_c2r_kernel(const cplx<T>* spec, int 
   constexpr int M = N / 2;
   constexpr int L = NOUT * RY;
   __shared__ cplx<T> cs[M * L];
-  __shared__ cplx<T> stw[N];
-  __shared__ cplx<T> stwm[M];
+  __shared__ cplx<T> stw[M];   // W_N^j (j < M) for the pre-processing
+  __shared__ cplx<T> stwm[M];  // W_M^j = W_N^(2j), formed from stw (W_N^M = -1)
   const int y0 = blockIdx.x * RY, z = blockIdx.y;
   const int tid = threadIdx.x;
   // 1. pre-process X_k -> Z_k = E_k + i O_k, E_k = X_k + conj X_{M-k}, O_k = (X_k - conj X_{M-k}) W^-k;
   //    the spectrum (component-interleaved) is read component fastest, so that the loads of a row
-  //    are contiguous; the reads are issued first, the twiddle tables are staged while they are in flight
+  //    are contiguous; the reads are issued first, the twiddle table is staged while they are in flight
+  //    and the half-length table is formed from it in LDS
   constexpr int PJ = (L * M + NT - 1) / NT;
   cplx<T> xk[PJ], xm[PJ];
 #pragma unroll
@@ -254,9 +255,9 @@ __global__ __launch_bounds__(NT) void fft_x_c2r_kernel(const cplx<T>* spec, int 
       xm[q] = row[(M - k) * NOUT + c];
     }
   }
-  for (int j = tid; j < N; j += NT) stw[j] = tw[j];
-  for (int j = tid; j < M; j += NT) stwm[j] = tw[2 * j];
+  for (int j = tid; j < M; j += NT) stw[j] = tw[j];
   __syncthreads();
+  for (int j = tid; j < M; j += NT) stwm[j] = 2 * j < M ? stw[2 * j] : mk(-stw[2 * j - M].x, -stw[2 * j - M].y);
 #pragma unroll
   for (int q = 0; q < PJ; ++q) {
     const int job = tid + q * NT;
