@@ -49,7 +49,7 @@ def stage_bytes(n: int, n_p: int, rs: int) -> dict:
         "fft_y_fwd": 2 * 10 * S,
         "kspace": 10 * S + 5 * S + 8 * S,  # sources in, solutions out, tensor state in and out
         "fft_y_inv": 2 * 5 * S,
-        "fft_x_inv": 5 * S + 5 * F,
+        "fft_x_inv": 5 * S + 7 * F,  # 5 spectra in, 5 fields out; phi_{n-1} in and the increment out
         "kick_drift": n_p * (2 * P + 4) + 5 * F,                  # state in and out, rank out, 5 fields in
         "sort": 16 * n ** 3 + n_p * (4 + 2 * (P + 4)),           # counts/offsets; rank, state and id in and out
     }
