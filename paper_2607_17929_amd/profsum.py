@@ -12,7 +12,10 @@ dispatch; each is scaled by what the same counter reads for the runtime's
 plain device-to-device copy of a known size (the bench's copy probe), which
 absorbs the counters' request-size accounting on this GPU.  The table carries
 the SHA-256 of the kernel sources it was measured with, so that a reader (the
-bench) can tell when a kernel has changed since.
+bench) can tell when a kernel has changed since.  `traffic` and `counters` take
+the last launches of each stage's kernels, so the profiled run must end with the
+legs they describe: the bench is profiled without its closure-cost legs
+(`--no-closure-cost`), which run some of the same kernels on other meshes.
 """
 from __future__ import annotations
 

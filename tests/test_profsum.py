@@ -28,3 +28,15 @@ def test_bench_drops_traffic_when_sources_change(monkeypatch):
     monkeypatch.setattr(profsum, "source_hash", lambda stage, csrc=profsum.CSRC: "0" * 64)
     assert bench.measured_traffic(512, "kick_drift") is None
     assert bench.measured_traffic(256, "kick_drift") is None
+
+
+def test_committed_512_summaries_leave_out_the_closure_legs():
+    """The summaries average the last launches of each stage's kernels, which belong to the step legs only
+    when no later leg of the profiled bench runs the same kernels: every 512^3 summary's bench command
+    leaves out the closure's cost legs (a 1024^3 mesh and the closure step reuse the scan and scatter)."""
+    for name in ("pm_step_512_clustered_kernel_trace.md", "pm_step_512_clustered_traffic.md",
+                 "pm_step_512_clustered_counters.md"):
+        with open(os.path.join(ROOT, "profiles", name)) as fh:
+            cmds = [ln for ln in fh.read().splitlines() if "rocprofv3" in ln and "bench.py" in ln]
+        assert cmds, name
+        assert all("--no-closure-cost" in c for c in cmds), name
